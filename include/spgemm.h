@@ -1,0 +1,265 @@
+/*
+ * spgemm.h - C ABI of the MI355X (gfx950) local SpGEMM of the sparsity-aware
+ * 1D algorithm (Hong & Buluc, "A sparsity-aware distributed-memory algorithm
+ * for sparse-sparse matrix multiplication").
+ *
+ * One call sequence computes one 1D partition's local product
+ *     C_i = A * B_i          (Sec. II: C = AB; Alg. 1, the local step)
+ * with A (m x k), B_i (k x n_i) and C_i (m x n_i) in CSC:
+ *
+ *   spgemm_plan      H_i, Alg. 2 block selection, column map, gather of A~
+ *   spgemm_symbolic  sparse flops per column, binning, nnz per column, scan
+ *   spgemm_numeric   values of C_i (rows ascending inside every column)
+ *   spgemm_backward  (dC*B_i^T) o pattern(A) and (A^T*dC) o pattern(B_i)
+ *   spgemm_batched   numeric of many planned products in one persistent launch
+ *
+ * Conventions for every entry point:
+ *   - Matrices are CSC: colptr int64[ncols+1], rowidx int32[nnz] with row ids
+ *     ascending and unique inside each column, vals float or double (the
+ *     plan's dtype).  Unless a comment says "host", pointers are DEVICE
+ *     pointers on the current HIP device.
+ *   - The caller owns every buffer it passes in and keeps A, B_i and the
+ *     given value arrays alive and unchanged until the plan is destroyed (or,
+ *     for value arrays passed to spgemm_numeric, until the stream reaches the
+ *     end of that call).  A plan owns its workspace and the gathered A~.
+ *   - Work is enqueued on the plan's stream (a hipStream_t passed as void*,
+ *     NULL = the null stream) and is asynchronous unless stated otherwise.
+ *   - Every call returns SPGEMM_OK (0) or a negative status; nothing aborts
+ *     or throws across the ABI.  spgemm_last_error() returns a message for
+ *     the last failing call on the calling thread.
+ *   - Sizes are int64; row and column ids are int32, so m, k and n_i must be
+ *     below 2^31.
+ */
+#ifndef SPGEMM_MI355X_H
+#define SPGEMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SPGEMM_OK 0
+#define SPGEMM_EINVAL (-1)       /* bad argument or malformed matrix */
+#define SPGEMM_ENOMEM (-2)       /* device or host allocation failed / over limit */
+#define SPGEMM_EHIP (-3)         /* a HIP runtime call failed (message has text) */
+#define SPGEMM_EUNSUPPORTED (-4) /* valid request this build cannot serve */
+#define SPGEMM_ESTATE (-5)       /* call out of order (e.g. numeric before symbolic) */
+
+typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
+
+typedef struct {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nnz;
+    const int64_t *colptr; /* device, ncols+1, colptr[0] == 0, colptr[ncols] == nnz */
+    const int32_t *rowidx; /* device, nnz */
+    const void *vals;      /* device, nnz values of the plan's dtype (may be NULL
+                              for a pattern-only plan; numeric then needs values) */
+} spgemm_csc;
+
+/*
+ * Tuning knobs.  spgemm_default_tuning() fills the defaults; a NULL tuning
+ * pointer means the defaults.  Thresholds only change which kernel computes
+ * a column, never the result.
+ */
+typedef struct {
+    int32_t tiny_max_flop;      /* columns with flop <= this (1..64) use one wave each */
+    int32_t hash_max_flop;      /* symbolic LDS hash up to this flop (<= 4096), else bitmap */
+    int32_t hash_max_nnz;       /* numeric LDS hash up to this nnz (<= 2048), else dense windows */
+    int32_t dense_window_rows;  /* rows per dense numeric window (power of 2, 1024..8192) */
+    int32_t validate;           /* 1: check the CSC invariants of A and B_i on the device */
+    int32_t own_partition;      /* >= 0: B_i belongs to this partition of A ... */
+    int32_t own_partition_whole;/* ... and 1 selects that partition's nonzero columns whole */
+    int32_t reserved;
+    int64_t workspace_limit;    /* bytes of device workspace a plan may take; 0 = no limit */
+} spgemm_tuning;
+
+/* Plan statistics (host struct), filled by spgemm_plan_stats. */
+typedef struct {
+    int64_t m, k, n;        /* A is m x k, B_i is k x n */
+    int64_t nnz_A, nnz_B;
+    int64_t h_count;        /* |H_i|: rows of B_i holding an entry */
+    int64_t nzc_A;          /* nonzero columns of A over all partitions */
+    int64_t K;              /* groups formed by Alg. 2 over all partitions */
+    int64_t M;              /* groups chosen (hit blocks, i.e. fetch messages) */
+    int64_t kt;             /* columns of A~ */
+    int64_t nnz_At;         /* stored entries of A~ */
+    double cv_memA;         /* nnz_At / nnz_A: fetched share of A (Discussion) */
+    int64_t flops;          /* sparse flops of A*B_i (-1 before symbolic) */
+    int64_t nnz_C;          /* stored entries of C_i (-1 before symbolic) */
+    int64_t sym_bins[8];    /* columns per symbolic bin: 0 empty, 1 tiny, 2..5 hash, 6 bitmap, 7 unused */
+    int64_t num_bins[8];    /* columns per numeric bin: 0 empty, 1 tiny, 2..5 hash, 6 dense, 7 unused */
+} spgemm_stats;
+
+typedef struct spgemm_plan_s *spgemm_plan_t;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *spgemm_last_error(void);
+
+/* Library version string. */
+const char *spgemm_version(void);
+
+/* Fills *t with the default tuning.  Returns SPGEMM_EINVAL for NULL. */
+int spgemm_default_tuning(spgemm_tuning *t);
+
+/*
+ * spgemm_plan - the gather half of Alg. 1 for partition i.
+ *
+ *   A            m x k, all P column partitions of A (Alg. 1 Data: A_r is a
+ *                column slice of A).  A->vals may be NULL for a pattern-only
+ *                plan.
+ *   Bi           k x n_i, the caller's column slice of B.
+ *   dtype        value type of A, B_i and C_i.
+ *   a_part_offsets  HOST int64[P+1]: partition r owns columns
+ *                [offs[r], offs[r+1]) of A; offs[0] = 0, offs[P] = k,
+ *                non-decreasing.
+ *   P            number of partitions (>= 1).
+ *   block_size   b >= 1: Alg. 2 cuts each partition's ordered nonzero
+ *                column ids into consecutive groups of b (the last group may
+ *                be shorter); a group holding any column named by H_i is
+ *                fetched whole.
+ *   tuning       NULL = defaults.
+ *   stream       hipStream_t used by this and every later call on the plan.
+ *   out          receives the plan handle (NULL on failure).
+ *
+ * Computes, on the device and asynchronously: H_i (rows of B_i that hold an
+ * entry; notation table, Alg. 1), the group id of every nonzero column of A,
+ * the chosen groups (Alg. 2), the selection and map of A's columns into A~
+ * (an exclusive prefix over the selected columns, -1 for others) and copies
+ * the selected columns' row ids and values into A~ (Alg. 1, fetch and build
+ * A~).  Host-side checks cover dimensions, pointers and offsets; with
+ * tuning->validate the CSC invariants of A and B_i are checked on the device
+ * and the call synchronises the stream to report them (SPGEMM_EINVAL).
+ */
+int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
+                const int64_t *a_part_offsets, int32_t P, int64_t block_size,
+                const spgemm_tuning *tuning, void *stream, spgemm_plan_t *out);
+
+/* Re-targets later calls on the plan to another stream (NULL = null stream). */
+int spgemm_plan_set_stream(spgemm_plan_t plan, void *stream);
+
+/* Synchronises the plan's stream and fills *stats (host struct). */
+int spgemm_plan_stats(spgemm_plan_t plan, spgemm_stats *stats);
+
+/*
+ * Copies plan internals to caller buffers (DEVICE pointers; any may be NULL):
+ *   H         uint8[k]        H_i
+ *   map       int32[k]        column of A -> column of A~, or -1
+ *   At_colptr int64[kt+1]     A~ column pointers
+ *   At_rowidx int32[nnz_At]   A~ row ids
+ *   At_vals   dtype[nnz_At]   A~ values
+ *   blocks    int64[2*M]      (first, last) column of each chosen group, in
+ *                             partition then group order (Alg. 2's R)
+ * Sizes come from spgemm_plan_stats.  Enqueued on the plan's stream.
+ */
+int spgemm_plan_export(spgemm_plan_t plan, uint8_t *H, int32_t *map, int64_t *At_colptr,
+                       int32_t *At_rowidx, void *At_vals, int64_t *blocks);
+
+/*
+ * Copies the symbolic phase's per-column data (DEVICE pointers, may be NULL):
+ *   flop     int64[n_i]  sparse flops of each column of C_i (Sec. III-B)
+ *   sym_bin  int32[n_i]  symbolic bin of each column (see spgemm_stats)
+ *   num_bin  int32[n_i]  numeric bin of each column
+ * Valid after spgemm_symbolic; SPGEMM_ESTATE before.
+ */
+int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
+                            int32_t *num_bin);
+
+/*
+ * spgemm_symbolic - pattern size of C_i (Sec. III-A column-by-column formula).
+ *
+ *   C_colptr  int64[n_i+1], caller-allocated; receives C_i's column pointers.
+ *   nnzC      HOST int64*; receives nnz(C_i).
+ *
+ * Computes the sparse flops of every column (Sec. III-B), bins columns by
+ * them, counts the distinct rows of every output column (a row is stored
+ * whenever a product reaches it, even if values later cancel) and scans the
+ * counts.  Synchronises the plan's stream twice (bin sizes, then nnzC).
+ */
+int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
+
+/*
+ * spgemm_numeric - values of C_i = A * B_i.
+ *
+ *   A_vals    dtype[nnz(A)] new values of A on the planned pattern, or NULL
+ *             to use the values gathered by spgemm_plan.  Non-NULL values are
+ *             gathered into A~ first (values half of Alg. 1's fetch).
+ *   Bi_vals   dtype[nnz(B_i)] or NULL for the values given to spgemm_plan.
+ *   C_rowidx  int32[nnzC], caller-allocated; receives ascending row ids.
+ *   C_vals    dtype[nnzC], caller-allocated.
+ *
+ * Requires spgemm_symbolic (SPGEMM_ESTATE otherwise) with the C_colptr it
+ * filled still alive.  Can be re-run with new values on the same patterns.
+ * Products are summed in an unspecified order (FP32 in FP32, FP64 in FP64).
+ */
+int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
+                   int32_t *C_rowidx, void *C_vals);
+
+/*
+ * spgemm_backward - gradients of L = <dC, A * B_i> on the stored entries:
+ *   dA = (dC * B_i^T) o pattern(A)      dtype[nnz(A)] (zero where B_i's row is empty)
+ *   dB = (A^T * dC) o pattern(B_i)      dtype[nnz(B_i)]
+ *
+ *   C_colptr/C_rowidx  C_i's pattern as produced by symbolic/numeric.
+ *   A_vals/Bi_vals     values (NULL = the plan's).
+ *   dC_vals            dtype[nnzC] upstream gradient on pattern(C_i).
+ *   dA_vals/dB_vals    outputs; either may be NULL to skip it.
+ * Every output entry is written by one thread in a fixed order, so results
+ * are bitwise reproducible.  Requires spgemm_symbolic.
+ */
+int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *C_rowidx,
+                    const void *A_vals, const void *Bi_vals, const void *dC_vals,
+                    void *dA_vals, void *dB_vals);
+
+/* Frees the plan and returns its workspace to the library's pool.  NULL is OK. */
+int spgemm_plan_destroy(spgemm_plan_t plan);
+
+/* ---------------------------------------------------------------------------
+ * Batched numeric: many planned products (uneven sizes, optionally chained
+ * like the two products of each AMG Galerkin level) in ONE persistent kernel
+ * launch, optionally captured once into a hipGraph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const void *A_vals;   /* dtype[nnz(A)] or NULL = plan's values */
+    const void *B_vals;   /* dtype[nnz(B)] or NULL = plan's values */
+    int32_t *C_rowidx;    /* int32[nnzC] of this product */
+    void *C_vals;         /* dtype[nnzC] */
+    int32_t dep_A;        /* index of an earlier product whose C is this A, or -1 */
+    int32_t dep_B;        /* index of an earlier product whose C is this B, or -1 */
+} spgemm_batch_io;
+
+typedef struct spgemm_batch_s *spgemm_batch_t;
+
+/*
+ * Builds a batch over `count` plans that have all finished spgemm_symbolic
+ * and share one dtype.  Dependencies must point to lower indices.  The work
+ * list (value gathers and per-bin column tiles of every product) is built on
+ * the host once; plans must outlive the batch.  Synchronises plans' streams.
+ */
+int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
+                        const spgemm_tuning *tuning, spgemm_batch_t *out);
+
+/*
+ * Runs the batch on `stream`:
+ *   mode 0  launch the persistent kernel directly;
+ *   mode 1  capture that launch into a hipGraph, instantiate it and launch it;
+ *   mode 2  relaunch the instantiated graph (SPGEMM_ESTATE without mode 1).
+ * Launches of one batch must not overlap (they share queue counters).
+ */
+int spgemm_batched(spgemm_batch_t batch, int32_t mode, void *stream);
+
+/* Workgroups the persistent kernel uses, and the number of work items. */
+int spgemm_batch_info(spgemm_batch_t batch, int64_t *workgroups, int64_t *items);
+
+int spgemm_batch_destroy(spgemm_batch_t batch);
+
+/* Releases every pooled device/host buffer not held by a live plan. */
+int spgemm_pool_trim(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_MI355X_H */
