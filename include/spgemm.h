@@ -206,8 +206,10 @@ int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
  *   A_vals/Bi_vals     values (NULL = the plan's).
  *   dC_vals            dtype[nnzC] upstream gradient on pattern(C_i).
  *   dA_vals/dB_vals    outputs; either may be NULL to skip it.
- * Every output entry is written by one thread in a fixed order, so results
- * are bitwise reproducible.  Requires spgemm_symbolic.
+ * dB entries are each summed by one thread in a fixed order (bitwise
+ * reproducible); dA entries receive their products through atomic adds, so
+ * their summation order, and the last bits, may vary between calls.
+ * Requires spgemm_symbolic.
  */
 int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *C_rowidx,
                     const void *A_vals, const void *Bi_vals, const void *dC_vals,

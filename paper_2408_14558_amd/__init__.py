@@ -1,0 +1,14 @@
+"""MI355X (gfx950) local SpGEMM of the sparsity-aware 1D algorithm.
+
+C_i = A * B_i for one column partition: H_i, Alg. 2 block selection, the
+gather of A~, and a column-wise Gustavson product (flop binning, symbolic
+count, scan, numeric) in hand-written HIP kernels behind the C ABI of
+include/spgemm.h.  This package is the thin Python binding.
+"""
+
+from ._lib import SpgemmError, load  # noqa: F401
+from .api import (DeviceCsc, HostCsc, Plan, SpGEMM, default_tuning, spgemm,  # noqa: F401
+                  tuning, BIN_NAMES)
+
+__all__ = ["DeviceCsc", "HostCsc", "Plan", "SpGEMM", "SpgemmError", "default_tuning", "spgemm",
+           "tuning", "load", "BIN_NAMES"]

@@ -1,0 +1,251 @@
+"""Python binding of the local SpGEMM: argument marshalling over the C ABI.
+
+Every step runs inside libspgemm.so; this module only allocates the
+caller-owned buffers with torch (device memory) and passes raw pointers and
+the current HIP stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class DeviceCsc:
+    """A CSC matrix whose arrays live on the GPU."""
+    nrows: int
+    ncols: int
+    colptr: torch.Tensor  # int64[ncols+1]
+    rowidx: torch.Tensor  # int32[nnz]
+    vals: Optional[torch.Tensor]  # float32/float64[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowidx.numel())
+
+    @classmethod
+    def from_host(cls, M, dtype=torch.float64, device="cuda") -> "DeviceCsc":
+        """From any object with nrows, ncols, colptr, rowidx, vals (numpy)."""
+        colptr = torch.as_tensor(np.ascontiguousarray(M.colptr, dtype=np.int64)).to(device)
+        rowidx = torch.as_tensor(np.ascontiguousarray(M.rowidx, dtype=np.int32)).to(device)
+        vals = None
+        if M.vals is not None:
+            vals = torch.as_tensor(np.ascontiguousarray(M.vals)).to(device=device, dtype=dtype)
+        return cls(int(M.nrows), int(M.ncols), colptr, rowidx, vals)
+
+    def c_struct(self) -> _lib.Csc:
+        return _lib.Csc(self.nrows, self.ncols, self.nnz, self.colptr.data_ptr(),
+                        self.rowidx.data_ptr() if self.nnz else None,
+                        self.vals.data_ptr() if (self.vals is not None and self.nnz) else None)
+
+    def to_host(self):
+        v = None if self.vals is None else self.vals.cpu().numpy()
+        return HostCsc(self.nrows, self.ncols, self.colptr.cpu().numpy(),
+                       self.rowidx.cpu().numpy(), v)
+
+
+@dataclass
+class HostCsc:
+    nrows: int
+    ncols: int
+    colptr: np.ndarray
+    rowidx: np.ndarray
+    vals: Optional[np.ndarray]
+
+
+def default_tuning() -> _lib.Tuning:
+    t = _lib.Tuning()
+    check(_lib.load().spgemm_default_tuning(ctypes.byref(t)), "spgemm_default_tuning")
+    return t
+
+
+def tuning(**kw) -> _lib.Tuning:
+    t = default_tuning()
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+BIN_NAMES = ["empty", "tiny", "hash0", "hash1", "hash2", "hash3", "dense", "unused"]
+
+
+class Plan:
+    """One partition's local product C_i = A * B_i (plan, symbolic, numeric,
+    backward).  Keeps A and B_i alive while it exists."""
+
+    def __init__(self, A: DeviceCsc, Bi: DeviceCsc, offsets=None, block_size: int = 256,
+                 tuning: Optional[_lib.Tuning] = None, stream=None):
+        self.lib = _lib.load()
+        if A.vals is not None and Bi.vals is not None and A.vals.dtype != Bi.vals.dtype:
+            raise ValueError("A and B_i must share one value dtype")
+        dt = (A.vals if A.vals is not None else Bi.vals)
+        self.torch_dtype = torch.float64 if dt is None else dt.dtype
+        if self.torch_dtype not in (torch.float32, torch.float64):
+            raise ValueError("values must be float32 or float64")
+        self.dtype = _lib.F64 if self.torch_dtype == torch.float64 else _lib.F32
+        self.A, self.Bi = A, Bi
+        self.device = A.colptr.device
+        if offsets is None:
+            offsets = [0, A.ncols]
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.offsets = offs
+        self.P = offs.size - 1
+        self.block_size = int(block_size)
+        self._stream = stream
+        handle = ctypes.c_void_p()
+        a, b = A.c_struct(), Bi.c_struct()
+        tun = ctypes.byref(tuning) if tuning is not None else None
+        check(self.lib.spgemm_plan(ctypes.byref(a), ctypes.byref(b), self.dtype,
+                                   offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.P,
+                                   self.block_size, tun, _stream(stream), ctypes.byref(handle)),
+              "spgemm_plan")
+        self.handle = handle
+        self.C_colptr: Optional[torch.Tensor] = None
+        self.nnzC: Optional[int] = None
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.spgemm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream):
+        self._stream = stream
+        check(self.lib.spgemm_plan_set_stream(self.handle, _stream(stream)), "set_stream")
+
+    # -- queries ------------------------------------------------------------
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        check(self.lib.spgemm_plan_stats(self.handle, ctypes.byref(s)), "spgemm_plan_stats")
+        out = {f: getattr(s, f) for f, _ in _lib.Stats._fields_ if f not in ("sym_bins", "num_bins")}
+        out["sym_bins"] = list(s.sym_bins)
+        out["num_bins"] = list(s.num_bins)
+        return out
+
+    def export(self) -> dict:
+        st = self.stats()
+        dev = self.device
+        k, kt, nt, M = st["k"], st["kt"], st["nnz_At"], st["M"]
+        H = torch.empty(k, dtype=torch.uint8, device=dev)
+        mp = torch.empty(k, dtype=torch.int32, device=dev)
+        atc = torch.empty(kt + 1, dtype=torch.int64, device=dev)
+        atr = torch.empty(nt, dtype=torch.int32, device=dev)
+        atv = torch.empty(nt, dtype=self.torch_dtype, device=dev)
+        blocks = torch.empty((M, 2), dtype=torch.int64, device=dev)
+        check(self.lib.spgemm_plan_export(self.handle, _ptr(H), _ptr(mp), _ptr(atc), _ptr(atr),
+                                          _ptr(atv), _ptr(blocks)), "spgemm_plan_export")
+        return {"H": H, "map": mp, "At_colptr": atc, "At_rowidx": atr, "At_vals": atv,
+                "blocks": blocks, "stats": st}
+
+    def export_bins(self):
+        n = self.Bi.ncols
+        flop = torch.empty(n, dtype=torch.int64, device=self.device)
+        sb = torch.empty(n, dtype=torch.int32, device=self.device)
+        nb = torch.empty(n, dtype=torch.int32, device=self.device)
+        check(self.lib.spgemm_plan_export_bins(self.handle, _ptr(flop), _ptr(sb), _ptr(nb)),
+              "spgemm_plan_export_bins")
+        return flop, sb, nb
+
+    # -- the phases -----------------------------------------------------------
+    def symbolic(self) -> torch.Tensor:
+        colptr = torch.empty(self.Bi.ncols + 1, dtype=torch.int64, device=self.device)
+        nnz = ctypes.c_int64(0)
+        check(self.lib.spgemm_symbolic(self.handle, _ptr(colptr), ctypes.byref(nnz)),
+              "spgemm_symbolic")
+        self.C_colptr = colptr
+        self.nnzC = int(nnz.value)
+        return colptr
+
+    def numeric(self, A_vals: Optional[torch.Tensor] = None, B_vals: Optional[torch.Tensor] = None,
+                out: Optional[tuple] = None):
+        if self.nnzC is None:
+            raise RuntimeError("numeric() needs symbolic() first")
+        if out is None:
+            rows = torch.empty(self.nnzC, dtype=torch.int32, device=self.device)
+            vals = torch.empty(self.nnzC, dtype=self.torch_dtype, device=self.device)
+        else:
+            rows, vals = out
+        for t, what in ((A_vals, "A_vals"), (B_vals, "B_vals")):
+            if t is not None and (t.dtype != self.torch_dtype or not t.is_contiguous()):
+                raise ValueError(f"{what} must be contiguous {self.torch_dtype}")
+        check(self.lib.spgemm_numeric(self.handle, _ptr(A_vals), _ptr(B_vals), _ptr(rows),
+                                      _ptr(vals)), "spgemm_numeric")
+        return rows, vals
+
+    def backward(self, C_rowidx: torch.Tensor, dC: torch.Tensor,
+                 A_vals: Optional[torch.Tensor] = None, B_vals: Optional[torch.Tensor] = None,
+                 need_dA: bool = True, need_dB: bool = True):
+        dA = torch.empty(self.A.nnz, dtype=self.torch_dtype, device=self.device) if need_dA else None
+        dB = torch.empty(self.Bi.nnz, dtype=self.torch_dtype, device=self.device) if need_dB else None
+        dC = dC.contiguous()
+        check(self.lib.spgemm_backward(self.handle, _ptr(self.C_colptr), _ptr(C_rowidx),
+                                       _ptr(A_vals), _ptr(B_vals), _ptr(dC), _ptr(dA), _ptr(dB)),
+              "spgemm_backward")
+        return dA, dB
+
+    def run(self):
+        """symbolic + numeric with the plan's values; returns C_i on the device."""
+        colptr = self.symbolic()
+        rows, vals = self.numeric()
+        return DeviceCsc(self.A.nrows, self.Bi.ncols, colptr, rows, vals)
+
+
+def spgemm(A: DeviceCsc, Bi: DeviceCsc, offsets=None, block_size: int = 256,
+           tuning: Optional[_lib.Tuning] = None) -> DeviceCsc:
+    """C_i = A * B_i in one call (plan, symbolic, numeric)."""
+    with Plan(A, Bi, offsets, block_size, tuning) as p:
+        return p.run()
+
+
+class SpGEMM(torch.autograd.Function):
+    """C_vals = values of A * B_i on the plan's fixed patterns, differentiable
+    in A's and B_i's values.  Usage: ``SpGEMM.apply(A_vals, B_vals, plan)``
+    after ``plan.symbolic()``; returns C's values (rows in plan.C_rowidx)."""
+
+    @staticmethod
+    def forward(ctx, A_vals, B_vals, plan: Plan):
+        rows, vals = plan.numeric(A_vals.detach().contiguous(), B_vals.detach().contiguous())
+        plan.C_rowidx = rows
+        ctx.plan = plan
+        ctx.save_for_backward(A_vals, B_vals)
+        ctx.mark_non_differentiable(rows)
+        return vals
+
+    @staticmethod
+    def backward(ctx, dC):
+        A_vals, B_vals = ctx.saved_tensors
+        plan: Plan = ctx.plan
+        need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dA, dB = plan.backward(plan.C_rowidx, dC.contiguous(), A_vals.detach().contiguous(),
+                               B_vals.detach().contiguous(), need_a, need_b)
+        return dA, dB, None

@@ -1,0 +1,548 @@
+// C ABI of the local SpGEMM (include/spgemm.h): argument checks, the plan
+// object and its workspace, the pooled allocator, and the order of launches.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace spg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_last_error;
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    t_last_error = msg;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// pooled allocator: device workspaces and pinned host blocks are kept after a
+// plan is destroyed and handed to the next plan that fits, so repeated
+// plan/destroy cycles do not call hipMalloc.  A block freed on one stream
+// and reused on another makes the new stream wait on an event recorded at
+// the free (device), or waits on the host (pinned).
+// ---------------------------------------------------------------------------
+struct PoolBlock {
+    void *ptr;
+    size_t bytes;
+    int device;
+    bool pinned;
+    hipEvent_t ev;
+    hipStream_t stream;
+};
+
+static std::mutex g_pool_mtx;
+static std::vector<PoolBlock> g_pool;
+
+static size_t round_block(size_t bytes, bool pinned) {
+    const size_t g = pinned ? 4096 : (1 << 20);
+    return (bytes + g - 1) / g * g;
+}
+
+static int pool_get(size_t bytes, bool pinned, int device, hipStream_t stream, void **out,
+                    size_t *got) {
+    bytes = round_block(std::max<size_t>(bytes, 1), pinned);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mtx);
+        int best = -1;
+        for (size_t i = 0; i < g_pool.size(); ++i) {
+            const PoolBlock &b = g_pool[i];
+            if (b.pinned != pinned || b.device != device || b.bytes < bytes ||
+                b.bytes > 2 * bytes + (1 << 20))
+                continue;
+            if (best < 0 || b.bytes < g_pool[best].bytes) best = (int)i;
+        }
+        if (best >= 0) {
+            PoolBlock b = g_pool[best];
+            g_pool.erase(g_pool.begin() + best);
+            if (pinned) {
+                SPG_HIP(hipEventSynchronize(b.ev));
+            } else if (b.stream != stream) {
+                SPG_HIP(hipStreamWaitEvent(stream, b.ev, 0));
+            }
+            SPG_HIP(hipEventDestroy(b.ev));
+            *out = b.ptr;
+            *got = b.bytes;
+            return SPGEMM_OK;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = pinned ? hipHostMalloc(&p, bytes, hipHostMallocDefault) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPGEMM_ENOMEM, std::string(pinned ? "hipHostMalloc" : "hipMalloc") + " of " +
+                                       std::to_string(bytes) + " bytes failed: " +
+                                       hipGetErrorString(e));
+    }
+    *out = p;
+    *got = bytes;
+    return SPGEMM_OK;
+}
+
+static void pool_put(void *ptr, size_t bytes, bool pinned, int device, hipStream_t stream) {
+    if (!ptr) return;
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, stream) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        if (pinned) (void)hipHostFree(ptr); else (void)hipFree(ptr);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_pool_mtx);
+    g_pool.push_back(PoolBlock{ptr, bytes, device, pinned, ev, stream});
+}
+
+static int pool_trim() {
+    std::vector<PoolBlock> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mtx);
+        blocks.swap(g_pool);
+    }
+    for (auto &b : blocks) {
+        (void)hipEventSynchronize(b.ev);
+        (void)hipEventDestroy(b.ev);
+        if (b.pinned) (void)hipHostFree(b.ptr); else (void)hipFree(b.ptr);
+    }
+    return SPGEMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+struct Carver {
+    size_t off = 0;
+    template <typename T>
+    size_t take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t at = off;
+        off += (size_t)std::max<int64_t>(count, 0) * sizeof(T);
+        return at;
+    }
+};
+
+static int check_csc(const spgemm_csc *M, const char *name) {
+    if (!M) return fail(SPGEMM_EINVAL, std::string(name) + " is NULL");
+    if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0)
+        return fail(SPGEMM_EINVAL, std::string(name) + " has a negative size");
+    if (M->nrows >= (1ll << 31) || M->ncols >= (1ll << 31))
+        return fail(SPGEMM_EINVAL, std::string(name) + " dimensions must be below 2^31");
+    if (!M->colptr) return fail(SPGEMM_EINVAL, std::string(name) + "->colptr is NULL");
+    if (M->nnz > 0 && !M->rowidx) return fail(SPGEMM_EINVAL, std::string(name) + "->rowidx is NULL");
+    if (M->nnz > 0 && M->nrows == 0)
+        return fail(SPGEMM_EINVAL, std::string(name) + " stores entries but has no rows");
+    return SPGEMM_OK;
+}
+
+static void thresholds_from(const spgemm_tuning &t, Thresholds &th) {
+    // hash bin h holds keys up to half its table; a bin is used only above
+    // the previous bin's limit and never above the tuned maximum
+    th.tiny_max_flop = t.tiny_max_flop;
+    int prev = t.tiny_max_flop;
+    for (int h = 0; h < 4; ++h) {
+        const int lim = kSymTable[h] / 2;
+        if (prev >= t.hash_max_flop) {
+            th.sym_hash_max[h] = 0;
+        } else {
+            th.sym_hash_max[h] = std::min(lim, t.hash_max_flop);
+            prev = th.sym_hash_max[h];
+        }
+    }
+    prev = 0;
+    for (int h = 0; h < 4; ++h) {
+        const int lim = kNumTable[h] / 2;
+        if (prev >= t.hash_max_nnz) {
+            th.num_hash_max[h] = 0;
+        } else {
+            th.num_hash_max[h] = std::min(lim, t.hash_max_nnz);
+            prev = th.num_hash_max[h];
+        }
+    }
+}
+
+static int check_tuning(const spgemm_tuning &t) {
+    if (t.tiny_max_flop < 0 || t.tiny_max_flop > 64)
+        return fail(SPGEMM_EINVAL, "tiny_max_flop must lie in [0, 64]");
+    if (t.hash_max_flop < 0 || t.hash_max_flop > kSymTable[3] / 2)
+        return fail(SPGEMM_EINVAL, "hash_max_flop must lie in [0, 4096]");
+    if (t.hash_max_nnz < 0 || t.hash_max_nnz > kNumTable[3] / 2)
+        return fail(SPGEMM_EINVAL, "hash_max_nnz must lie in [0, 2048]");
+    if (t.workspace_limit < 0) return fail(SPGEMM_EINVAL, "workspace_limit must be >= 0");
+    return SPGEMM_OK;
+}
+
+static int sync_counters(Plan &p) {
+    SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
+    SPG_HIP(hipStreamSynchronize(p.stream));
+    return SPGEMM_OK;
+}
+
+}  // namespace spg
+
+using namespace spg;
+
+struct spgemm_plan_s : public spg::Plan {};
+
+extern "C" {
+
+const char *spgemm_last_error(void) { return spg::t_last_error.c_str(); }
+
+const char *spgemm_version(void) { return "spgemm-mi355x 0.1 (gfx950)"; }
+
+int spgemm_default_tuning(spgemm_tuning *t) {
+    if (!t) return fail(SPGEMM_EINVAL, "tuning is NULL");
+    std::memset(t, 0, sizeof(*t));
+    t->tiny_max_flop = 64;
+    t->hash_max_flop = 4096;
+    t->hash_max_nnz = 2048;
+    t->dense_window_rows = 0;
+    t->validate = 0;
+    t->own_partition = -1;
+    t->own_partition_whole = 0;
+    t->workspace_limit = 0;
+    return SPGEMM_OK;
+}
+
+int spgemm_pool_trim(void) { return pool_trim(); }
+
+int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
+                const int64_t *offs, int32_t P, int64_t block_size, const spgemm_tuning *tuning,
+                void *stream, spgemm_plan_t *out) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!out) return fail(SPGEMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc;
+    if ((rc = check_csc(A, "A")) || (rc = check_csc(Bi, "Bi"))) return rc;
+    if (dtype != SPGEMM_F32 && dtype != SPGEMM_F64)
+        return fail(SPGEMM_EUNSUPPORTED, "dtype must be SPGEMM_F32 or SPGEMM_F64");
+    if (A->ncols != Bi->nrows)
+        return fail(SPGEMM_EINVAL, "A has " + std::to_string(A->ncols) + " columns but Bi has " +
+                                       std::to_string(Bi->nrows) + " rows");
+    if (P < 1) return fail(SPGEMM_EINVAL, "P must be >= 1");
+    if (block_size < 1) return fail(SPGEMM_EINVAL, "block_size must be >= 1");
+    if (!offs) return fail(SPGEMM_EINVAL, "a_part_offsets is NULL");
+    if (offs[0] != 0 || offs[P] != A->ncols)
+        return fail(SPGEMM_EINVAL, "a_part_offsets must start at 0 and end at A->ncols");
+    for (int r = 0; r < P; ++r)
+        if (offs[r + 1] < offs[r]) return fail(SPGEMM_EINVAL, "a_part_offsets must not decrease");
+    spgemm_tuning tun;
+    spgemm_default_tuning(&tun);
+    if (tuning) tun = *tuning;
+    if ((rc = check_tuning(tun))) return rc;
+    if (tun.own_partition_whole && (tun.own_partition < 0 || tun.own_partition >= P))
+        return fail(SPGEMM_EINVAL, "own_partition_whole needs own_partition in [0, P)");
+    if (tun.own_partition_whole)
+        return fail(SPGEMM_EUNSUPPORTED, "own_partition_whole is not available in this build");
+
+    auto *p = new (std::nothrow) spgemm_plan_s();
+    if (!p) return fail(SPGEMM_ENOMEM, "plan allocation failed");
+    Plan &pl = *p;
+    if (hipGetDevice(&pl.device) != hipSuccess) {
+        delete p;
+        return fail(SPGEMM_EHIP, "hipGetDevice failed");
+    }
+    pl.stream = (hipStream_t)stream;
+    pl.dtype = dtype;
+    pl.vsize = dtype == SPGEMM_F64 ? 8 : 4;
+    pl.tun = tun;
+    thresholds_from(tun, pl.th);
+    pl.m = A->nrows;
+    pl.k = A->ncols;
+    pl.n = Bi->ncols;
+    pl.nnzA = A->nnz;
+    pl.nnzB = Bi->nnz;
+    pl.Acolptr = A->colptr;
+    pl.Arowidx = A->rowidx;
+    pl.Avals = A->vals;
+    pl.Bcolptr = Bi->colptr;
+    pl.Browidx = Bi->rowidx;
+    pl.Bvals = Bi->vals;
+    pl.P = P;
+    pl.b = block_size;
+    pl.offs.assign(offs, offs + P + 1);
+
+    // group-id space and rank tiles
+    std::vector<int64_t> gbase(P + 1, 0);
+    std::vector<RankTile> tiles;
+    for (int r = 0; r < P; ++r) {
+        const int64_t kr = offs[r + 1] - offs[r];
+        gbase[r + 1] = gbase[r] + (kr + block_size - 1) / block_size;
+        const int64_t nt = (kr + kScanTile - 1) / kScanTile;
+        for (int64_t t = 0; t < nt; ++t) {
+            RankTile d;
+            d.col0 = offs[r] + t * kScanTile;
+            d.ncols = (int32_t)std::min<int64_t>(kScanTile, kr - t * kScanTile);
+            d.part = r;
+            d.head = t == 0;
+            d.last = t == nt - 1;
+            tiles.push_back(d);
+        }
+    }
+    pl.G = gbase[P];
+    if (pl.G >= (1ll << 31)) {
+        delete p;
+        return fail(SPGEMM_EINVAL, "too many groups for int32 group ids");
+    }
+    pl.n_rank_tiles = (int64_t)tiles.size();
+    pl.n_sel_tiles = (pl.k + kScanTile - 1) / kScanTile;
+    pl.n_col_tiles = (pl.n + kScanTile - 1) / kScanTile;
+
+    Carver cv;
+    const size_t o_H = cv.take<uint8_t>(pl.k);
+    const size_t o_gid = cv.take<int32_t>(pl.k);
+    const size_t o_hit = cv.take<uint8_t>(pl.G);
+    const size_t o_gfirst = cv.take<int32_t>(pl.G);
+    const size_t o_glast = cv.take<int32_t>(pl.G);
+    const size_t o_gbase = cv.take<int64_t>(P + 1);
+    const size_t o_tiles = cv.take<RankTile>(pl.n_rank_tiles);
+    const size_t o_map = cv.take<int32_t>(pl.k);
+    const size_t o_colid = cv.take<int32_t>(pl.k);
+    const size_t o_Atc = cv.take<int64_t>(pl.k + 1);
+    const size_t o_Atr = cv.take<int32_t>(pl.nnzA);
+    const size_t o_Atv = cv.take<uint8_t>(pl.nnzA * (int64_t)pl.vsize);
+    const size_t o_st = cv.take<uint64_t>(pl.n_rank_tiles + 2 * pl.n_sel_tiles);
+    const size_t o_stc = cv.take<uint64_t>(pl.n_col_tiles);
+    const size_t o_ctr = cv.take<DevCounters>(1);
+    const size_t o_flop = cv.take<int64_t>(pl.n);
+    const size_t o_sbin = cv.take<int32_t>(pl.n);
+    const size_t o_nbin = cv.take<int32_t>(pl.n);
+    const size_t o_slist = cv.take<int32_t>(kNumBins * pl.n);
+    const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
+    const size_t ws_bytes = cv.off;
+    if (tun.workspace_limit > 0 && (int64_t)ws_bytes > tun.workspace_limit) {
+        delete p;
+        return fail(SPGEMM_ENOMEM, "plan needs " + std::to_string(ws_bytes) +
+                                       " bytes of workspace, above workspace_limit");
+    }
+    Carver ch;
+    const size_t h_ctr = ch.take<DevCounters>(1);
+    const size_t h_gbase = ch.take<int64_t>(P + 1);
+    const size_t h_tiles = ch.take<RankTile>(pl.n_rank_tiles);
+    const size_t pinned_bytes = ch.off;
+
+    if ((rc = pool_get(ws_bytes, false, pl.device, pl.stream, &pl.ws, &pl.ws_bytes))) {
+        delete p;
+        return rc;
+    }
+    if ((rc = pool_get(pinned_bytes, true, pl.device, pl.stream, &pl.pinned, &pl.pinned_bytes))) {
+        pool_put(pl.ws, pl.ws_bytes, false, pl.device, pl.stream);
+        delete p;
+        return rc;
+    }
+    char *w = (char *)pl.ws;
+    pl.H = (uint8_t *)(w + o_H);
+    pl.gid = (int32_t *)(w + o_gid);
+    pl.hit = (uint8_t *)(w + o_hit);
+    pl.gfirst = (int32_t *)(w + o_gfirst);
+    pl.glast = (int32_t *)(w + o_glast);
+    pl.group_base = (int64_t *)(w + o_gbase);
+    pl.rank_tiles = (RankTile *)(w + o_tiles);
+    pl.map = (int32_t *)(w + o_map);
+    pl.colid = (int32_t *)(w + o_colid);
+    pl.At_colptr = (int64_t *)(w + o_Atc);
+    pl.At_rowidx = (int32_t *)(w + o_Atr);
+    pl.At_vals = (void *)(w + o_Atv);
+    pl.st_rank = (uint64_t *)(w + o_st);
+    pl.st_sel_cnt = pl.st_rank + pl.n_rank_tiles;
+    pl.st_sel_nnz = pl.st_sel_cnt + pl.n_sel_tiles;
+    pl.st_colptr = (uint64_t *)(w + o_stc);
+    pl.ctr = (DevCounters *)(w + o_ctr);
+    pl.flop = (int64_t *)(w + o_flop);
+    pl.sym_bin = (int32_t *)(w + o_sbin);
+    pl.num_bin = (int32_t *)(w + o_nbin);
+    pl.sym_list = (int32_t *)(w + o_slist);
+    pl.num_list = (int32_t *)(w + o_nlist);
+    char *h = (char *)pl.pinned;
+    pl.hctr = (DevCounters *)(h + h_ctr);
+    std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
+    if (!tiles.empty()) std::memcpy(h + h_tiles, tiles.data(), sizeof(RankTile) * tiles.size());
+
+    auto cleanup = [&](int code) {
+        (void)hipStreamSynchronize(pl.stream);
+        pool_put(pl.ws, pl.ws_bytes, false, pl.device, pl.stream);
+        pool_put(pl.pinned, pl.pinned_bytes, true, pl.device, pl.stream);
+        delete p;
+        return code;
+    };
+    hipError_t e = hipMemcpyAsync(pl.group_base, h + h_gbase, sizeof(int64_t) * (P + 1),
+                                  hipMemcpyHostToDevice, pl.stream);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpyAsync(pl.rank_tiles, h + h_tiles, sizeof(RankTile) * tiles.size(),
+                           hipMemcpyHostToDevice, pl.stream);
+    if (e != hipSuccess) return cleanup(fail(SPGEMM_EHIP, std::string("hipMemcpyAsync: ") +
+                                                              hipGetErrorString(e)));
+    if (tun.validate) {
+        e = hipMemsetAsync(pl.ctr, 0, sizeof(DevCounters), pl.stream);
+        if (e != hipSuccess) return cleanup(fail(SPGEMM_EHIP, hipGetErrorString(e)));
+        if ((rc = launch_validate(pl))) return cleanup(rc);
+        if ((rc = sync_counters(pl))) return cleanup(rc);
+        if (pl.hctr->error & 1) return cleanup(fail(SPGEMM_EINVAL, "A is not a valid CSC matrix "
+                                                                   "(pointers or sorted unique rows)"));
+        if (pl.hctr->error & 2) return cleanup(fail(SPGEMM_EINVAL, "Bi is not a valid CSC matrix "
+                                                                   "(pointers or sorted unique rows)"));
+    }
+    if ((rc = launch_plan_kernels(pl))) return cleanup(rc);
+    *out = p;
+    return SPGEMM_OK;
+}
+
+int spgemm_plan_set_stream(spgemm_plan_t plan, void *stream) {
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    plan->stream = (hipStream_t)stream;
+    return SPGEMM_OK;
+}
+
+int spgemm_plan_stats(spgemm_plan_t plan, spgemm_stats *s) {
+    if (!plan || !s) return fail(SPGEMM_EINVAL, "plan or stats is NULL");
+    Plan &p = *plan;
+    int rc = sync_counters(p);
+    if (rc) return rc;
+    const DevCounters &c = *p.hctr;
+    std::memset(s, 0, sizeof(*s));
+    s->m = p.m;
+    s->k = p.k;
+    s->n = p.n;
+    s->nnz_A = p.nnzA;
+    s->nnz_B = p.nnzB;
+    s->h_count = c.h_count;
+    s->nzc_A = c.nzc;
+    s->K = c.K;
+    s->M = c.M;
+    s->kt = c.kt;
+    s->nnz_At = c.nnz_At;
+    s->cv_memA = p.nnzA > 0 ? (double)c.nnz_At / (double)p.nnzA : 0.0;
+    s->flops = p.symbolic_done ? p.flops : -1;
+    s->nnz_C = p.symbolic_done ? p.nnzC : -1;
+    for (int b = 0; b < kNumBins; ++b) {
+        s->sym_bins[b] = p.symbolic_done ? p.sym_count[b] : 0;
+        s->num_bins[b] = p.symbolic_done ? p.num_count[b] : 0;
+    }
+    return SPGEMM_OK;
+}
+
+int spgemm_plan_export(spgemm_plan_t plan, uint8_t *H, int32_t *map, int64_t *At_colptr,
+                       int32_t *At_rowidx, void *At_vals, int64_t *blocks) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    Plan &p = *plan;
+    int rc = sync_counters(p);
+    if (rc) return rc;
+    const int64_t kt = p.hctr->kt, nt = p.hctr->nnz_At;
+    if (H && p.k) SPG_HIP(hipMemcpyAsync(H, p.H, p.k, hipMemcpyDeviceToDevice, p.stream));
+    if (map && p.k)
+        SPG_HIP(hipMemcpyAsync(map, p.map, 4 * p.k, hipMemcpyDeviceToDevice, p.stream));
+    if (At_colptr)
+        SPG_HIP(hipMemcpyAsync(At_colptr, p.At_colptr, 8 * (kt + 1), hipMemcpyDeviceToDevice,
+                               p.stream));
+    if (At_rowidx && nt)
+        SPG_HIP(hipMemcpyAsync(At_rowidx, p.At_rowidx, 4 * nt, hipMemcpyDeviceToDevice, p.stream));
+    if (At_vals && nt)
+        SPG_HIP(hipMemcpyAsync(At_vals, p.At_vals, p.vsize * nt, hipMemcpyDeviceToDevice,
+                               p.stream));
+    if (blocks && (rc = launch_export_blocks(p, blocks))) return rc;
+    return SPGEMM_OK;
+}
+
+int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
+                            int32_t *num_bin) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    Plan &p = *plan;
+    if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_symbolic has not run on this plan");
+    if (p.n == 0) return SPGEMM_OK;
+    if (flop) SPG_HIP(hipMemcpyAsync(flop, p.flop, 8 * p.n, hipMemcpyDeviceToDevice, p.stream));
+    if (sym_bin)
+        SPG_HIP(hipMemcpyAsync(sym_bin, p.sym_bin, 4 * p.n, hipMemcpyDeviceToDevice, p.stream));
+    if (num_bin)
+        SPG_HIP(hipMemcpyAsync(num_bin, p.num_bin, 4 * p.n, hipMemcpyDeviceToDevice, p.stream));
+    return SPGEMM_OK;
+}
+
+int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    if (!C_colptr || !nnzC) return fail(SPGEMM_EINVAL, "C_colptr and nnzC must not be NULL");
+    Plan &p = *plan;
+    p.C_colptr = C_colptr;
+    p.symbolic_done = false;
+    int rc;
+    if (p.n == 0) {
+        SPG_HIP(hipMemsetAsync(C_colptr, 0, sizeof(int64_t), p.stream));
+        p.nnzC = 0;
+        p.flops = 0;
+        for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.num_count[b] = 0;
+        p.symbolic_done = true;
+        *nnzC = 0;
+        return SPGEMM_OK;
+    }
+    // reset the symbolic counters: colptr ticket, flops .. num_count
+    SPG_HIP(hipMemsetAsync(&p.ctr->tickets[kTkColptr], 0, sizeof(unsigned long long), p.stream));
+    SPG_HIP(hipMemsetAsync(&p.ctr->flops, 0,
+                           offsetof(DevCounters, error) - offsetof(DevCounters, flops), p.stream));
+    if ((rc = launch_flop_bin(p))) return rc;
+    SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
+    SPG_HIP(hipStreamSynchronize(p.stream));
+    for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b];
+    if ((rc = launch_symbolic_bins(p))) return rc;
+    if ((rc = launch_colptr_scan(p))) return rc;
+    SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
+    SPG_HIP(hipStreamSynchronize(p.stream));
+    p.nnzC = p.hctr->nnzC;
+    p.flops = p.hctr->flops;
+    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hctr->num_count[b];
+    p.symbolic_done = true;
+    *nnzC = p.nnzC;
+    return SPGEMM_OK;
+}
+
+int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
+                   int32_t *C_rowidx, void *C_vals) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    Plan &p = *plan;
+    if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_numeric needs spgemm_symbolic first");
+    if (p.nnzC > 0 && (!C_rowidx || !C_vals))
+        return fail(SPGEMM_EINVAL, "C_rowidx and C_vals must not be NULL");
+    const void *Bv = Bi_vals ? Bi_vals : p.Bvals;
+    if (p.nnzC > 0 && !Bv) return fail(SPGEMM_EINVAL, "no values for B_i");
+    if (!A_vals && !p.Avals && p.nnzC > 0) return fail(SPGEMM_EINVAL, "no values for A");
+    int rc;
+    if (A_vals && (rc = launch_gather_values(p, A_vals))) return rc;
+    return launch_numeric_bins(p, Bv, C_rowidx, C_vals);
+}
+
+int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *C_rowidx,
+                    const void *A_vals, const void *Bi_vals, const void *dC_vals, void *dA_vals,
+                    void *dB_vals) {
+    (void)hipGetLastError();  // drop errors left by other code on this thread
+    if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+    Plan &p = *plan;
+    if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_backward needs spgemm_symbolic first");
+    if (!dA_vals && !dB_vals) return SPGEMM_OK;
+    const void *Av = A_vals ? A_vals : p.Avals;
+    const void *Bv = Bi_vals ? Bi_vals : p.Bvals;
+    if (!C_colptr) return fail(SPGEMM_EINVAL, "C_colptr is NULL");
+    if (p.nnzC > 0 && (!C_rowidx || !dC_vals))
+        return fail(SPGEMM_EINVAL, "C_rowidx and dC_vals must not be NULL");
+    if ((p.nnzA > 0 && !Av) || (p.nnzB > 0 && !Bv))
+        return fail(SPGEMM_EINVAL, "backward needs the values of A and B_i");
+    return launch_backward(p, C_colptr, C_rowidx, Av, Bv, dC_vals, dA_vals, dB_vals);
+}
+
+int spgemm_plan_destroy(spgemm_plan_t plan) {
+    if (!plan) return SPGEMM_OK;
+    Plan &p = *plan;
+    pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
+    pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream);
+    delete plan;
+    return SPGEMM_OK;
+}
+
+}  // extern "C"

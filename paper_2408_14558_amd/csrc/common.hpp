@@ -1,0 +1,218 @@
+// Device-side helpers shared by the gfx950 kernels of the local SpGEMM.
+//
+// Wave64 primitives (scans, bitonic steps over lanes), the chained-scan tile
+// protocol used by every prefix sum of the path, and small atomics.  Nothing
+// here is specific to one step of the method.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace spg {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Compiler + LDS ordering point for lanes of one wave (a wave runs in
+// lockstep, so only the compiler and LDS completion need fencing).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronises a group of G threads: a wave-local fence when the group
+// lies inside one wave, a workgroup barrier otherwise (then the group is the
+// whole workgroup).
+template <int G>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (G <= kWave) {
+        wave_sync();
+    } else {
+        __syncthreads();
+    }
+}
+
+// Inclusive scan over the lanes of a wave (width W, power of two <= 64).
+template <int W = kWave, typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id() & (W - 1);
+#pragma unroll
+    for (int d = 1; d < W; d <<= 1) {
+        T o = __shfl_up(v, d, W);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+template <int W = kWave, typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = W >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, W);
+    return v;
+}
+
+template <int W = kWave, typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int d = W >> 1; d > 0; d >>= 1) {
+        T o = __shfl_xor(v, d, W);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Number of set bits of a 64-bit lane mask below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+    return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+}
+
+// Exclusive scan of one int value per thread over a group of G threads
+// (G a power of two).  `tmp` is LDS scratch of at least G/64+1 ints when
+// G > 64 (unused otherwise).  Returns the exclusive prefix; *total gets the
+// group sum.  All G threads must call it.
+template <int G>
+__device__ __forceinline__ int group_excl_scan(int v, int *tmp, int *total) {
+    if constexpr (G <= kWave) {
+        int incl = wave_incl_scan<G>(v);
+        *total = __shfl(incl, G - 1, G);
+        return incl - v;
+    } else {
+        constexpr int NW = G / kWave;
+        const int t = threadIdx.x;
+        const int w = t / kWave;
+        int incl = wave_incl_scan<kWave>(v);
+        if (lane_id() == kWave - 1) tmp[w] = incl;
+        __syncthreads();
+        if (t < kWave) {
+            int s = (t < NW) ? tmp[t] : 0;
+            int si = wave_incl_scan<kWave>(s);
+            if (t < NW) tmp[t] = si - s;
+            if (t == kWave - 1) tmp[NW] = si;
+        }
+        __syncthreads();
+        int res = tmp[w] + incl - v;
+        *total = tmp[NW];
+        __syncthreads();
+        return res;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ long long group_excl_scan64(long long v, long long *tmp,
+                                                       long long *total) {
+    if constexpr (G <= kWave) {
+        long long incl = wave_incl_scan<G>(v);
+        *total = __shfl(incl, G - 1, G);
+        return incl - v;
+    } else {
+        constexpr int NW = G / kWave;
+        const int t = threadIdx.x;
+        const int w = t / kWave;
+        long long incl = wave_incl_scan<kWave>(v);
+        if (lane_id() == kWave - 1) tmp[w] = incl;
+        __syncthreads();
+        if (t < kWave) {
+            long long s = (t < NW) ? tmp[t] : 0;
+            long long si = wave_incl_scan<kWave>(s);
+            if (t < NW) tmp[t] = si - s;
+            if (t == kWave - 1) tmp[NW] = si;
+        }
+        __syncthreads();
+        long long res = tmp[w] + incl - v;
+        *total = tmp[NW];
+        __syncthreads();
+        return res;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chained scan across workgroups (single pass, decoupled look-back).
+//
+// Every tile publishes one 64-bit status word: bits 62..63 hold the state
+// (1 = tile aggregate, 2 = inclusive prefix), bits 0..61 the value.  A tile
+// marked as a segment head publishes its inclusive prefix at once, so a
+// look-back never crosses a head.  Tiles are handed out in launch order by
+// an atomic ticket, so every tile a look-back waits on is already resident
+// and finishes without waiting on later tiles.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStInc = 2ull << 62;
+constexpr uint64_t kStMask = 3ull << 62;
+constexpr uint64_t kValMask = ~kStMask;
+
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by ONE thread of the tile.  Returns the exclusive prefix of `tile`
+// and publishes its inclusive prefix.
+__device__ __forceinline__ long long chained_prefix(uint64_t *status, long long tile, bool head,
+                                                    long long aggregate) {
+    if (head) {
+        status_store(&status[tile], kStInc | (uint64_t)aggregate);
+        return 0;
+    }
+    status_store(&status[tile], kStAgg | (uint64_t)aggregate);
+    long long prefix = 0;
+    long long j = tile - 1;
+    while (true) {
+        uint64_t s = status_load(&status[j]);
+        uint64_t st = s & kStMask;
+        if (st == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        prefix += (long long)(s & kValMask);
+        if (st == kStInc) break;
+        --j;
+    }
+    status_store(&status[tile], kStInc | (uint64_t)(prefix + aggregate));
+    return prefix;
+}
+
+// Takes the next tile ticket (thread 0) and broadcasts it to the workgroup.
+__device__ __forceinline__ long long take_ticket(unsigned long long *counter, long long *lds_slot) {
+    if (threadIdx.x == 0) *lds_slot = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    long long t = *lds_slot;
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+// Slot of row r in a table of T (power of two) slots: the top log2(T) bits
+// of r times 2^32/phi (Knuth's multiplicative hashing), so rows that differ
+// only in high bits still spread over the table.
+template <int T>
+__device__ __forceinline__ uint32_t hash_slot(int32_t r) {
+    static_assert((T & (T - 1)) == 0 && T >= 2, "table size must be a power of two");
+    constexpr int kBits = __builtin_ctz(T);
+    return ((uint32_t)r * 2654435761u) >> (32 - kBits);
+}
+
+__device__ __forceinline__ void atomic_add_i64(long long *p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+template <typename V>
+__device__ __forceinline__ void lds_atomic_add(V *p, V v) {
+    atomicAdd(p, v);
+}
+
+__device__ __forceinline__ int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace spg

@@ -1,0 +1,181 @@
+// Internal declarations shared by the host side of the library and the
+// kernel translation units.  Not part of the public ABI (include/spgemm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spgemm.h"
+
+namespace spg {
+
+// Bins of output columns.  The symbolic phase bins by sparse flops, the
+// numeric phase by flops (tiny) and by the exact nnz of the column.
+enum Bin : int {
+    kBinEmpty = 0,
+    kBinTiny = 1,  // flop <= tiny_max_flop (<= 64): one wave, terms in registers
+    kBinH0 = 2,    // LDS hash, smallest table
+    kBinH1 = 3,
+    kBinH2 = 4,
+    kBinH3 = 5,    // LDS hash, largest table
+    kBinDense = 6, // LDS bitmap over all rows (symbolic) / rank windows (numeric)
+    kNumBins = 8
+};
+
+// Hash-table sizes (slots, power of two) per hash bin.  A bin holds columns
+// whose key count (flops for symbolic, nnz for numeric) is at most half the
+// table, so probing stays short.
+constexpr int kSymTable[4] = {256, 1024, 4096, 8192};
+constexpr int kNumTable[4] = {256, 512, 2048, 4096};
+
+// Dense-bin limits: the bitmap covers every row of C in LDS.
+constexpr int64_t kMaxDenseRows = 1 << 18;  // 32 KiB bitmap
+constexpr int kDenseThreads = 1024;
+
+// Tiles of the chained scans.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 1024 elements
+
+struct RankTile {
+    int64_t col0;   // first column of the tile
+    int32_t ncols;  // columns in the tile (<= kScanTile)
+    int32_t part;   // partition of A the tile lies in
+    int32_t head;   // 1: first tile of its partition
+    int32_t last;   // 1: last tile of its partition
+};
+
+// Counters kept in device memory; the host copies the block from h_count on.
+struct DevCounters {
+    unsigned long long tickets[8];  // chained-scan tile tickets
+    long long h_count;
+    long long nzc;
+    long long K;
+    long long M;
+    long long kt;
+    long long nnz_At;
+    long long flops;
+    long long nnzC;
+    int sym_count[kNumBins];
+    int num_count[kNumBins];
+    int error;  // bit 0: A malformed, bit 1: B malformed
+    int pad[7];
+};
+
+enum Ticket { kTkRank = 0, kTkSelect = 1, kTkColptr = 2, kTkExport = 3 };
+
+struct Thresholds {
+    int tiny_max_flop;
+    int sym_hash_max[4];  // flop limit per symbolic hash bin (0 = bin unused)
+    int num_hash_max[4];  // nnz limit per numeric hash bin
+};
+
+// ---------------------------------------------------------------------------
+// host-side plan
+// ---------------------------------------------------------------------------
+struct Plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    spgemm_dtype dtype = SPGEMM_F64;
+    size_t vsize = 8;
+    spgemm_tuning tun{};
+    Thresholds th{};
+
+    int64_t m = 0, k = 0, n = 0, nnzA = 0, nnzB = 0;
+    const int64_t *Acolptr = nullptr;
+    const int32_t *Arowidx = nullptr;
+    const void *Avals = nullptr;
+    const int64_t *Bcolptr = nullptr;
+    const int32_t *Browidx = nullptr;
+    const void *Bvals = nullptr;
+    int32_t P = 1;
+    int64_t b = 1;
+    std::vector<int64_t> offs;
+
+    // workspace (one pooled device block carved into arrays)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *pinned = nullptr;  // pooled pinned host block
+    size_t pinned_bytes = 0;
+
+    uint8_t *H = nullptr;
+    int32_t *gid = nullptr;
+    uint8_t *hit = nullptr;
+    int32_t *gfirst = nullptr;
+    int32_t *glast = nullptr;
+    int64_t G = 0;  // size of the group-id space
+    int64_t *group_base = nullptr;  // device [P+1]
+    RankTile *rank_tiles = nullptr;  // device
+    int64_t n_rank_tiles = 0;
+    int32_t *map = nullptr;
+    int32_t *colid = nullptr;
+    int64_t *At_colptr = nullptr;
+    int32_t *At_rowidx = nullptr;
+    void *At_vals = nullptr;
+    uint64_t *st_rank = nullptr;
+    uint64_t *st_sel_cnt = nullptr;
+    uint64_t *st_sel_nnz = nullptr;
+    uint64_t *st_colptr = nullptr;
+    int64_t n_sel_tiles = 0, n_col_tiles = 0;
+    DevCounters *ctr = nullptr;
+
+    int64_t *flop = nullptr;
+    int32_t *sym_bin = nullptr;
+    int32_t *num_bin = nullptr;
+    int32_t *sym_list = nullptr;  // kNumBins x n
+    int32_t *num_list = nullptr;  // kNumBins x n
+    int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
+
+    // host view of the counters (inside the pinned block)
+    DevCounters *hctr = nullptr;
+
+    // symbolic results
+    bool symbolic_done = false;
+    int64_t *C_colptr = nullptr;
+    int64_t nnzC = -1;
+    int64_t flops = -1;
+    int sym_count[kNumBins] = {0};
+    int num_count[kNumBins] = {0};
+};
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define SPG_HIP(call)                                                                \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::spg::fail(SPGEMM_EHIP, std::string(#call) + ": " +              \
+                                                 hipGetErrorString(e_));             \
+    } while (0)
+
+// Checks the launch just made; names the kernel in the message.
+#define SPG_LAUNCHED(name)                                                           \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess)                                                        \
+            return ::spg::fail(SPGEMM_EHIP, std::string("launch of ") + (name) + ": " + \
+                                                 hipGetErrorString(e_));             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// launchers (each returns SPGEMM_OK or an error code with the message set)
+// ---------------------------------------------------------------------------
+int launch_validate(Plan &p);
+int launch_plan_kernels(Plan &p);
+int launch_gather_values(Plan &p, const void *Avals);
+int launch_export_blocks(Plan &p, int64_t *blocks);
+int launch_flop_bin(Plan &p);
+int launch_symbolic_bins(Plan &p);
+int launch_colptr_scan(Plan &p);
+int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
+int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
+                    const void *Bvals, const void *dC, void *dA, void *dB);
+
+}  // namespace spg

@@ -1,0 +1,103 @@
+// Numeric phase kernels: one launch per non-empty column bin.
+#include "numeric.hpp"
+
+namespace spg {
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_num_tiny(const int32_t *__restrict__ list, int count,
+                                                  NumArgs<V> a) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= count) return;
+    num_tiny_column<V>(a, list[w]);
+}
+
+template <int T, int G, typename V>
+__global__ __launch_bounds__(G < 256 ? 256 : G) void k_num_hash(const int32_t *__restrict__ list,
+                                                                int count, NumArgs<V> a) {
+    constexpr int CPW = G < 256 ? 256 / G : 1;
+    __shared__ NumHashLds<T, G, V> lds[CPW];
+    const int grp = threadIdx.x / G, gt = threadIdx.x % G;
+    const int w = blockIdx.x * CPW + grp;
+    if (w >= count) return;  // CPW > 1 only when a group sits inside one wave
+    num_hash_column<T, G, V>(a, list[w], lds[grp], gt);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__restrict__ list,
+                                                             int count, NumArgs<V> a, int VC) {
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ NumDenseStatic<V> S;
+    const int w = blockIdx.x;
+    if (w >= count) return;
+    const int nw = (int)((a.m + 31) >> 5);
+    uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
+    int *wpre = reinterpret_cast<int *>(bits + nw);
+    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 8 + 15) & ~(size_t)15));
+    num_dense_column<V>(a, list[w], bits, wpre, vals, VC, S);
+}
+
+// Dynamic LDS of the dense kernel and the window size it allows.
+size_t dense_lds_bytes(int64_t m, size_t vsize, int *VC_out) {
+    const size_t nw = (size_t)((m + 31) / 32);
+    const size_t head = (nw * 8 + 15) & ~(size_t)15;
+    // keep the whole workgroup under 144 KiB: static part ~ 24 KiB
+    const size_t budget = 120 * 1024;
+    size_t vc_bytes = budget > head ? budget - head : 0;
+    int VC = 1;
+    while ((size_t)(VC * 2) * vsize <= vc_bytes && VC < (1 << 16)) VC *= 2;
+    *VC_out = VC;
+    return head + (size_t)VC * vsize;
+}
+
+template <int T, int G, typename V>
+static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
+    const int cnt = p.num_count[bin];
+    if (cnt <= 0) return SPGEMM_OK;
+    constexpr int CPW = G < 256 ? 256 / G : 1;
+    constexpr int threads = G < 256 ? 256 : G;
+    const unsigned grid = (unsigned)((cnt + CPW - 1) / CPW);
+    hipLaunchKernelGGL((k_num_hash<T, G, V>), dim3(grid), dim3(threads), 0, p.stream,
+                       p.num_list + (int64_t)bin * p.n, cnt, a);
+    SPG_LAUNCHED("k_num_hash<" + std::to_string(T) + ">");
+    return SPGEMM_OK;
+}
+
+template <typename V>
+static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
+    NumArgs<V> a{p.m,         p.Bcolptr, p.Browidx,  Bvals, p.map,
+                 p.At_colptr, p.At_rowidx, (const V *)p.At_vals, p.C_colptr, Crow, Cval};
+    const int64_t n = p.n;
+    auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
+    if (p.num_count[kBinTiny] > 0)
+    {
+        hipLaunchKernelGGL(k_num_tiny<V>, dim3((p.num_count[kBinTiny] + 3) / 4), dim3(256), 0,
+                           p.stream, list(kBinTiny), p.num_count[kBinTiny], a);
+        SPG_LAUNCHED("k_num_tiny");
+    }
+    int rc;
+    if ((rc = num_hash_launch<kNumTable[0], kNumTable[0] / 8, V>(p, kBinH0, a))) return rc;
+    if ((rc = num_hash_launch<kNumTable[1], kNumTable[1] / 8, V>(p, kBinH1, a))) return rc;
+    if ((rc = num_hash_launch<kNumTable[2], kNumTable[2] / 8, V>(p, kBinH2, a))) return rc;
+    if ((rc = num_hash_launch<kNumTable[3], kNumTable[3] / 8, V>(p, kBinH3, a))) return rc;
+    if (p.num_count[kBinDense] > 0) {
+        if (p.m > kMaxDenseRows)
+            return fail(SPGEMM_EUNSUPPORTED,
+                        "columns with more rows than the largest hash bin need m <= 262144");
+        int VC;
+        const size_t lds = dense_lds_bytes(p.m, sizeof(V), &VC);
+        hipLaunchKernelGGL(k_num_dense<V>, dim3(p.num_count[kBinDense]), dim3(kDenseThreads), lds,
+                           p.stream, list(kBinDense), p.num_count[kBinDense], a, VC);
+        SPG_LAUNCHED("k_num_dense (dynamic LDS " + std::to_string(lds) + " B)");
+    }
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals) {
+    if (p.n == 0 || p.nnzC == 0) return SPGEMM_OK;
+    if (p.dtype == SPGEMM_F64)
+        return numeric_bins_t<double>(p, (const double *)Bvals, Crow, (double *)Cvals);
+    return numeric_bins_t<float>(p, (const float *)Bvals, Crow, (float *)Cvals);
+}
+
+}  // namespace spg

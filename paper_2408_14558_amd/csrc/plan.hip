@@ -1,0 +1,352 @@
+// Plan-phase kernels: the gather half of the sparsity-aware 1D algorithm
+// (Alg. 1: H_i, the required columns, Alg. 2's block grouping, the fetch of
+// the chosen blocks and the compacted A~).  On one GPU the one-sided fetch
+// of a remote block becomes a device copy of a contiguous range of A's CSC
+// arrays.
+#include "common.hpp"
+
+namespace spg {
+
+// Clears H, the group tables, the scan states and the counters.
+__global__ void k_plan_init(uint8_t *__restrict__ H, int64_t k, uint8_t *__restrict__ hit,
+                            int32_t *__restrict__ gfirst, int32_t *__restrict__ glast, int64_t G,
+                            uint64_t *__restrict__ status, int64_t nstatus,
+                            DevCounters *__restrict__ ctr, int64_t *__restrict__ At_colptr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < k; i += stride) H[i] = 0;
+    for (int64_t g = t0; g < G; g += stride) {
+        hit[g] = 0;
+        gfirst[g] = -1;
+        glast[g] = -1;
+    }
+    for (int64_t s = t0; s < nstatus; s += stride) status[s] = 0;
+    if (t0 == 0) {
+        int *w = reinterpret_cast<int *>(ctr);
+        for (size_t i = 0; i < sizeof(DevCounters) / sizeof(int); ++i) w[i] = 0;
+        At_colptr[0] = 0;
+    }
+}
+
+// H_i: every row of B_i holding a stored entry (notation table; Alg. 1).
+__global__ void k_mark_rows(const int32_t *__restrict__ Browidx, int64_t nnzB,
+                            uint8_t *__restrict__ H) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzB; q += stride)
+        H[Browidx[q]] = 1;
+}
+
+// Rank of every nonzero column among the nonzero columns of its partition
+// (a scan segmented at partition starts), its Alg. 2 group
+// g = group_base[part] + rank / b, and the group's hit flag (any column of
+// the group named by H).  Also records each group's first and last column
+// and counts |H|, nzc and the number of groups K.
+__global__ __launch_bounds__(kScanThreads) void k_rank_groups(
+    const int64_t *__restrict__ Acolptr, const uint8_t *__restrict__ H,
+    const RankTile *__restrict__ tiles, const int64_t *__restrict__ group_base, int64_t b,
+    int32_t *__restrict__ gid, uint8_t *__restrict__ hit, int32_t *__restrict__ gfirst,
+    int32_t *__restrict__ glast, uint64_t *__restrict__ status, DevCounters *__restrict__ ctr) {
+    __shared__ long long s_ticket;
+    __shared__ int s_tmp[kScanThreads / kWave + 1];
+    __shared__ long long s_prefix;
+    const long long t = take_ticket(&ctr->tickets[kTkRank], &s_ticket);
+    const RankTile d = tiles[t];
+    const int tid = threadIdx.x;
+    int nz[kScanItems];
+    int cnt = 0, hcnt = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int off = tid * kScanItems + i;
+        nz[i] = 0;
+        if (off < d.ncols) {
+            const int64_t c = d.col0 + off;
+            nz[i] = Acolptr[c + 1] > Acolptr[c] ? 1 : 0;
+            hcnt += H[c];
+        }
+        cnt += nz[i];
+    }
+    int total;
+    int excl = group_excl_scan<kScanThreads>(cnt, s_tmp, &total);
+    if (tid == 0) s_prefix = chained_prefix(status, t, d.head != 0, total);
+    __syncthreads();
+    long long rank = s_prefix + excl;
+    const int64_t base = group_base[d.part];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int off = tid * kScanItems + i;
+        if (off >= d.ncols) break;
+        const int64_t c = d.col0 + off;
+        if (nz[i]) {
+            const int64_t g = base + rank / b;
+            gid[c] = (int32_t)g;
+            if (H[c]) hit[g] = 1;
+            if (rank % b == 0) gfirst[g] = (int32_t)c;
+            atomicMax(&glast[g], (int32_t)c);
+            ++rank;
+        } else {
+            gid[c] = -1;
+        }
+    }
+    int hsum = wave_sum(hcnt);
+    if (lane_id() == 0 && hsum) atomic_add_i64(&ctr->h_count, (long long)hsum);
+    if (tid == 0) {
+        atomic_add_i64(&ctr->nzc, (long long)total);
+        if (d.last) {
+            const long long nzc_part = s_prefix + total;
+            atomic_add_i64(&ctr->K, (nzc_part + b - 1) / b);
+        }
+    }
+}
+
+// Selection (column lies in a chosen group) and the map into A~: an
+// exclusive scan of the selection, with a second scan of the selected
+// columns' lengths giving A~'s column pointers.  Counts kt, nnz(A~) and the
+// chosen groups M.
+__global__ __launch_bounds__(kScanThreads) void k_select(
+    const int64_t *__restrict__ Acolptr, int64_t k, const int32_t *__restrict__ gid,
+    const uint8_t *__restrict__ hit, const int32_t *__restrict__ gfirst,
+    int32_t *__restrict__ map, int32_t *__restrict__ colid, int64_t *__restrict__ At_colptr,
+    uint64_t *__restrict__ st_cnt, uint64_t *__restrict__ st_nnz, int64_t ntiles,
+    DevCounters *__restrict__ ctr) {
+    __shared__ long long s_ticket;
+    __shared__ int s_tmp[kScanThreads / kWave + 1];
+    __shared__ long long s_tmp64[kScanThreads / kWave + 1];
+    __shared__ long long s_pc, s_pn;
+    const long long t = take_ticket(&ctr->tickets[kTkSelect], &s_ticket);
+    const int tid = threadIdx.x;
+    const int64_t c0 = t * kScanTile + (int64_t)tid * kScanItems;
+    int sel[kScanItems];
+    long long len[kScanItems];
+    int cnt = 0, mcnt = 0;
+    long long nnz = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t c = c0 + i;
+        sel[i] = 0;
+        len[i] = 0;
+        if (c < k) {
+            const int32_t g = gid[c];
+            if (g >= 0 && hit[g]) {
+                sel[i] = 1;
+                len[i] = Acolptr[c + 1] - Acolptr[c];
+                if (gfirst[g] == (int32_t)c) ++mcnt;
+            }
+        }
+        cnt += sel[i];
+        nnz += len[i];
+    }
+    int totc;
+    long long totn;
+    int exc = group_excl_scan<kScanThreads>(cnt, s_tmp, &totc);
+    long long exn = group_excl_scan64<kScanThreads>(nnz, s_tmp64, &totn);
+    if (tid == 0) s_pc = chained_prefix(st_cnt, t, t == 0, totc);
+    if (tid == kWave) s_pn = chained_prefix(st_nnz, t, t == 0, totn);
+    __syncthreads();
+    long long j = s_pc + exc;
+    long long pos = s_pn + exn;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t c = c0 + i;
+        if (c >= k) break;
+        if (sel[i]) {
+            map[c] = (int32_t)j;
+            colid[j] = (int32_t)c;
+            At_colptr[j] = pos;
+            ++j;
+            pos += len[i];
+        } else {
+            map[c] = -1;
+        }
+    }
+    int msum = wave_sum(mcnt);
+    if (lane_id() == 0 && msum) atomic_add_i64(&ctr->M, (long long)msum);
+    if (t == ntiles - 1 && tid == 0) {
+        const long long kt = s_pc + totc;
+        const long long nt = s_pn + totn;
+        At_colptr[kt] = nt;
+        ctr->kt = kt;
+        ctr->nnz_At = nt;
+    }
+}
+
+// Largest o in [0, n) with pref[o] <= s (pref non-decreasing, pref[0] = 0).
+__device__ __forceinline__ int find_owner(const int *pref, int n, int s) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= s)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Copies the selected columns (a chosen block is a contiguous range of A's
+// arrays) into A~.  One workgroup per 256 columns of A; the tile's copy work
+// is spread evenly over the workgroup.  kRows=false copies values only (new
+// values on the planned pattern).
+template <typename V, bool kRows>
+__global__ __launch_bounds__(256) void k_gather(const int64_t *__restrict__ Acolptr,
+                                                const int32_t *__restrict__ Arowidx,
+                                                const V *__restrict__ Avals,
+                                                const int32_t *__restrict__ map,
+                                                const int64_t *__restrict__ At_colptr, int64_t k,
+                                                int32_t *__restrict__ At_rowidx,
+                                                V *__restrict__ At_vals) {
+    __shared__ int s_pref[256];
+    __shared__ long long s_src[256];
+    __shared__ long long s_dst[256];
+    __shared__ int s_tmp[256 / kWave + 1];
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * 256 + tid;
+    int len = 0;
+    long long src = 0, dst = 0;
+    if (c < k) {
+        const int32_t j = map[c];
+        if (j >= 0) {
+            src = Acolptr[c];
+            len = (int)(Acolptr[c + 1] - src);
+            dst = At_colptr[j];
+        }
+    }
+    int total;
+    const int excl = group_excl_scan<256>(len, s_tmp, &total);
+    s_pref[tid] = excl;
+    s_src[tid] = src;
+    s_dst[tid] = dst;
+    __syncthreads();
+    for (int e = tid; e < total; e += 256) {
+        const int o = find_owner(s_pref, 256, e);
+        const int64_t off = e - s_pref[o];
+        const int64_t sp = s_src[o] + off;
+        const int64_t dp = s_dst[o] + off;
+        if (kRows) At_rowidx[dp] = Arowidx[sp];
+        At_vals[dp] = Avals[sp];
+    }
+}
+
+// Checks the CSC invariants of a matrix: colptr[0] = 0, colptr[n] = nnz,
+// non-decreasing pointers, row ids in range and strictly ascending per
+// column.  Sets bit `flag` of ctr->error on a violation.
+__global__ void k_validate(const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
+                           int64_t nrows, int64_t ncols, int64_t nnz, int flag,
+                           DevCounters *__restrict__ ctr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0 && (colptr[0] != 0 || colptr[ncols] != nnz)) bad = true;
+    for (int64_t j = t0; j < ncols; j += stride) {
+        const int64_t lo = colptr[j], hi = colptr[j + 1];
+        if (hi < lo || lo < 0 || hi > nnz) {
+            bad = true;
+            continue;
+        }
+        int32_t prev = -1;
+        for (int64_t p = lo; p < hi; ++p) {
+            const int32_t r = rowidx[p];
+            if (r <= prev || r >= nrows) {
+                bad = true;
+                break;
+            }
+            prev = r;
+        }
+    }
+    if (bad) atomicOr(&ctr->error, flag);
+}
+
+// Writes (first, last) of every chosen group in group order (Alg. 2's R).
+__global__ __launch_bounds__(1024) void k_export_blocks(const uint8_t *__restrict__ hit,
+                                                        const int32_t *__restrict__ gfirst,
+                                                        const int32_t *__restrict__ glast,
+                                                        int64_t G, int64_t *__restrict__ blocks) {
+    __shared__ int s_tmp[1024 / kWave + 1];
+    long long base = 0;
+    for (int64_t g0 = 0; g0 < G; g0 += 1024) {
+        const int64_t g = g0 + threadIdx.x;
+        const int h = (g < G && hit[g]) ? 1 : 0;
+        int total;
+        const int excl = group_excl_scan<1024>(h, s_tmp, &total);
+        if (h) {
+            blocks[2 * (base + excl)] = gfirst[g];
+            blocks[2 * (base + excl) + 1] = glast[g];
+        }
+        base += total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+int launch_validate(Plan &p) {
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(p.k, 256, 4096)), dim3(256), 0, p.stream,
+                       p.Acolptr, p.Arowidx, p.m, p.k, p.nnzA, 1, p.ctr);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(p.n, 256, 4096)), dim3(256), 0, p.stream,
+                       p.Bcolptr, p.Browidx, p.k, p.n, p.nnzB, 2, p.ctr);
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+int launch_plan_kernels(Plan &p) {
+    const int64_t nstatus = p.n_rank_tiles + 2 * p.n_sel_tiles;
+    const int64_t clear_work = std::max<int64_t>(std::max<int64_t>(p.k, p.G), nstatus);
+    hipLaunchKernelGGL(k_plan_init, dim3(grid_for(clear_work, 256, 2048)), dim3(256), 0, p.stream,
+                       p.H, p.k, p.hit, p.gfirst, p.glast, p.G, p.st_rank, nstatus, p.ctr,
+                       p.At_colptr);
+    if (p.nnzB > 0)
+        hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(p.nnzB, 256, 8192)), dim3(256), 0, p.stream,
+                           p.Browidx, p.nnzB, p.H);
+    if (p.n_rank_tiles > 0)
+        hipLaunchKernelGGL(k_rank_groups, dim3((unsigned)p.n_rank_tiles), dim3(kScanThreads), 0,
+                           p.stream, p.Acolptr, p.H, p.rank_tiles, p.group_base, p.b, p.gid,
+                           p.hit, p.gfirst, p.glast, p.st_rank, p.ctr);
+    if (p.n_sel_tiles > 0)
+        hipLaunchKernelGGL(k_select, dim3((unsigned)p.n_sel_tiles), dim3(kScanThreads), 0,
+                           p.stream, p.Acolptr, p.k, p.gid, p.hit, p.gfirst, p.map, p.colid,
+                           p.At_colptr, p.st_sel_cnt, p.st_sel_nnz, p.n_sel_tiles, p.ctr);
+    if (p.k > 0 && p.nnzA > 0) {
+        const unsigned g = (unsigned)((p.k + 255) / 256);
+        if (p.dtype == SPGEMM_F64)
+            hipLaunchKernelGGL((k_gather<double, true>), dim3(g), dim3(256), 0, p.stream,
+                               p.Acolptr, p.Arowidx, (const double *)p.Avals, p.map, p.At_colptr,
+                               p.k, p.At_rowidx, (double *)p.At_vals);
+        else
+            hipLaunchKernelGGL((k_gather<float, true>), dim3(g), dim3(256), 0, p.stream,
+                               p.Acolptr, p.Arowidx, (const float *)p.Avals, p.map, p.At_colptr,
+                               p.k, p.At_rowidx, (float *)p.At_vals);
+    }
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+int launch_gather_values(Plan &p, const void *Avals) {
+    if (p.k == 0 || p.nnzA == 0) return SPGEMM_OK;
+    const unsigned g = (unsigned)((p.k + 255) / 256);
+    if (p.dtype == SPGEMM_F64)
+        hipLaunchKernelGGL((k_gather<double, false>), dim3(g), dim3(256), 0, p.stream, p.Acolptr,
+                           p.Arowidx, (const double *)Avals, p.map, p.At_colptr, p.k, p.At_rowidx,
+                           (double *)p.At_vals);
+    else
+        hipLaunchKernelGGL((k_gather<float, false>), dim3(g), dim3(256), 0, p.stream, p.Acolptr,
+                           p.Arowidx, (const float *)Avals, p.map, p.At_colptr, p.k, p.At_rowidx,
+                           (float *)p.At_vals);
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+int launch_export_blocks(Plan &p, int64_t *blocks) {
+    if (p.G == 0) return SPGEMM_OK;
+    hipLaunchKernelGGL(k_export_blocks, dim3(1), dim3(1024), 0, p.stream, p.hit, p.gfirst,
+                       p.glast, p.G, blocks);
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+}  // namespace spg

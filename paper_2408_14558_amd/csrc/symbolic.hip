@@ -1,0 +1,322 @@
+// Symbolic phase of C_i = A~ * B_i: sparse flops per output column
+// (Sec. III-B), binning of columns by flops, the number of distinct rows of
+// each output column (Sec. III-A, column-by-column formula; a row counts as
+// soon as one product reaches it), and the exclusive scan giving C_i's
+// column pointers.  The scan also bins the columns for the numeric phase.
+#include "terms.hpp"
+
+namespace spg {
+
+__device__ __forceinline__ int sym_bin_of(long long f, const Thresholds &th) {
+    if (f == 0) return kBinEmpty;
+    if (f <= th.tiny_max_flop) return kBinTiny;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+        if (th.sym_hash_max[h] > 0 && f <= th.sym_hash_max[h]) return kBinH0 + h;
+    return kBinDense;
+}
+
+__device__ __forceinline__ int num_bin_of(long long f, long long nnz, const Thresholds &th) {
+    if (nnz == 0) return kBinEmpty;
+    if (f <= th.tiny_max_flop) return kBinTiny;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+        if (th.num_hash_max[h] > 0 && nnz <= th.num_hash_max[h]) return kBinH0 + h;
+    return kBinDense;
+}
+
+// Appends the workgroup's columns to the per-bin lists: one global atomic
+// per non-empty bin and workgroup reserves a contiguous range.
+__device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const int *s_lpos,
+                                               int *s_cnt, int *s_base, int64_t j0,
+                                               int *__restrict__ gcount,
+                                               int32_t *__restrict__ list, int64_t n) {
+    // s_cnt already holds the per-bin counts of this workgroup
+    if (threadIdx.x < kNumBins) {
+        const int c = s_cnt[threadIdx.x];
+        s_base[threadIdx.x] = c ? atomicAdd(&gcount[threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+        const int b = s_bin[i];
+        if (b != kBinEmpty) list[(int64_t)b * n + s_base[b] + s_lpos[i]] = (int32_t)(j0 + i);
+    }
+}
+
+// Sparse flops of every column of B_i and its symbolic bin.  A group of 16
+// lanes walks one column's entries; a workgroup covers 256 columns.
+constexpr int kFlopCols = 256;
+__global__ __launch_bounds__(256) void k_flop_bin(
+    int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
+    const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
+    int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
+    int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
+    DevCounters *__restrict__ ctr) {
+    __shared__ int s_bin[kFlopCols];
+    __shared__ int s_lpos[kFlopCols];
+    __shared__ int s_cnt[kNumBins];
+    __shared__ int s_base[kNumBins];
+    __shared__ long long s_flops;
+    const int tid = threadIdx.x;
+    {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t s = (int64_t)blockIdx.x * blockDim.x + tid; s < nstatus; s += stride)
+            status[s] = 0;
+    }
+    if (tid < kNumBins) s_cnt[tid] = 0;
+    if (tid == 0) s_flops = 0;
+    __syncthreads();
+    const int sub = tid & 15, grp = tid >> 4;
+    const int64_t j0 = (int64_t)blockIdx.x * kFlopCols;
+    const int nloc = (int)min<int64_t>(kFlopCols, n - j0);
+    long long my_flops = 0;
+    for (int r = 0; r < kFlopCols / 16; ++r) {
+        const int lc = grp + 16 * r;
+        const int64_t j = j0 + lc;
+        long long acc = 0;
+        if (lc < nloc) {
+            const int64_t q1 = Bcolptr[j + 1];
+            for (int64_t q = Bcolptr[j] + sub; q < q1; q += 16) {
+                const int32_t jt = map[Browidx[q]];
+                if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
+            }
+        }
+        acc = wave_sum<16>(acc);
+        if (lc < nloc && sub == 0) {
+            flop[j] = acc;
+            const int b = sym_bin_of(acc, th);
+            sym_bin[j] = b;
+            s_bin[lc] = b;
+            s_lpos[lc] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
+            if (b == kBinEmpty) Ccount[j] = 0;
+            my_flops += acc;
+        }
+    }
+    if (my_flops) atomic_add_i64(&s_flops, my_flops);
+    __syncthreads();
+    if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops, s_flops);
+    append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
+}
+
+// --- tiny bin: one wave per column, terms in registers, sort + count ------
+__global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ list, int count,
+                                                  const int64_t *__restrict__ Bcolptr,
+                                                  const int32_t *__restrict__ Browidx,
+                                                  const int32_t *__restrict__ map,
+                                                  const int64_t *__restrict__ At_colptr,
+                                                  const int32_t *__restrict__ At_rowidx,
+                                                  int64_t *__restrict__ Ccount) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= count) return;  // whole wave leaves together
+    const int32_t j = list[w];
+    int64_t p;
+    float dummy;
+    tiny_terms<float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, p, dummy);
+    int key = (p >= 0) ? At_rowidx[p] : kNoRow;
+    wave_sort_keys(key);
+    const int prev = __shfl_up(key, 1);
+    const bool head = key != kNoRow && (lane_id() == 0 || prev != key);
+    const uint64_t m = __ballot(head);
+    if (lane_id() == 0) Ccount[j] = __popcll(m);
+}
+
+// --- hash bins: LDS open addressing (linear probing), count inserts -------
+template <int T, int G>
+struct SymHashLds {
+    int keys[T];
+    EntryStage<G, float> st;
+};
+
+template <int T, int G>
+__global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
+    const int32_t *__restrict__ list, int count, const int64_t *__restrict__ Bcolptr,
+    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
+    const int64_t *__restrict__ At_colptr, const int32_t *__restrict__ At_rowidx,
+    int64_t *__restrict__ Ccount) {
+    constexpr int CPW = G < 256 ? 256 / G : 1;
+    __shared__ SymHashLds<T, G> lds[CPW];
+    const int grp = threadIdx.x / G, gt = threadIdx.x % G;
+    const int w = blockIdx.x * CPW + grp;
+    if (CPW == 1) {
+        if (w >= count) return;  // uniform over the workgroup
+    } else {
+        if (w >= count) return;  // groups live inside one wave: no workgroup barrier used
+    }
+    SymHashLds<T, G> &L = lds[grp];
+    const int32_t j = list[w];
+    for (int s = gt; s < T; s += G) L.keys[s] = -1;
+    group_sync<G>();
+    int inserted = 0;
+    for_each_term<G, float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, &L.st,
+                            gt, [&](int64_t p, float) {
+                                const int32_t r = At_rowidx[p];
+                                uint32_t h = hash_slot<T>(r);
+                                while (true) {
+                                    const int old = atomicCAS(&L.keys[h], -1, r);
+                                    if (old == -1) {
+                                        ++inserted;
+                                        break;
+                                    }
+                                    if (old == r) break;
+                                    h = (h + 1) & (T - 1);
+                                }
+                            });
+    int total;
+    if constexpr (G <= kWave) {
+        total = wave_sum<G>(inserted);
+    } else {
+        (void)group_excl_scan<G>(inserted, L.st.tmp, &total);
+    }
+    if (gt == 0) Ccount[j] = total;
+}
+
+// --- dense bin: bitmap of all m rows in LDS ---------------------------------
+struct SymDenseLds {
+    EntryStage<kDenseThreads, float> st;
+    int red[kDenseThreads / kWave + 2];
+};
+
+__global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
+    const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
+    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
+    const int64_t *__restrict__ At_colptr, const int32_t *__restrict__ At_rowidx,
+    int64_t *__restrict__ Ccount) {
+    extern __shared__ uint32_t s_bits[];
+    __shared__ SymDenseLds L;
+    const int w = blockIdx.x;
+    if (w >= count) return;
+    const int32_t j = list[w];
+    const int nw = (int)((m + 31) >> 5);
+    const int gt = threadIdx.x;
+    for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
+    __syncthreads();
+    for_each_term<kDenseThreads, float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map,
+                                        At_colptr, &L.st, gt, [&](int64_t p, float) {
+                                            const int32_t r = At_rowidx[p];
+                                            atomicOr(&s_bits[r >> 5], 1u << (r & 31));
+                                        });
+    int c = 0;
+    for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
+    int total;
+    (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
+    if (gt == 0) Ccount[j] = total;
+}
+
+// Exclusive scan of the per-column counts into C_i's column pointers (in
+// place), numeric binning of every column, nnz(C_i) into the counters.
+__global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
+    int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
+    int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
+    uint64_t *__restrict__ status, int64_t ntiles, DevCounters *__restrict__ ctr) {
+    __shared__ long long s_ticket;
+    __shared__ long long s_tmp64[kScanThreads / kWave + 1];
+    __shared__ long long s_prefix;
+    __shared__ int s_bin[kScanTile];
+    __shared__ int s_lpos[kScanTile];
+    __shared__ int s_cnt[kNumBins];
+    __shared__ int s_base[kNumBins];
+    const long long t = take_ticket(&ctr->tickets[kTkColptr], &s_ticket);
+    const int tid = threadIdx.x;
+    if (tid < kNumBins) s_cnt[tid] = 0;
+    __syncthreads();
+    const int64_t j0 = t * kScanTile;
+    const int nloc = (int)min<int64_t>(kScanTile, n - j0);
+    long long cnt[kScanItems];
+    long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int lc = tid * kScanItems + i;
+        cnt[i] = 0;
+        if (lc < nloc) {
+            const int64_t j = j0 + lc;
+            cnt[i] = Ccolptr[j];
+            const int b = num_bin_of(flop[j], cnt[i], th);
+            num_bin[j] = b;
+            s_bin[lc] = b;
+            s_lpos[lc] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
+        }
+        sum += cnt[i];
+    }
+    long long total;
+    long long excl = group_excl_scan64<kScanThreads>(sum, s_tmp64, &total);
+    if (tid == 0) s_prefix = chained_prefix(status, t, t == 0, total);
+    __syncthreads();
+    long long run = s_prefix + excl;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int lc = tid * kScanItems + i;
+        if (lc < nloc) Ccolptr[j0 + lc] = run;
+        run += cnt[i];
+    }
+    if (t == ntiles - 1 && tid == 0) {
+        Ccolptr[n] = s_prefix + total;
+        ctr->nnzC = s_prefix + total;
+    }
+    append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->num_count, num_list, n);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int launch_flop_bin(Plan &p) {
+    if (p.n == 0) return SPGEMM_OK;
+    const unsigned g = (unsigned)((p.n + kFlopCols - 1) / kFlopCols);
+    hipLaunchKernelGGL(k_flop_bin, dim3(g), dim3(256), 0, p.stream, p.n, p.Bcolptr, p.Browidx,
+                       p.map, p.At_colptr, p.th, p.flop, p.sym_bin, p.sym_list, p.C_colptr,
+                       p.st_colptr, p.n_col_tiles, p.ctr);
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+template <int T, int G>
+static int sym_hash_launch(Plan &p, int bin) {
+    const int cnt = p.sym_count[bin];
+    if (cnt <= 0) return SPGEMM_OK;
+    constexpr int CPW = G < 256 ? 256 / G : 1;
+    constexpr int threads = G < 256 ? 256 : G;
+    const unsigned g = (unsigned)((cnt + CPW - 1) / CPW);
+    hipLaunchKernelGGL((k_sym_hash<T, G>), dim3(g), dim3(threads), 0, p.stream,
+                       p.sym_list + (int64_t)bin * p.n, cnt, p.Bcolptr, p.Browidx, p.map,
+                       p.At_colptr, p.At_rowidx, p.C_colptr);
+    SPG_LAUNCHED("k_sym_hash<" + std::to_string(T) + ">");
+    return SPGEMM_OK;
+}
+
+
+int launch_symbolic_bins(Plan &p) {
+    if (p.n == 0) return SPGEMM_OK;
+    if (p.sym_count[kBinTiny] > 0) {
+        const unsigned g = (unsigned)((p.sym_count[kBinTiny] + 3) / 4);
+        hipLaunchKernelGGL(k_sym_tiny, dim3(g), dim3(256), 0, p.stream,
+                           p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
+                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.C_colptr);
+    }
+    int rc;
+    if ((rc = sym_hash_launch<kSymTable[0], 64>(p, kBinH0))) return rc;
+    if ((rc = sym_hash_launch<kSymTable[1], 64>(p, kBinH1))) return rc;
+    if ((rc = sym_hash_launch<kSymTable[2], 256>(p, kBinH2))) return rc;
+    if ((rc = sym_hash_launch<kSymTable[3], 512>(p, kBinH3))) return rc;
+    if (p.sym_count[kBinDense] > 0) {
+        if (p.m > kMaxDenseRows)
+            return fail(SPGEMM_EUNSUPPORTED,
+                        "columns with more flops than the largest hash bin need m <= 262144");
+        const size_t lds = (size_t)((p.m + 31) / 32) * 4;
+        hipLaunchKernelGGL(k_sym_dense, dim3((unsigned)p.sym_count[kBinDense]),
+                           dim3(kDenseThreads), lds, p.stream,
+                           p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
+                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.C_colptr);
+        SPG_LAUNCHED("k_sym_dense");
+    }
+    return SPGEMM_OK;
+}
+
+int launch_colptr_scan(Plan &p) {
+    if (p.n == 0) return SPGEMM_OK;
+    hipLaunchKernelGGL(k_colptr_scan, dim3((unsigned)p.n_col_tiles), dim3(kScanThreads), 0,
+                       p.stream, p.n, p.C_colptr, p.flop, p.th, p.num_bin, p.num_list,
+                       p.st_colptr, p.n_col_tiles, p.ctr);
+    SPG_HIP(hipGetLastError());
+    return SPGEMM_OK;
+}
+
+}  // namespace spg

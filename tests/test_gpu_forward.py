@@ -1,0 +1,227 @@
+"""GPU parity of the forward path (plan, symbolic, numeric) against the CPU
+oracle, through the C ABI.
+
+Bit-exact: H_i, the column map, Alg. 2's chosen blocks, A~ (row ids and
+values), the sparse flops per column, C_i's column pointers and row ids.
+Values: FP64 per entry within 1e-12 of max(|c|, sum |a||b|); FP32
+normwise within 1e-5 of the FP64 oracle.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _util import assert_values, columns_of
+
+pytestmark = pytest.mark.gpu
+
+spg = pytest.importorskip("paper_2408_14558_amd")
+
+
+def _dev(M, dtype):
+    return spg.DeviceCsc.from_host(M, dtype=dtype)
+
+
+def check_local(A, Bi, offs, b, dtype=torch.float64, tun=None, cols=None):
+    """Runs the GPU path for one partition and compares every stage."""
+    Ad, Bd = _dev(A, dtype), _dev(Bi, dtype)
+    if dtype == torch.float32:
+        A = synth.as_fp32(A)
+        Bi = synth.as_fp32(Bi)
+    ref = oracle.local_product(A, Bi, offs, b)
+    with spg.Plan(Ad, Bd, offs, b, tuning=tun) as p:
+        ex = p.export()
+        st = ex["stats"]
+        assert np.array_equal(ex["H"].cpu().numpy(), ref.H)
+        assert np.array_equal(ex["map"].cpu().numpy(), ref.selection.map)
+        assert st["kt"] == ref.selection.kt
+        assert st["K"] == ref.selection.K
+        assert st["M"] == ref.selection.blocks.shape[0]
+        assert np.array_equal(ex["blocks"].cpu().numpy().reshape(-1, 2), ref.selection.blocks)
+        assert st["h_count"] == int(ref.H.sum())
+        assert np.array_equal(ex["At_colptr"].cpu().numpy(), ref.At.colptr)
+        assert np.array_equal(ex["At_rowidx"].cpu().numpy(), ref.At.rowidx)
+        atv = ex["At_vals"].cpu().numpy()
+        assert np.array_equal(atv, np.asarray(ref.At.vals, dtype=atv.dtype))
+        colptr = p.symbolic()
+        flop, sbin, nbin = p.export_bins()
+        assert np.array_equal(flop.cpu().numpy(), ref.flop)
+        assert np.array_equal(colptr.cpu().numpy(), ref.C.colptr)
+        st2 = p.stats()
+        assert st2["flops"] == int(ref.flop.sum())
+        assert st2["nnz_C"] == int(ref.C.colptr[-1])
+        rows, vals = p.numeric()
+        assert np.array_equal(rows.cpu().numpy(), ref.C.rowidx)
+        assert_values(vals.cpu().numpy(), ref.C.vals, ref.C.absvals, dtype == torch.float64)
+        return st2, sbin.cpu().numpy(), nbin.cpu().numpy()
+
+
+def rand_csc(rng, m, n, density, lo=-1.0, hi=1.0, empty_cols=()):
+    mask = rng.random((m, n)) < density
+    for c in empty_cols:
+        mask[:, c] = False
+    r, c = np.nonzero(mask)
+    return synth.from_triplets(m, n, r, c, rng.uniform(lo, hi, r.size))
+
+
+def test_device_properties():
+    props = torch.cuda.get_device_properties(0)
+    print("device:", props.name, getattr(props, "gcnArchName", "?"),
+          "CUs:", props.multi_processor_count, flush=True)
+    assert "gfx950" in getattr(props, "gcnArchName", "gfx950")
+
+
+@pytest.mark.parametrize("b", [64, 1, 256])
+@pytest.mark.parametrize("i", [0, 1, 2, 3])
+def test_laplacian2d_partitions(i, b):
+    w = synth.workload("lap2d_64_p4")
+    A = w["A"]
+    Bi = synth.column_slice(A, int(w["offsets"][i]), int(w["offsets"][i + 1]))
+    check_local(A, Bi, w["offsets"], b)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_shapes(seed):
+    rng = np.random.default_rng(1000 + seed)
+    m, k, n = (int(x) for x in rng.integers(1, 300, 3))
+    A = rand_csc(rng, m, k, float(rng.uniform(0.0, 0.1)), empty_cols=(0,) if k > 1 else ())
+    Bi = rand_csc(rng, k, n, float(rng.uniform(0.0, 0.1)))
+    P = int(rng.integers(1, min(k, 8) + 1))
+    offs = synth.partition_offsets(k, P)
+    b = int(rng.choice([1, 2, 3, 16, 1000]))
+    check_local(A, Bi, offs, b)
+
+
+@pytest.mark.parametrize("case", ["emptyB", "one_row", "one_col", "P_equals_k", "all_empty_A"])
+def test_edge_cases(case):
+    rng = np.random.default_rng(7)
+    if case == "emptyB":
+        A = rand_csc(rng, 50, 40, 0.1)
+        Bi = synth.from_triplets(40, 10, [], [], [])
+        offs = synth.partition_offsets(40, 4)
+    elif case == "one_row":
+        A = rand_csc(rng, 1, 30, 0.5)
+        Bi = rand_csc(rng, 30, 20, 0.2)
+        offs = synth.partition_offsets(30, 3)
+    elif case == "one_col":
+        A = rand_csc(rng, 40, 1, 1.0)
+        Bi = rand_csc(rng, 1, 25, 0.7)
+        offs = synth.partition_offsets(1, 1)
+    elif case == "P_equals_k":
+        A = rand_csc(rng, 30, 12, 0.3)
+        Bi = rand_csc(rng, 12, 9, 0.3)
+        offs = synth.partition_offsets(12, 12)
+    else:
+        A = synth.from_triplets(20, 15, [], [], [])
+        Bi = rand_csc(rng, 15, 6, 0.4)
+        offs = synth.partition_offsets(15, 2)
+    check_local(A, Bi, offs, 2)
+
+
+def _bin_tunings():
+    return {
+        "default": None,
+        "all_dense": spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0),
+        "no_tiny": spg.tuning(tiny_max_flop=0),
+        "small_hash": spg.tuning(hash_max_flop=128, hash_max_nnz=128),
+        "mid_hash": spg.tuning(hash_max_flop=512, hash_max_nnz=256),
+    }
+
+
+@pytest.mark.parametrize("name", ["default", "all_dense", "no_tiny", "small_hash", "mid_hash"])
+def test_every_bin_gives_the_same_product(name):
+    """Bin thresholds move columns between kernels but never change C."""
+    A = synth.rmat(11, 16, 0.57, 0.19, 0.19, 0.05, seed=3)
+    tun = _bin_tunings()[name]
+    st, sbin, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 1), 64, tun=tun)
+    print(name, "sym bins", st["sym_bins"], "num bins", st["num_bins"], flush=True)
+    if name == "all_dense":
+        assert set(np.unique(nbin)) <= {0, 6}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rmat_scale12_both_dtypes(dtype):
+    A = synth.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, seed=3)
+    check_local(A, A, synth.partition_offsets(A.ncols, 1), 256, dtype=dtype)
+
+
+@pytest.mark.parametrize("b", [256, 64, 1024, 1])
+def test_er65536_partition0_block_sizes(b):
+    w = synth.workload("er65536_d16_p16")
+    offs = w["offsets"]
+    Bi = synth.column_slice(w["B"], int(offs[0]), int(offs[1]))
+    st, _, _ = check_local(w["A"], Bi, offs, b)
+    if b >= 64:
+        assert st["kt"] == 65536 and st["nnz_At"] == w["A"].nnz  # every block is hit
+
+
+@pytest.mark.parametrize("i", [1, 7, 15])
+def test_er65536_other_partitions(i):
+    w = synth.workload("er65536_d16_p16")
+    offs = w["offsets"]
+    Bi = synth.column_slice(w["B"], int(offs[i]), int(offs[i + 1]))
+    check_local(w["A"], Bi, offs, 256)
+
+
+def test_numeric_rerun_with_new_values():
+    """Same patterns, new values of A and B_i (gathered again into A~)."""
+    rng = np.random.default_rng(5)
+    A = synth.erdos_renyi(3000, 2000, 6, seed=11)
+    B = synth.erdos_renyi(2000, 700, 5, seed=12)
+    offs = synth.partition_offsets(2000, 4)
+    Ad, Bd = _dev(A, torch.float64), _dev(B, torch.float64)
+    with spg.Plan(Ad, Bd, offs, 16) as p:
+        p.symbolic()
+        p.numeric()
+        A2 = synth.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, rng.uniform(-2, 2, A.nnz))
+        B2 = synth.CSC(B.nrows, B.ncols, B.colptr, B.rowidx, rng.uniform(-2, 2, B.nnz))
+        rows, vals = p.numeric(torch.tensor(A2.vals, device="cuda"),
+                               torch.tensor(B2.vals, device="cuda"))
+        ref = oracle.spgemm(A2, B2)
+        assert np.array_equal(rows.cpu().numpy(), ref.rowidx)
+        assert_values(vals.cpu().numpy(), ref.vals, ref.absvals, True)
+
+
+def test_validation_on_device_rejects_unsorted_rows():
+    A = synth.erdos_renyi(100, 50, 4, seed=1)
+    bad = synth.CSC(A.nrows, A.ncols, A.colptr, A.rowidx.copy(), A.vals)
+    bad.rowidx[0], bad.rowidx[1] = bad.rowidx[1], bad.rowidx[0]
+    B = synth.erdos_renyi(50, 10, 3, seed=2)
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Plan(_dev(bad, torch.float64), _dev(B, torch.float64), None, 4,
+                 tuning=spg.tuning(validate=1))
+    assert e.value.code == -1
+    # the valid pair passes validation
+    with spg.Plan(_dev(A, torch.float64), _dev(B, torch.float64), None, 4,
+                  tuning=spg.tuning(validate=1)) as p:
+        p.run()
+
+
+def test_numeric_before_symbolic_is_a_state_error():
+    A = synth.erdos_renyi(100, 50, 4, seed=1)
+    B = synth.erdos_renyi(50, 10, 3, seed=2)
+    with spg.Plan(_dev(A, torch.float64), _dev(B, torch.float64)) as p:
+        lib = spg.load()
+        rc = lib.spgemm_numeric(p.handle, None, None, None, None)
+        assert rc == -5
+
+
+def test_workspace_limit_forces_enomem():
+    A = synth.erdos_renyi(100, 50, 4, seed=1)
+    B = synth.erdos_renyi(50, 10, 3, seed=2)
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Plan(_dev(A, torch.float64), _dev(B, torch.float64), None, 4,
+                 tuning=spg.tuning(workspace_limit=1024))
+    assert e.value.code == -2
+
+
+def test_plans_reuse_pooled_workspace():
+    """Many plan/destroy cycles on one stream stay correct (pooled blocks)."""
+    A = synth.erdos_renyi(2000, 2000, 8, seed=1)
+    ref = oracle.spgemm(A, A)
+    Ad = _dev(A, torch.float64)
+    for _ in range(5):
+        C = spg.spgemm(Ad, Ad, None, 64)
+        assert np.array_equal(C.rowidx.cpu().numpy(), ref.rowidx)
