@@ -68,11 +68,13 @@ typedef struct {
     int32_t tiny_max_flop;      /* columns with flop <= this (1..64) use one wave each */
     int32_t hash_max_flop;      /* symbolic LDS hash up to this flop (<= 4096), else bitmap */
     int32_t hash_max_nnz;       /* numeric LDS hash up to this nnz (<= 2048), else dense windows */
-    int32_t dense_window_rows;  /* rows per dense numeric window (power of 2, 1024..8192) */
+    int32_t dense_window;       /* most output rows one dense-bin pass holds in LDS
+                                   (0 = as many as LDS allows, else a power of 2 >= 32) */
     int32_t validate;           /* 1: check the CSC invariants of A and B_i on the device */
     int32_t own_partition;      /* >= 0: B_i belongs to this partition of A ... */
     int32_t own_partition_whole;/* ... and 1 selects that partition's nonzero columns whole */
-    int32_t reserved;
+    int32_t medium_kernel;      /* medium numeric bins: 0 = choose by m, 1 = LDS hash and
+                                   sort, 2 = LDS bitmap and rank */
     int64_t workspace_limit;    /* bytes of device workspace a plan may take; 0 = no limit */
 } spgemm_tuning;
 

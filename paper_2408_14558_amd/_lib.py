@@ -40,9 +40,9 @@ class Csc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tiny_max_flop", ctypes.c_int32), ("hash_max_flop", ctypes.c_int32),
-                ("hash_max_nnz", ctypes.c_int32), ("dense_window_rows", ctypes.c_int32),
+                ("hash_max_nnz", ctypes.c_int32), ("dense_window", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("own_partition", ctypes.c_int32),
-                ("own_partition_whole", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("own_partition_whole", ctypes.c_int32), ("medium_kernel", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64)]
 
 

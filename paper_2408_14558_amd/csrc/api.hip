@@ -175,6 +175,10 @@ static int check_tuning(const spgemm_tuning &t) {
     if (t.hash_max_nnz < 0 || t.hash_max_nnz > kNumTable[3] / 2)
         return fail(SPGEMM_EINVAL, "hash_max_nnz must lie in [0, 2048]");
     if (t.workspace_limit < 0) return fail(SPGEMM_EINVAL, "workspace_limit must be >= 0");
+    if (t.dense_window != 0 && (t.dense_window < 32 || (t.dense_window & (t.dense_window - 1))))
+        return fail(SPGEMM_EINVAL, "dense_window must be 0 or a power of two >= 32");
+    if (t.medium_kernel < 0 || t.medium_kernel > 2)
+        return fail(SPGEMM_EINVAL, "medium_kernel must be 0, 1 or 2");
     return SPGEMM_OK;
 }
 
@@ -202,7 +206,8 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->tiny_max_flop = 64;
     t->hash_max_flop = 4096;
     t->hash_max_nnz = 2048;
-    t->dense_window_rows = 0;
+    t->dense_window = 0;
+    t->medium_kernel = 0;
     t->validate = 0;
     t->own_partition = -1;
     t->own_partition_whole = 0;

@@ -152,29 +152,40 @@ __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by ONE thread of the tile.  Returns the exclusive prefix of `tile`
-// and publishes its inclusive prefix.
+// Called by all 64 lanes of ONE wave of the tile (the same wave for the
+// whole call).  Returns, in every lane, the exclusive prefix of `tile` and
+// publishes its inclusive prefix.  The look-back reads 64 predecessor
+// states per round trip: it sums the aggregates of the closest tiles up to
+// and including the first one that already holds its inclusive prefix.
 __device__ __forceinline__ long long chained_prefix(uint64_t *status, long long tile, bool head,
                                                     long long aggregate) {
+    const int lane = lane_id();
     if (head) {
-        status_store(&status[tile], kStInc | (uint64_t)aggregate);
+        if (lane == 0) status_store(&status[tile], kStInc | (uint64_t)aggregate);
         return 0;
     }
-    status_store(&status[tile], kStAgg | (uint64_t)aggregate);
+    if (lane == 0) status_store(&status[tile], kStAgg | (uint64_t)aggregate);
     long long prefix = 0;
-    long long j = tile - 1;
+    long long base = tile - 1;
     while (true) {
-        uint64_t s = status_load(&status[j]);
-        uint64_t st = s & kStMask;
-        if (st == 0) {
+        const long long j = base - lane;
+        // there is always an inclusive tile at or after index 0 (a head)
+        const uint64_t s = j >= 0 ? status_load(&status[j]) : kStInc;
+        const uint64_t st = s & kStMask;
+        const uint64_t inc = __ballot(st == kStInc);
+        const uint64_t notready = __ballot(st == 0);
+        const int first = inc ? (__ffsll((unsigned long long)inc) - 1) : kWave;
+        const uint64_t needed = first == kWave ? ~0ull : ((2ull << first) - 1ull);
+        if (notready & needed) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        prefix += (long long)(s & kValMask);
-        if (st == kStInc) break;
-        --j;
+        const long long v = lane <= first && j >= 0 ? (long long)(s & kValMask) : 0;
+        prefix += wave_sum(v);
+        if (first < kWave) break;
+        base -= kWave;
     }
-    status_store(&status[tile], kStInc | (uint64_t)(prefix + aggregate));
+    if (lane == 0) status_store(&status[tile], kStInc | (uint64_t)(prefix + aggregate));
     return prefix;
 }
 

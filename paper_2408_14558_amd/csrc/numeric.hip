@@ -36,6 +36,27 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__re
     num_dense_column<V>(a, list[w], bits, wpre, vals, VC, S);
 }
 
+template <int G, typename V>
+__global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ list, int count,
+                                                  NumArgs<V> a) {
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ NumBitmapStatic<G, V> S;
+    if ((int)blockIdx.x >= count) return;
+    const int nw = (int)((a.m + 31) >> 5);
+    uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
+    uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
+    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
+    num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, S);
+}
+
+// Bitmap instead of hash for a medium bin when the bitmap is not much
+// larger than the bin's table and fits next to the values.
+static bool use_bitmap(int64_t m, int table, size_t vsize, size_t *lds) {
+    const size_t nw = (size_t)((m + 31) / 32);
+    *lds = ((nw * 6 + 15) & ~(size_t)15) + (size_t)(table / 2) * vsize;
+    return nw <= (size_t)8 * table && *lds <= 96 * 1024;
+}
+
 // Dynamic LDS of the dense kernel and the window size it allows.
 size_t dense_lds_bytes(int64_t m, size_t vsize, int *VC_out) {
     const size_t nw = (size_t)((m + 31) / 32);
@@ -53,6 +74,16 @@ template <int T, int G, typename V>
 static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     const int cnt = p.num_count[bin];
     if (cnt <= 0) return SPGEMM_OK;
+    size_t lds;
+    const bool fits = use_bitmap(p.m, T, sizeof(V), &lds);
+    const int mk = p.tun.medium_kernel;
+    if ((mk == 0 && fits) || (mk == 2 && lds <= 96 * 1024)) {
+        constexpr int GB = T <= 512 ? 128 : 256;
+        hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(cnt), dim3(GB), lds, p.stream,
+                           p.num_list + (int64_t)bin * p.n, cnt, a);
+        SPG_LAUNCHED("k_num_bitmap<" + std::to_string(GB) + ">");
+        return SPGEMM_OK;
+    }
     constexpr int CPW = G < 256 ? 256 / G : 1;
     constexpr int threads = G < 256 ? 256 : G;
     const unsigned grid = (unsigned)((cnt + CPW - 1) / CPW);
@@ -84,7 +115,11 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
             return fail(SPGEMM_EUNSUPPORTED,
                         "columns with more rows than the largest hash bin need m <= 262144");
         int VC;
-        const size_t lds = dense_lds_bytes(p.m, sizeof(V), &VC);
+        size_t lds = dense_lds_bytes(p.m, sizeof(V), &VC);
+        if (p.tun.dense_window > 0 && p.tun.dense_window < VC) {
+            lds -= (size_t)(VC - p.tun.dense_window) * sizeof(V);
+            VC = p.tun.dense_window;
+        }
         hipLaunchKernelGGL(k_num_dense<V>, dim3(p.num_count[kBinDense]), dim3(kDenseThreads), lds,
                            p.stream, list(kBinDense), p.num_count[kBinDense], a, VC);
         SPG_LAUNCHED("k_num_dense (dynamic LDS " + std::to_string(lds) + " B)");

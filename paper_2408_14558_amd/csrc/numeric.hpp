@@ -142,6 +142,60 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     group_sync<G>();
 }
 
+// --- bitmap: medium columns when m is small --------------------------------
+// A bitmap of all m rows plus per-word prefix counts in LDS give every row
+// of the column its final position (its rank), so values are accumulated at
+// that position and no sort is needed.  Two passes over the terms: rows,
+// then values.  LDS (dynamic): bits[nw] u32 | wpre[nw] u16 | vals[vcap].
+template <int G, typename V>
+struct NumBitmapStatic {
+    EntryStage<G, V> st;
+    int red[G / kWave + 2];
+};
+
+template <int G, typename V>
+__device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
+                                                  uint16_t *wpre, V *vals,
+                                                  NumBitmapStatic<G, V> &S) {
+    const int gt = threadIdx.x;
+    const int nw = (int)((a.m + 31) >> 5);
+    const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
+    for (int i = gt; i < nw; i += G) bits[i] = 0u;
+    __syncthreads();
+    for_each_term<G, V>(q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
+                        [&](int64_t p, V) {
+                            const int32_t r = a.At_rowidx[p];
+                            atomicOr(&bits[r >> 5], 1u << (r & 31));
+                        });
+    const int per = (nw + G - 1) / G;
+    const int w0 = gt * per, w1 = min(nw, w0 + per);
+    int c = 0;
+    for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+    int total;
+    int run = group_excl_scan<G>(c, S.red, &total);
+    const int64_t o = a.Ccolptr[j];
+    for (int w = w0; w < w1; ++w) {
+        wpre[w] = (uint16_t)run;
+        uint32_t b = bits[w];
+        while (b) {
+            a.Crow[o + run] = (w << 5) + __ffs(b) - 1;
+            ++run;
+            b &= b - 1;
+        }
+    }
+    for (int i = gt; i < total; i += G) vals[i] = V(0);
+    __syncthreads();
+    for_each_term<G, V>(q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
+                        [&](int64_t p, V bv) {
+                            const int32_t r = a.At_rowidx[p];
+                            const uint32_t w = bits[r >> 5];
+                            const int rk = wpre[r >> 5] + __popc(w & ((1u << (r & 31)) - 1u));
+                            lds_atomic_add(&vals[rk], a.At_vals[p] * bv);
+                        });
+    for (int i = gt; i < total; i += G) a.Cval[o + i] = vals[i];
+    __syncthreads();
+}
+
 // --- dense: bitmap of all m rows + rank windows -----------------------------
 // LDS layout (dynamic): bits[nw] | wpre[nw] | vals[VC]
 template <typename V>

@@ -67,9 +67,13 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
     }
     int total;
     int excl = group_excl_scan<kScanThreads>(cnt, s_tmp, &total);
-    if (tid == 0) s_prefix = chained_prefix(status, t, d.head != 0, total);
+    if (tid < kWave) {
+        const long long pre = chained_prefix(status, t, d.head != 0, total);
+        if (tid == 0) s_prefix = pre;
+    }
     __syncthreads();
     long long rank = s_prefix + excl;
+    const long long part_last = d.last ? s_prefix + total - 1 : -1;
     const int64_t base = group_base[d.part];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
@@ -80,8 +84,9 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
             const int64_t g = base + rank / b;
             gid[c] = (int32_t)g;
             if (H[c]) hit[g] = 1;
-            if (rank % b == 0) gfirst[g] = (int32_t)c;
-            atomicMax(&glast[g], (int32_t)c);
+            const long long r = rank % b;
+            if (r == 0) gfirst[g] = (int32_t)c;
+            if (r == b - 1 || rank == part_last) glast[g] = (int32_t)c;
             ++rank;
         } else {
             gid[c] = -1;
@@ -139,8 +144,13 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
     long long totn;
     int exc = group_excl_scan<kScanThreads>(cnt, s_tmp, &totc);
     long long exn = group_excl_scan64<kScanThreads>(nnz, s_tmp64, &totn);
-    if (tid == 0) s_pc = chained_prefix(st_cnt, t, t == 0, totc);
-    if (tid == kWave) s_pn = chained_prefix(st_nnz, t, t == 0, totn);
+    if (tid < kWave) {
+        const long long pre = chained_prefix(st_cnt, t, t == 0, totc);
+        if (tid == 0) s_pc = pre;
+    } else if (tid < 2 * kWave) {
+        const long long pre = chained_prefix(st_nnz, t, t == 0, totn);
+        if (tid == kWave) s_pn = pre;
+    }
     __syncthreads();
     long long j = s_pc + exc;
     long long pos = s_pn + exn;
@@ -256,9 +266,13 @@ __global__ void k_validate(const int64_t *__restrict__ colptr, const int32_t *__
 }
 
 // Writes (first, last) of every chosen group in group order (Alg. 2's R).
+// A group's last column is recorded by the plan when its rank closes the
+// group; a partition's final, shorter group whose last column was not seen
+// by the partition's last tile is completed here by walking its columns.
 __global__ __launch_bounds__(1024) void k_export_blocks(const uint8_t *__restrict__ hit,
                                                         const int32_t *__restrict__ gfirst,
                                                         const int32_t *__restrict__ glast,
+                                                        const int32_t *__restrict__ gid, int64_t k,
                                                         int64_t G, int64_t *__restrict__ blocks) {
     __shared__ int s_tmp[1024 / kWave + 1];
     long long base = 0;
@@ -268,8 +282,18 @@ __global__ __launch_bounds__(1024) void k_export_blocks(const uint8_t *__restric
         int total;
         const int excl = group_excl_scan<1024>(h, s_tmp, &total);
         if (h) {
-            blocks[2 * (base + excl)] = gfirst[g];
-            blocks[2 * (base + excl) + 1] = glast[g];
+            const int32_t first = gfirst[g];
+            int32_t last = glast[g];
+            if (last < 0) {
+                last = first;
+                for (int64_t c = first + 1; c < k; ++c) {
+                    const int32_t gg = gid[c];
+                    if (gg == (int32_t)g) last = (int32_t)c;
+                    else if (gg != -1) break;
+                }
+            }
+            blocks[2 * (base + excl)] = first;
+            blocks[2 * (base + excl) + 1] = last;
         }
         base += total;
     }
@@ -344,7 +368,7 @@ int launch_gather_values(Plan &p, const void *Avals) {
 int launch_export_blocks(Plan &p, int64_t *blocks) {
     if (p.G == 0) return SPGEMM_OK;
     hipLaunchKernelGGL(k_export_blocks, dim3(1), dim3(1024), 0, p.stream, p.hit, p.gfirst,
-                       p.glast, p.G, blocks);
+                       p.glast, p.gid, p.k, p.G, blocks);
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
 }

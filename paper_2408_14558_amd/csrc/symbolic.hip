@@ -43,10 +43,12 @@ __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const
     }
 }
 
-// Sparse flops of every column of B_i and its symbolic bin.  A group of 16
-// lanes walks one column's entries; a workgroup covers 256 columns.
-constexpr int kFlopCols = 256;
-__global__ __launch_bounds__(256) void k_flop_bin(
+// Sparse flops of every column of B_i and its symbolic bin.  One thread
+// per column walks short columns (independent loads, unrolled); columns with
+// more than kFlopShort entries are summed by a whole wave afterwards.
+constexpr int kFlopCols = 128;
+constexpr int kFlopShort = 64;
+__global__ __launch_bounds__(kFlopCols) void k_flop_bin(
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
@@ -54,8 +56,11 @@ __global__ __launch_bounds__(256) void k_flop_bin(
     DevCounters *__restrict__ ctr) {
     __shared__ int s_bin[kFlopCols];
     __shared__ int s_lpos[kFlopCols];
+    __shared__ int s_long[kFlopCols];
+    __shared__ long long s_f[kFlopCols];
     __shared__ int s_cnt[kNumBins];
     __shared__ int s_base[kNumBins];
+    __shared__ int s_nlong;
     __shared__ long long s_flops;
     const int tid = threadIdx.x;
     {
@@ -64,35 +69,52 @@ __global__ __launch_bounds__(256) void k_flop_bin(
             status[s] = 0;
     }
     if (tid < kNumBins) s_cnt[tid] = 0;
-    if (tid == 0) s_flops = 0;
+    if (tid == 0) {
+        s_flops = 0;
+        s_nlong = 0;
+    }
     __syncthreads();
-    const int sub = tid & 15, grp = tid >> 4;
     const int64_t j0 = (int64_t)blockIdx.x * kFlopCols;
     const int nloc = (int)min<int64_t>(kFlopCols, n - j0);
-    long long my_flops = 0;
-    for (int r = 0; r < kFlopCols / 16; ++r) {
-        const int lc = grp + 16 * r;
-        const int64_t j = j0 + lc;
-        long long acc = 0;
-        if (lc < nloc) {
-            const int64_t q1 = Bcolptr[j + 1];
-            for (int64_t q = Bcolptr[j] + sub; q < q1; q += 16) {
+    const int64_t j = j0 + tid;
+    if (tid < nloc) {
+        const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1];
+        if (q1 - q0 <= kFlopShort) {
+            long long acc = 0;
+#pragma unroll 4
+            for (int64_t q = q0; q < q1; ++q) {
                 const int32_t jt = map[Browidx[q]];
                 if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
             }
-        }
-        acc = wave_sum<16>(acc);
-        if (lc < nloc && sub == 0) {
-            flop[j] = acc;
-            const int b = sym_bin_of(acc, th);
-            sym_bin[j] = b;
-            s_bin[lc] = b;
-            s_lpos[lc] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
-            if (b == kBinEmpty) Ccount[j] = 0;
-            my_flops += acc;
+            s_f[tid] = acc;
+        } else {
+            s_long[atomicAdd(&s_nlong, 1)] = tid;
         }
     }
-    if (my_flops) atomic_add_i64(&s_flops, my_flops);
+    __syncthreads();
+    const int wv = tid / kWave, lane = lane_id();
+    for (int li = wv; li < s_nlong; li += kFlopCols / kWave) {
+        const int t = s_long[li];
+        const int64_t q1 = Bcolptr[j0 + t + 1];
+        long long acc = 0;
+        for (int64_t q = Bcolptr[j0 + t] + lane; q < q1; q += kWave) {
+            const int32_t jt = map[Browidx[q]];
+            if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) s_f[t] = acc;
+    }
+    __syncthreads();
+    if (tid < nloc) {
+        const long long f = s_f[tid];
+        flop[j] = f;
+        const int b = sym_bin_of(f, th);
+        sym_bin[j] = b;
+        s_bin[tid] = b;
+        s_lpos[tid] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
+        if (b == kBinEmpty) Ccount[j] = 0;
+        if (f) atomic_add_i64(&s_flops, f);
+    }
     __syncthreads();
     if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops, s_flops);
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
@@ -239,7 +261,10 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     }
     long long total;
     long long excl = group_excl_scan64<kScanThreads>(sum, s_tmp64, &total);
-    if (tid == 0) s_prefix = chained_prefix(status, t, t == 0, total);
+    if (tid < kWave) {
+        const long long pre = chained_prefix(status, t, t == 0, total);
+        if (tid == 0) s_prefix = pre;
+    }
     __syncthreads();
     long long run = s_prefix + excl;
 #pragma unroll
@@ -261,7 +286,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
 int launch_flop_bin(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     const unsigned g = (unsigned)((p.n + kFlopCols - 1) / kFlopCols);
-    hipLaunchKernelGGL(k_flop_bin, dim3(g), dim3(256), 0, p.stream, p.n, p.Bcolptr, p.Browidx,
+    hipLaunchKernelGGL(k_flop_bin, dim3(g), dim3(kFlopCols), 0, p.stream, p.n, p.Bcolptr, p.Browidx,
                        p.map, p.At_colptr, p.th, p.flop, p.sym_bin, p.sym_list, p.C_colptr,
                        p.st_colptr, p.n_col_tiles, p.ctr);
     SPG_HIP(hipGetLastError());

@@ -124,13 +124,18 @@ def _bin_tunings():
     return {
         "default": None,
         "all_dense": spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0),
+        "all_dense_windows": spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0,
+                                        dense_window=32),
         "no_tiny": spg.tuning(tiny_max_flop=0),
         "small_hash": spg.tuning(hash_max_flop=128, hash_max_nnz=128),
         "mid_hash": spg.tuning(hash_max_flop=512, hash_max_nnz=256),
+        "force_hash": spg.tuning(tiny_max_flop=0, medium_kernel=1),
+        "force_bitmap": spg.tuning(tiny_max_flop=0, medium_kernel=2),
     }
 
 
-@pytest.mark.parametrize("name", ["default", "all_dense", "no_tiny", "small_hash", "mid_hash"])
+@pytest.mark.parametrize("name", ["default", "all_dense", "all_dense_windows", "no_tiny",
+                                  "small_hash", "mid_hash", "force_hash", "force_bitmap"])
 def test_every_bin_gives_the_same_product(name):
     """Bin thresholds move columns between kernels but never change C."""
     A = synth.rmat(11, 16, 0.57, 0.19, 0.19, 0.05, seed=3)
@@ -139,6 +144,36 @@ def test_every_bin_gives_the_same_product(name):
     print(name, "sym bins", st["sym_bins"], "num bins", st["num_bins"], flush=True)
     if name == "all_dense":
         assert set(np.unique(nbin)) <= {0, 6}
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_er_medium_bins_hash_and_bitmap(kernel):
+    """ER columns with ~256 and ~1000 entries through both medium kernels."""
+    A = synth.erdos_renyi(20000, 20000, 16, seed=21)
+    B = synth.erdos_renyi(20000, 300, 16, seed=22)
+    B2 = synth.erdos_renyi(20000, 200, 64, seed=23)
+    for Bi in (B, B2):
+        check_local(A, Bi, synth.partition_offsets(20000, 4), 128,
+                    tun=spg.tuning(medium_kernel=kernel))
+
+
+def test_dense_windows_on_big_columns():
+    """Dense-bin columns split into many rank windows (window of 64 rows)."""
+    A = synth.rmat(13, 16, 0.57, 0.19, 0.19, 0.05, seed=4)
+    st, _, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 2), 256,
+                              tun=spg.tuning(dense_window=64, hash_max_nnz=128))
+    assert (nbin == 6).sum() > 0
+
+
+def test_export_of_partial_group_before_empty_tail():
+    """A partition whose last tile holds no nonzero column: its final, short
+    group must still report its last column."""
+    rng = np.random.default_rng(11)
+    k = 3000
+    A = rand_csc(rng, 40, k, 0.05, empty_cols=tuple(range(2000, 3000)))
+    Bi = rand_csc(rng, k, 30, 0.01)
+    check_local(A, Bi, synth.partition_offsets(k, 1), 300)
+    check_local(A, Bi, synth.partition_offsets(k, 2), 7)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
