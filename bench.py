@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="er65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes, 5 times "
+                         "(reference for HBM byte counters), and print its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -108,6 +111,21 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_ref:
+        src = torch.empty(args.copy_ref // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        dst.copy_(src)
+        ev[0].record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
+        print(json.dumps({"copy_ref_bytes": src.numel() * 8, "ms": ms,
+                          "GBps_read_plus_write": 2 * src.numel() * 8 / (ms * 1e-3) / 1e9}))
+        return
 
     import paper_2408_14558_amd as spg
 

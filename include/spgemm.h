@@ -65,7 +65,7 @@ typedef struct {
  * a column, never the result.
  */
 typedef struct {
-    int32_t tiny_max_flop;      /* columns with flop <= this (1..64) use one wave each */
+    int32_t tiny_max_flop;      /* columns with flop <= this (0..512) use one wave each */
     int32_t hash_max_flop;      /* symbolic LDS hash up to this flop (<= 4096), else bitmap */
     int32_t hash_max_nnz;       /* numeric LDS hash up to this nnz (<= 2048), else dense windows */
     int32_t dense_window;       /* most output rows one dense-bin pass holds in LDS

@@ -168,8 +168,8 @@ static void thresholds_from(const spgemm_tuning &t, Thresholds &th) {
 }
 
 static int check_tuning(const spgemm_tuning &t) {
-    if (t.tiny_max_flop < 0 || t.tiny_max_flop > 64)
-        return fail(SPGEMM_EINVAL, "tiny_max_flop must lie in [0, 64]");
+    if (t.tiny_max_flop < 0 || t.tiny_max_flop > 512)
+        return fail(SPGEMM_EINVAL, "tiny_max_flop must lie in [0, 512]");
     if (t.hash_max_flop < 0 || t.hash_max_flop > kSymTable[3] / 2)
         return fail(SPGEMM_EINVAL, "hash_max_flop must lie in [0, 4096]");
     if (t.hash_max_nnz < 0 || t.hash_max_nnz > kNumTable[3] / 2)
@@ -203,7 +203,7 @@ const char *spgemm_version(void) { return "spgemm-mi355x 0.1 (gfx950)"; }
 int spgemm_default_tuning(spgemm_tuning *t) {
     if (!t) return fail(SPGEMM_EINVAL, "tuning is NULL");
     std::memset(t, 0, sizeof(*t));
-    t->tiny_max_flop = 64;
+    t->tiny_max_flop = 256;
     t->hash_max_flop = 4096;
     t->hash_max_nnz = 2048;
     t->dense_window = 0;
@@ -249,9 +249,11 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     auto *p = new (std::nothrow) spgemm_plan_s();
     if (!p) return fail(SPGEMM_ENOMEM, "plan allocation failed");
     Plan &pl = *p;
-    if (hipGetDevice(&pl.device) != hipSuccess) {
+    if (hipGetDevice(&pl.device) != hipSuccess ||
+        hipDeviceGetAttribute(&pl.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              pl.device) != hipSuccess) {
         delete p;
-        return fail(SPGEMM_EHIP, "hipGetDevice failed");
+        return fail(SPGEMM_EHIP, "hipGetDevice / hipDeviceGetAttribute failed");
     }
     pl.stream = (hipStream_t)stream;
     pl.dtype = dtype;
@@ -307,6 +309,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_glast = cv.take<int32_t>(pl.G);
     const size_t o_gbase = cv.take<int64_t>(P + 1);
     const size_t o_tiles = cv.take<RankTile>(pl.n_rank_tiles);
+    // the upload copies [group_base .. tiles] as one block: same relative layout
+    const size_t up_gap = o_tiles - o_gbase;
     const size_t o_map = cv.take<int32_t>(pl.k);
     const size_t o_colid = cv.take<int32_t>(pl.k);
     const size_t o_Atc = cv.take<int64_t>(pl.k + 1);
@@ -320,6 +324,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_nbin = cv.take<int32_t>(pl.n);
     const size_t o_slist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
+    const size_t o_cur = cv.take<int32_t>(pl.nnzB);
     const size_t ws_bytes = cv.off;
     if (tun.workspace_limit > 0 && (int64_t)ws_bytes > tun.workspace_limit) {
         delete p;
@@ -329,8 +334,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     Carver ch;
     const size_t h_ctr = ch.take<DevCounters>(1);
     const size_t h_gbase = ch.take<int64_t>(P + 1);
-    const size_t h_tiles = ch.take<RankTile>(pl.n_rank_tiles);
-    const size_t pinned_bytes = ch.off;
+    const size_t h_tiles = h_gbase + up_gap;
+    const size_t pinned_bytes = h_tiles + sizeof(RankTile) * (size_t)pl.n_rank_tiles;
 
     if ((rc = pool_get(ws_bytes, false, pl.device, pl.stream, &pl.ws, &pl.ws_bytes))) {
         delete p;
@@ -364,6 +369,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.num_bin = (int32_t *)(w + o_nbin);
     pl.sym_list = (int32_t *)(w + o_slist);
     pl.num_list = (int32_t *)(w + o_nlist);
+    pl.cursor = (int32_t *)(w + o_cur);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);
     std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
@@ -376,11 +382,10 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
         delete p;
         return code;
     };
-    hipError_t e = hipMemcpyAsync(pl.group_base, h + h_gbase, sizeof(int64_t) * (P + 1),
-                                  hipMemcpyHostToDevice, pl.stream);
-    if (e == hipSuccess && !tiles.empty())
-        e = hipMemcpyAsync(pl.rank_tiles, h + h_tiles, sizeof(RankTile) * tiles.size(),
-                           hipMemcpyHostToDevice, pl.stream);
+    // group bases and rank tiles sit at the same offsets in both blocks: one copy
+    const size_t up_bytes = (h_tiles - h_gbase) + sizeof(RankTile) * tiles.size();
+    hipError_t e = hipMemcpyAsync(pl.group_base, h + h_gbase, up_bytes, hipMemcpyHostToDevice,
+                                  pl.stream);
     if (e != hipSuccess) return cleanup(fail(SPGEMM_EHIP, std::string("hipMemcpyAsync: ") +
                                                               hipGetErrorString(e)));
     if (tun.validate) {
@@ -489,19 +494,20 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     }
     // reset the symbolic counters: colptr ticket, flops .. num_count
     SPG_HIP(hipMemsetAsync(&p.ctr->tickets[kTkColptr], 0, sizeof(unsigned long long), p.stream));
-    SPG_HIP(hipMemsetAsync(&p.ctr->flops, 0,
-                           offsetof(DevCounters, error) - offsetof(DevCounters, flops), p.stream));
+    SPG_HIP(hipMemsetAsync(&p.ctr->nnzC, 0, sizeof(long long), p.stream));
+    SPG_HIP(hipMemsetAsync(&p.ctr->flops, 0, sizeof(DevCounters) - offsetof(DevCounters, flops),
+                           p.stream));
     if ((rc = launch_flop_bin(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));
-    for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b];
+    for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
     if ((rc = launch_symbolic_bins(p))) return rc;
     if ((rc = launch_colptr_scan(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));
     p.nnzC = p.hctr->nnzC;
-    p.flops = p.hctr->flops;
-    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hctr->num_count[b];
+    p.flops = p.hctr->flops.v;
+    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hctr->num_count[b].v;
     p.symbolic_done = true;
     *nnzC = p.nnzC;
     return SPGEMM_OK;

@@ -16,7 +16,7 @@ namespace spg {
 // numeric phase by flops (tiny) and by the exact nnz of the column.
 enum Bin : int {
     kBinEmpty = 0,
-    kBinTiny = 1,  // flop <= tiny_max_flop (<= 64): one wave, terms in registers
+    kBinTiny = 1,  // flop <= tiny_max_flop (<= 512): one wave, terms in registers
     kBinH0 = 2,    // LDS hash, smallest table
     kBinH1 = 3,
     kBinH2 = 4,
@@ -48,7 +48,18 @@ struct RankTile {
     int32_t last;   // 1: last tile of its partition
 };
 
-// Counters kept in device memory; the host copies the block from h_count on.
+// A counter alone on its 128-byte line, so atomics on different counters
+// do not serialise on one cache line.
+struct alignas(128) LineInt {
+    int v;
+    int pad[31];
+};
+struct alignas(128) LineI64 {
+    long long v;
+    long long pad[15];
+};
+
+// Counters kept in device memory; the host copies the whole block.
 struct DevCounters {
     unsigned long long tickets[8];  // chained-scan tile tickets
     long long h_count;
@@ -57,12 +68,12 @@ struct DevCounters {
     long long M;
     long long kt;
     long long nnz_At;
-    long long flops;
     long long nnzC;
-    int sym_count[kNumBins];
-    int num_count[kNumBins];
     int error;  // bit 0: A malformed, bit 1: B malformed
-    int pad[7];
+    int pad0;
+    LineI64 flops;
+    LineInt sym_count[kNumBins];
+    LineInt num_count[kNumBins];
 };
 
 enum Ticket { kTkRank = 0, kTkSelect = 1, kTkColptr = 2, kTkExport = 3 };
@@ -128,6 +139,7 @@ struct Plan {
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
+    int lds_max = 65536;          // LDS bytes one workgroup may use on this device
 
     // host view of the counters (inside the pinned block)
     DevCounters *hctr = nullptr;

@@ -3,12 +3,19 @@
 
 namespace spg {
 
+// Up to 64*8 terms per column: one wave per column, four columns per
+// workgroup, 64*8 LDS slots per wave for merging equal rows.
+constexpr int kWaveSortMax = 8 * kWave;
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_num_tiny(const int32_t *__restrict__ list, int count,
                                                   NumArgs<V> a) {
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ int s_rows[4][kWaveSortMax];
+    __shared__ V s_vals[4][kWaveSortMax];
+    const int wv = threadIdx.x >> 6;
+    const int w = blockIdx.x * 4 + wv;
     if (w >= count) return;
-    num_tiny_column<V>(a, list[w]);
+    num_wave_dispatch<V>(a, list[w], s_rows[wv], s_vals[wv]);
 }
 
 template <int T, int G, typename V>
@@ -31,8 +38,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__re
     if (w >= count) return;
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
-    int *wpre = reinterpret_cast<int *>(bits + nw);
-    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 8 + 15) & ~(size_t)15));
+    uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
+    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
     num_dense_column<V>(a, list[w], bits, wpre, vals, VC, S);
 }
 
@@ -57,13 +64,15 @@ static bool use_bitmap(int64_t m, int table, size_t vsize, size_t *lds) {
     return nw <= (size_t)8 * table && *lds <= 96 * 1024;
 }
 
-// Dynamic LDS of the dense kernel and the window size it allows.
-size_t dense_lds_bytes(int64_t m, size_t vsize, int *VC_out) {
+// Dynamic LDS of the dense kernel and the number of values (a power of
+// two) one rank window holds: whatever the device's per-workgroup LDS leaves
+// after the bitmap, the word ranks and the kernel's static part.
+size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
     const size_t nw = (size_t)((m + 31) / 32);
-    const size_t head = (nw * 8 + 15) & ~(size_t)15;
-    // keep the whole workgroup under 144 KiB: static part ~ 24 KiB
-    const size_t budget = 120 * 1024;
-    size_t vc_bytes = budget > head ? budget - head : 0;
+    const size_t head = (nw * 6 + 15) & ~(size_t)15;
+    const size_t stat = vsize == 8 ? sizeof(NumDenseStatic<double>) : sizeof(NumDenseStatic<float>);
+    const size_t budget = (size_t)lds_max > stat + 1024 ? (size_t)lds_max - stat - 1024 : 0;
+    const size_t vc_bytes = budget > head ? budget - head : 0;
     int VC = 1;
     while ((size_t)(VC * 2) * vsize <= vc_bytes && VC < (1 << 16)) VC *= 2;
     *VC_out = VC;
@@ -95,8 +104,9 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
 
 template <typename V>
 static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
-    NumArgs<V> a{p.m,         p.Bcolptr, p.Browidx,  Bvals, p.map,
-                 p.At_colptr, p.At_rowidx, (const V *)p.At_vals, p.C_colptr, Crow, Cval};
+    NumArgs<V> a{p.m,         p.Bcolptr,  p.Browidx,           Bvals,      p.map,
+                 p.At_colptr, p.At_rowidx, (const V *)p.At_vals, p.C_colptr, Crow,
+                 Cval,        p.flop,      p.cursor};
     const int64_t n = p.n;
     auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
     if (p.num_count[kBinTiny] > 0)
@@ -115,7 +125,7 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
             return fail(SPGEMM_EUNSUPPORTED,
                         "columns with more rows than the largest hash bin need m <= 262144");
         int VC;
-        size_t lds = dense_lds_bytes(p.m, sizeof(V), &VC);
+        size_t lds = dense_lds_bytes(p.m, sizeof(V), p.lds_max, &VC);
         if (p.tun.dense_window > 0 && p.tun.dense_window < VC) {
             lds -= (size_t)(VC - p.tun.dense_window) * sizeof(V);
             VC = p.tun.dense_window;

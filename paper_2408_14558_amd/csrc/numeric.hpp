@@ -22,37 +22,75 @@ struct NumArgs {
     const int64_t *Ccolptr;
     int32_t *Crow;
     V *Cval;
+    const int64_t *flop;  // sparse flops per column (picks the wave-sort width)
+    int32_t *cursor;      // nnz(B_i) scratch for windowed dense columns
 };
 
-// --- tiny: <= 64 terms, one wave ------------------------------------------
-template <typename V>
-__device__ __forceinline__ void num_tiny_column(const NumArgs<V> &a, int32_t j) {
-    int64_t p;
-    V bv;
-    tiny_terms<V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.Browidx, a.Bvals, a.map, a.At_colptr, p, bv);
-    int key = kNoRow;
-    V val = V(0);
-    if (p >= 0) {
-        key = a.At_rowidx[p];
-        val = a.At_vals[p] * bv;
-    }
-    wave_sort_pairs(key, val);
-    const int lane = lane_id();
-    // sum runs of equal rows (rows are sorted, so runs are contiguous)
+// --- wave sort: <= 64*E terms, one wave, registers ---------------------------
+// Terms are gathered into registers, sorted by row across the wave, equal
+// rows are merged by LDS atomics at their output slot, and the column is
+// written out coalesced.  s_rows/s_vals: this wave's 64*E LDS slots.
+template <int E, typename V>
+__device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, int *s_rows,
+                                                V *s_vals) {
+    int64_t p[E];
+    V bv[E];
+    wave_terms<E, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.Browidx, a.Bvals, a.map, a.At_colptr, p,
+                     bv);
+    int key[E];
+    V val[E];
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int ok = __shfl_down(key, d);
-        const V ov = __shfl_down(val, d);
-        if (lane + d < kWave && ok == key) val += ov;
+    for (int r = 0; r < E; ++r) {
+        key[r] = kNoRow;
+        val[r] = V(0);
+        if (p[r] >= 0) {
+            key[r] = a.At_rowidx[p[r]];
+            val[r] = a.At_vals[p[r]] * bv[r];
+        }
     }
-    const int prev = __shfl_up(key, 1);
-    const bool head = key != kNoRow && (lane == 0 || prev != key);
-    const uint64_t mask = __ballot(head);
-    if (head) {
-        const int64_t o = a.Ccolptr[j] + lanes_below(mask);
-        a.Crow[o] = key;
-        a.Cval[o] = val;
+    wave_sort<E, true, V>(key, val);
+    const int lane = lane_id();
+    const int prev_last = __shfl_up(key[E - 1], 1);
+    bool hd[E];
+    int nh = 0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int prev = r == 0 ? prev_last : key[r - 1];
+        hd[r] = key[r] != kNoRow && ((r == 0 && lane == 0) || key[r] != prev);
+        nh += hd[r];
     }
+    const int incl = wave_incl_scan(nh);
+    const int total = __shfl(incl, kWave - 1);
+    for (int e = lane; e < total; e += kWave) s_vals[e] = V(0);
+    wave_sync();
+    int run = incl - nh - 1;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        if (key[r] != kNoRow) {
+            if (hd[r]) {
+                ++run;
+                s_rows[run] = key[r];
+            }
+            lds_atomic_add(&s_vals[run], val[r]);
+        }
+    }
+    wave_sync();
+    const int64_t o = a.Ccolptr[j];
+    for (int e = lane; e < total; e += kWave) {
+        a.Crow[o + e] = s_rows[e];
+        a.Cval[o + e] = s_vals[e];
+    }
+    wave_sync();
+}
+
+template <typename V>
+__device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j, int *s_rows,
+                                                  V *s_vals) {
+    const int64_t f = a.flop[j];
+    if (f <= kWave) num_wave_column<1, V>(a, j, s_rows, s_vals);
+    else if (f <= 2 * kWave) num_wave_column<2, V>(a, j, s_rows, s_vals);
+    else if (f <= 4 * kWave) num_wave_column<4, V>(a, j, s_rows, s_vals);
+    else num_wave_column<8, V>(a, j, s_rows, s_vals);
 }
 
 // --- hash: LDS table, compaction, bitonic sort -----------------------------
@@ -60,7 +98,7 @@ template <int T, int G, typename V>
 struct NumHashLds {
     int keys[T];
     V vals[T];
-    EntryStage<G, V> st;
+    TermStage<G, V> st;
 };
 
 // G threads (gt in [0, G)) compute column j with a table of T slots.  The
@@ -75,9 +113,11 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     }
     group_sync<G>();
     for_each_term<G, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.Browidx, a.Bvals, a.map, a.At_colptr,
-                        &L.st, gt, [&](int64_t p, V bv) {
-                            const int32_t r = a.At_rowidx[p];
-                            const V v = a.At_vals[p] * bv;
+                        &L.st, gt,
+                        [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
+                        [&](const RowVal<V> &t, V bv) {
+                            const int32_t r = t.r;
+                            const V v = t.v * bv;
                             uint32_t h = hash_slot<T>(r);
                             while (true) {
                                 const int old = atomicCAS(&L.keys[h], -1, r);
@@ -149,7 +189,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
 // then values.  LDS (dynamic): bits[nw] u32 | wpre[nw] u16 | vals[vcap].
 template <int G, typename V>
 struct NumBitmapStatic {
-    EntryStage<G, V> st;
+    TermStage<G, V> st;
     int red[G / kWave + 2];
 };
 
@@ -163,10 +203,8 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     for (int i = gt; i < nw; i += G) bits[i] = 0u;
     __syncthreads();
     for_each_term<G, V>(q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
-                        [&](int64_t p, V) {
-                            const int32_t r = a.At_rowidx[p];
-                            atomicOr(&bits[r >> 5], 1u << (r & 31));
-                        });
+                        [&](int64_t p) { return a.At_rowidx[p]; },
+                        [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     const int per = (nw + G - 1) / G;
     const int w0 = gt * per, w1 = min(nw, w0 + per);
     int c = 0;
@@ -186,102 +224,123 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     for (int i = gt; i < total; i += G) vals[i] = V(0);
     __syncthreads();
     for_each_term<G, V>(q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
-                        [&](int64_t p, V bv) {
-                            const int32_t r = a.At_rowidx[p];
-                            const uint32_t w = bits[r >> 5];
-                            const int rk = wpre[r >> 5] + __popc(w & ((1u << (r & 31)) - 1u));
-                            lds_atomic_add(&vals[rk], a.At_vals[p] * bv);
+                        [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
+                        [&](const RowVal<V> &t, V bv) {
+                            const uint32_t w = bits[t.r >> 5];
+                            const int rk = wpre[t.r >> 5] + __popc(w & ((1u << (t.r & 31)) - 1u));
+                            lds_atomic_add(&vals[rk], t.v * bv);
                         });
     for (int i = gt; i < total; i += G) a.Cval[o + i] = vals[i];
     __syncthreads();
 }
 
 // --- dense: bitmap of all m rows + rank windows -----------------------------
-// LDS layout (dynamic): bits[nw] | wpre[nw] | vals[VC]
+// LDS (dynamic): bits[nw] u32 | wpre[nw] u16 | vals[VC].  wpre holds each
+// word's rank relative to its superblock of 2048 words (65536 rows), whose
+// absolute rank is in sbase, so ranks above 65535 need no 32-bit table.
+constexpr int kSuperShift = 11;
+constexpr int kMaxSuper = 16;
+
 template <typename V>
 struct NumDenseStatic {
-    EntryStage<kDenseThreads, V> st;
-    long long red64[kDenseThreads / kWave + 2];
+    TermStage<kDenseThreads, V> st;
     int red[kDenseThreads / kWave + 2];
-    int r_lo, r_hi;
+    int sbase[kMaxSuper];
+    int r_hi;
 };
 
-__device__ __forceinline__ int rank_of(const uint32_t *bits, const int *wpre, int32_t r) {
-    const uint32_t w = bits[r >> 5];
-    return wpre[r >> 5] + __popc(w & ((1u << (r & 31)) - 1u));
+__device__ __forceinline__ int word_rank(const uint16_t *wpre, const int *sbase, int w) {
+    return sbase[w >> kSuperShift] + wpre[w];
+}
+
+__device__ __forceinline__ int rank_of(const uint32_t *bits, const uint16_t *wpre,
+                                       const int *sbase, int32_t r) {
+    const int w = r >> 5;
+    return word_rank(wpre, sbase, w) + __popc(bits[w] & ((1u << (r & 31)) - 1u));
 }
 
 // Row holding rank R (0 <= R < total) of the bitmap.
-__device__ __forceinline__ int32_t row_of_rank(const uint32_t *bits, const int *wpre, int nw,
-                                               int R) {
+__device__ __forceinline__ int32_t row_of_rank(const uint32_t *bits, const uint16_t *wpre,
+                                               const int *sbase, int nw, int R) {
     int lo = 0, hi = nw - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (wpre[mid] <= R) lo = mid; else hi = mid - 1;
+        if (word_rank(wpre, sbase, mid) <= R) lo = mid; else hi = mid - 1;
     }
     uint32_t w = bits[lo];
-    int need = R - wpre[lo];
+    int need = R - word_rank(wpre, sbase, lo);
     while (need-- > 0) w &= w - 1;  // drop lower set bits
     return (lo << 5) + __ffs(w) - 1;
 }
 
 // kDenseThreads threads compute column j.  VC values fit in LDS at once;
-// columns with more rows are done in windows of VC consecutive ranks.
+// columns with more rows are done in windows of VC consecutive ranks, each
+// window resuming every entry's walk where the previous one stopped.
 template <typename V>
 __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
-                                                 int *wpre, V *vals, int VC,
+                                                 uint16_t *wpre, V *vals, int VC,
                                                  NumDenseStatic<V> &S) {
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
     for (int i = gt; i < nw; i += kDenseThreads) bits[i] = 0u;
     __syncthreads();
-    for_each_term<kDenseThreads, V>(q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr,
-                                    &S.st, gt, [&](int64_t p, V) {
-                                        const int32_t r = a.At_rowidx[p];
-                                        atomicOr(&bits[r >> 5], 1u << (r & 31));
-                                    });
-    // per-word exclusive prefix of set bits; each thread owns a run of words
+    for_each_term<kDenseThreads, V>(
+        q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
+        [&](int64_t p) { return a.At_rowidx[p]; },
+        [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
+    // ranks: every thread owns a run of consecutive words
     const int per = (nw + kDenseThreads - 1) / kDenseThreads;
     const int w0 = gt * per, w1 = min(nw, w0 + per);
     int c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
     int total;
-    int run = group_excl_scan<kDenseThreads>(c, S.red, &total);
-    const int64_t o = a.Ccolptr[j];
-    for (int w = w0; w < w1; ++w) {
-        wpre[w] = run;
-        uint32_t b = bits[w];
-        int r = run;
-        while (b) {
-            const int bit = __ffs(b) - 1;
-            a.Crow[o + r] = (w << 5) + bit;
-            ++r;
-            b &= b - 1;
+    const int run0 = group_excl_scan<kDenseThreads>(c, S.red, &total);
+    {
+        int run = run0;
+        for (int w = w0; w < w1; ++w) {
+            if ((w & ((1 << kSuperShift) - 1)) == 0) S.sbase[w >> kSuperShift] = run;
+            run += __popc(bits[w]);
         }
-        run = r;
     }
     __syncthreads();
+    const int64_t o = a.Ccolptr[j];
+    {
+        int run = run0;
+        for (int w = w0; w < w1; ++w) {
+            wpre[w] = (uint16_t)(run - S.sbase[w >> kSuperShift]);
+            uint32_t b = bits[w];
+            while (b) {
+                a.Crow[o + run] = (w << 5) + __ffs(b) - 1;
+                ++run;
+                b &= b - 1;
+            }
+        }
+    }
+    __syncthreads();
+    int32_t *cursor = a.cursor + q0;
     for (int w0r = 0; w0r < total; w0r += VC) {
         const int w1r = min(total, w0r + VC);
         const int cnt = w1r - w0r;
         for (int i = gt; i < cnt; i += kDenseThreads) vals[i] = V(0);
-        if (gt == 0) {
-            S.r_lo = row_of_rank(bits, wpre, nw, w0r);
-            S.r_hi = (w1r == total) ? (int32_t)a.m : row_of_rank(bits, wpre, nw, w1r);
-        }
+        if (gt == 0)
+            S.r_hi = (w1r == total) ? (int32_t)a.m : row_of_rank(bits, wpre, S.sbase, nw, w1r);
         __syncthreads();
-        auto acc = [&](int64_t p, V bv) {
-            const int32_t r = a.At_rowidx[p];
-            lds_atomic_add(&vals[rank_of(bits, wpre, r) - w0r], a.At_vals[p] * bv);
-        };
         if (cnt == total) {
-            for_each_term<kDenseThreads, V>(q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr,
-                                            &S.st, gt, acc);
+            for_each_term<kDenseThreads, V>(
+                q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
+                [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
+                [&](const RowVal<V> &t, V bv) {
+                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, t.r)], t.v * bv);
+                });
         } else {
-            const int32_t rl = S.r_lo, rh = S.r_hi;
-            for_each_term_rows<kDenseThreads, V>(q0, q1, rl, rh, a.Browidx, a.Bvals, a.map,
-                                                 a.At_colptr, a.At_rowidx, &S.st, gt, acc);
+            const int32_t rh = S.r_hi;
+            for_each_term_below<kDenseThreads, V>(
+                q0, q1, rh, w0r == 0, a.Browidx, a.Bvals, a.map, a.At_colptr, a.At_rowidx, cursor,
+                &S.st, gt, [&](int64_t p) { return a.At_vals[p]; },
+                [&](int32_t r, V av, V bv) {
+                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - w0r], av * bv);
+                });
         }
         for (int i = gt; i < cnt; i += kDenseThreads) a.Cval[o + w0r + i] = vals[i];
         __syncthreads();

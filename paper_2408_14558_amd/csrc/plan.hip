@@ -21,9 +21,9 @@ __global__ void k_plan_init(uint8_t *__restrict__ H, int64_t k, uint8_t *__restr
         glast[g] = -1;
     }
     for (int64_t s = t0; s < nstatus; s += stride) status[s] = 0;
+    int *w = reinterpret_cast<int *>(ctr);
+    for (int64_t i = t0; i < (int64_t)(sizeof(DevCounters) / sizeof(int)); i += stride) w[i] = 0;
     if (t0 == 0) {
-        int *w = reinterpret_cast<int *>(ctr);
-        for (size_t i = 0; i < sizeof(DevCounters) / sizeof(int); ++i) w[i] = 0;
         At_colptr[0] = 0;
     }
 }
@@ -193,46 +193,72 @@ __device__ __forceinline__ int find_owner(const int *pref, int n, int s) {
 }
 
 // Copies the selected columns (a chosen block is a contiguous range of A's
-// arrays) into A~.  One workgroup per 256 columns of A; the tile's copy work
-// is spread evenly over the workgroup.  kRows=false copies values only (new
-// values on the planned pattern).
+// arrays) into A~.  One workgroup per kGatherCols columns of A; the tile's
+// copy work is spread evenly over the workgroup with kUnrollCopy loads in
+// flight per thread.  kRows=false copies values only (new values on the
+// planned pattern).
+constexpr int kGatherCols = 64;
+constexpr int kGatherThreads = 256;
+constexpr int kUnrollCopy = 4;
 template <typename V, bool kRows>
-__global__ __launch_bounds__(256) void k_gather(const int64_t *__restrict__ Acolptr,
-                                                const int32_t *__restrict__ Arowidx,
-                                                const V *__restrict__ Avals,
-                                                const int32_t *__restrict__ map,
-                                                const int64_t *__restrict__ At_colptr, int64_t k,
-                                                int32_t *__restrict__ At_rowidx,
-                                                V *__restrict__ At_vals) {
-    __shared__ int s_pref[256];
-    __shared__ long long s_src[256];
-    __shared__ long long s_dst[256];
-    __shared__ int s_tmp[256 / kWave + 1];
+__global__ __launch_bounds__(kGatherThreads) void k_gather(const int64_t *__restrict__ Acolptr,
+                                                           const int32_t *__restrict__ Arowidx,
+                                                           const V *__restrict__ Avals,
+                                                           const int32_t *__restrict__ map,
+                                                           const int64_t *__restrict__ At_colptr,
+                                                           int64_t k, int32_t *__restrict__ At_rowidx,
+                                                           V *__restrict__ At_vals) {
+    __shared__ int s_pref[kGatherCols];
+    __shared__ long long s_src[kGatherCols];
+    __shared__ long long s_dst[kGatherCols];
+    __shared__ int s_total;
     const int tid = threadIdx.x;
-    const int64_t c = (int64_t)blockIdx.x * 256 + tid;
-    int len = 0;
-    long long src = 0, dst = 0;
-    if (c < k) {
-        const int32_t j = map[c];
-        if (j >= 0) {
-            src = Acolptr[c];
-            len = (int)(Acolptr[c + 1] - src);
-            dst = At_colptr[j];
+    if (tid < kWave) {
+        int len = 0;
+        long long src = 0, dst = 0;
+        const int64_t c = (int64_t)blockIdx.x * kGatherCols + tid;
+        if (tid < kGatherCols && c < k) {
+            const int32_t j = map[c];
+            if (j >= 0) {
+                src = Acolptr[c];
+                len = (int)(Acolptr[c + 1] - src);
+                dst = At_colptr[j];
+            }
         }
+        const int incl = wave_incl_scan(len);
+        if (tid < kGatherCols) {
+            s_pref[tid] = incl - len;
+            s_src[tid] = src;
+            s_dst[tid] = dst;
+        }
+        if (tid == kWave - 1) s_total = incl;
     }
-    int total;
-    const int excl = group_excl_scan<256>(len, s_tmp, &total);
-    s_pref[tid] = excl;
-    s_src[tid] = src;
-    s_dst[tid] = dst;
     __syncthreads();
-    for (int e = tid; e < total; e += 256) {
-        const int o = find_owner(s_pref, 256, e);
-        const int64_t off = e - s_pref[o];
-        const int64_t sp = s_src[o] + off;
-        const int64_t dp = s_dst[o] + off;
-        if (kRows) At_rowidx[dp] = Arowidx[sp];
-        At_vals[dp] = Avals[sp];
+    const int total = s_total;
+    for (int e0 = tid; e0 < total; e0 += kUnrollCopy * kGatherThreads) {
+        long long sp[kUnrollCopy], dp[kUnrollCopy];
+        int32_t r[kUnrollCopy];
+        V v[kUnrollCopy];
+#pragma unroll
+        for (int u = 0; u < kUnrollCopy; ++u) {
+            const int e = e0 + u * kGatherThreads;
+            if (e < total) {
+                const int o = find_owner(s_pref, kGatherCols, e);
+                const int64_t off = e - s_pref[o];
+                sp[u] = s_src[o] + off;
+                dp[u] = s_dst[o] + off;
+                if (kRows) r[u] = Arowidx[sp[u]];
+                v[u] = Avals[sp[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnrollCopy; ++u) {
+            const int e = e0 + u * kGatherThreads;
+            if (e < total) {
+                if (kRows) At_rowidx[dp[u]] = r[u];
+                At_vals[dp[u]] = v[u];
+            }
+        }
     }
 }
 
@@ -336,13 +362,13 @@ int launch_plan_kernels(Plan &p) {
                            p.stream, p.Acolptr, p.k, p.gid, p.hit, p.gfirst, p.map, p.colid,
                            p.At_colptr, p.st_sel_cnt, p.st_sel_nnz, p.n_sel_tiles, p.ctr);
     if (p.k > 0 && p.nnzA > 0) {
-        const unsigned g = (unsigned)((p.k + 255) / 256);
+        const unsigned g = (unsigned)((p.k + kGatherCols - 1) / kGatherCols);
         if (p.dtype == SPGEMM_F64)
-            hipLaunchKernelGGL((k_gather<double, true>), dim3(g), dim3(256), 0, p.stream,
+            hipLaunchKernelGGL((k_gather<double, true>), dim3(g), dim3(kGatherThreads), 0, p.stream,
                                p.Acolptr, p.Arowidx, (const double *)p.Avals, p.map, p.At_colptr,
                                p.k, p.At_rowidx, (double *)p.At_vals);
         else
-            hipLaunchKernelGGL((k_gather<float, true>), dim3(g), dim3(256), 0, p.stream,
+            hipLaunchKernelGGL((k_gather<float, true>), dim3(g), dim3(kGatherThreads), 0, p.stream,
                                p.Acolptr, p.Arowidx, (const float *)p.Avals, p.map, p.At_colptr,
                                p.k, p.At_rowidx, (float *)p.At_vals);
     }
@@ -352,15 +378,15 @@ int launch_plan_kernels(Plan &p) {
 
 int launch_gather_values(Plan &p, const void *Avals) {
     if (p.k == 0 || p.nnzA == 0) return SPGEMM_OK;
-    const unsigned g = (unsigned)((p.k + 255) / 256);
+    const unsigned g = (unsigned)((p.k + kGatherCols - 1) / kGatherCols);
     if (p.dtype == SPGEMM_F64)
-        hipLaunchKernelGGL((k_gather<double, false>), dim3(g), dim3(256), 0, p.stream, p.Acolptr,
-                           p.Arowidx, (const double *)Avals, p.map, p.At_colptr, p.k, p.At_rowidx,
-                           (double *)p.At_vals);
+        hipLaunchKernelGGL((k_gather<double, false>), dim3(g), dim3(kGatherThreads), 0, p.stream,
+                           p.Acolptr, p.Arowidx, (const double *)Avals, p.map, p.At_colptr, p.k,
+                           p.At_rowidx, (double *)p.At_vals);
     else
-        hipLaunchKernelGGL((k_gather<float, false>), dim3(g), dim3(256), 0, p.stream, p.Acolptr,
-                           p.Arowidx, (const float *)Avals, p.map, p.At_colptr, p.k, p.At_rowidx,
-                           (float *)p.At_vals);
+        hipLaunchKernelGGL((k_gather<float, false>), dim3(g), dim3(kGatherThreads), 0, p.stream,
+                           p.Acolptr, p.Arowidx, (const float *)Avals, p.map, p.At_colptr, p.k,
+                           p.At_rowidx, (float *)p.At_vals);
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
 }

@@ -29,12 +29,12 @@ __device__ __forceinline__ int num_bin_of(long long f, long long nnz, const Thre
 // per non-empty bin and workgroup reserves a contiguous range.
 __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const int *s_lpos,
                                                int *s_cnt, int *s_base, int64_t j0,
-                                               int *__restrict__ gcount,
+                                               LineInt *__restrict__ gcount,
                                                int32_t *__restrict__ list, int64_t n) {
     // s_cnt already holds the per-bin counts of this workgroup
     if (threadIdx.x < kNumBins) {
         const int c = s_cnt[threadIdx.x];
-        s_base[threadIdx.x] = c ? atomicAdd(&gcount[threadIdx.x], c) : 0;
+        s_base[threadIdx.x] = c ? atomicAdd(&gcount[threadIdx.x].v, c) : 0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
@@ -43,21 +43,22 @@ __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const
     }
 }
 
-// Sparse flops of every column of B_i and its symbolic bin.  One thread
-// per column walks short columns (independent loads, unrolled); columns with
-// more than kFlopShort entries are summed by a whole wave afterwards.
-constexpr int kFlopCols = 128;
-constexpr int kFlopShort = 64;
-__global__ __launch_bounds__(kFlopCols) void k_flop_bin(
+// Sparse flops of every column of B_i and its symbolic bin.  S lanes walk
+// one column (S picked from the average column length); columns with more
+// than 16*S entries are summed by a whole wave afterwards.
+constexpr int kFlopThreads = 256;
+template <int S>
+__global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
     DevCounters *__restrict__ ctr) {
-    __shared__ int s_bin[kFlopCols];
-    __shared__ int s_lpos[kFlopCols];
-    __shared__ int s_long[kFlopCols];
-    __shared__ long long s_f[kFlopCols];
+    constexpr int COLS = kFlopThreads / S;
+    __shared__ int s_bin[COLS];
+    __shared__ int s_lpos[COLS];
+    __shared__ int s_long[COLS];
+    __shared__ long long s_f[COLS];
     __shared__ int s_cnt[kNumBins];
     __shared__ int s_base[kNumBins];
     __shared__ int s_nlong;
@@ -74,38 +75,44 @@ __global__ __launch_bounds__(kFlopCols) void k_flop_bin(
         s_nlong = 0;
     }
     __syncthreads();
-    const int64_t j0 = (int64_t)blockIdx.x * kFlopCols;
-    const int nloc = (int)min<int64_t>(kFlopCols, n - j0);
-    const int64_t j = j0 + tid;
-    if (tid < nloc) {
-        const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1];
-        if (q1 - q0 <= kFlopShort) {
-            long long acc = 0;
+    const int64_t j0 = (int64_t)blockIdx.x * COLS;
+    const int nloc = (int)min<int64_t>(COLS, n - j0);
+    const int lc = tid / S, sub = tid % S;
+    long long acc = 0;
+    bool deferred = false;
+    if (lc < nloc) {
+        const int64_t q0 = Bcolptr[j0 + lc], q1 = Bcolptr[j0 + lc + 1];
+        if (q1 - q0 <= 16 * S) {
 #pragma unroll 4
-            for (int64_t q = q0; q < q1; ++q) {
+            for (int64_t q = q0 + sub; q < q1; q += S) {
                 const int32_t jt = map[Browidx[q]];
                 if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
             }
-            s_f[tid] = acc;
         } else {
-            s_long[atomicAdd(&s_nlong, 1)] = tid;
+            deferred = true;
         }
+    }
+    acc = wave_sum<S>(acc);
+    if (lc < nloc && sub == 0) {
+        if (deferred) s_long[atomicAdd(&s_nlong, 1)] = lc;
+        else s_f[lc] = acc;
     }
     __syncthreads();
     const int wv = tid / kWave, lane = lane_id();
-    for (int li = wv; li < s_nlong; li += kFlopCols / kWave) {
+    for (int li = wv; li < s_nlong; li += kFlopThreads / kWave) {
         const int t = s_long[li];
         const int64_t q1 = Bcolptr[j0 + t + 1];
-        long long acc = 0;
+        long long a2 = 0;
         for (int64_t q = Bcolptr[j0 + t] + lane; q < q1; q += kWave) {
             const int32_t jt = map[Browidx[q]];
-            if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
+            if (jt >= 0) a2 += At_colptr[jt + 1] - At_colptr[jt];
         }
-        acc = wave_sum(acc);
-        if (lane == 0) s_f[t] = acc;
+        a2 = wave_sum(a2);
+        if (lane == 0) s_f[t] = a2;
     }
     __syncthreads();
     if (tid < nloc) {
+        const int64_t j = j0 + tid;
         const long long f = s_f[tid];
         flop[j] = f;
         const int b = sym_bin_of(f, th);
@@ -116,37 +123,59 @@ __global__ __launch_bounds__(kFlopCols) void k_flop_bin(
         if (f) atomic_add_i64(&s_flops, f);
     }
     __syncthreads();
-    if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops, s_flops);
+    if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops.v, s_flops);
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
 }
 
-// --- tiny bin: one wave per column, terms in registers, sort + count ------
+// --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
+template <int E>
+__device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1,
+                                              const int32_t *__restrict__ Browidx,
+                                              const int32_t *__restrict__ map,
+                                              const int64_t *__restrict__ At_colptr,
+                                              const int32_t *__restrict__ At_rowidx) {
+    int64_t p[E];
+    float bv[E];
+    wave_terms<E, float>(q0, q1, Browidx, nullptr, map, At_colptr, p, bv);
+    int key[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) key[r] = p[r] >= 0 ? At_rowidx[p[r]] : kNoRow;
+    wave_sort<E, false, float>(key, bv);
+    const int prev_last = __shfl_up(key[E - 1], 1);
+    int nh = 0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int prev = r == 0 ? prev_last : key[r - 1];
+        nh += key[r] != kNoRow && ((r == 0 && lane_id() == 0) || key[r] != prev);
+    }
+    return wave_sum(nh);
+}
+
 __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ list, int count,
                                                   const int64_t *__restrict__ Bcolptr,
                                                   const int32_t *__restrict__ Browidx,
                                                   const int32_t *__restrict__ map,
                                                   const int64_t *__restrict__ At_colptr,
                                                   const int32_t *__restrict__ At_rowidx,
+                                                  const int64_t *__restrict__ flop,
                                                   int64_t *__restrict__ Ccount) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= count) return;  // whole wave leaves together
     const int32_t j = list[w];
-    int64_t p;
-    float dummy;
-    tiny_terms<float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, p, dummy);
-    int key = (p >= 0) ? At_rowidx[p] : kNoRow;
-    wave_sort_keys(key);
-    const int prev = __shfl_up(key, 1);
-    const bool head = key != kNoRow && (lane_id() == 0 || prev != key);
-    const uint64_t m = __ballot(head);
-    if (lane_id() == 0) Ccount[j] = __popcll(m);
+    const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1], f = flop[j];
+    int c;
+    if (f <= kWave) c = sym_wave_count<1>(q0, q1, Browidx, map, At_colptr, At_rowidx);
+    else if (f <= 2 * kWave) c = sym_wave_count<2>(q0, q1, Browidx, map, At_colptr, At_rowidx);
+    else if (f <= 4 * kWave) c = sym_wave_count<4>(q0, q1, Browidx, map, At_colptr, At_rowidx);
+    else c = sym_wave_count<8>(q0, q1, Browidx, map, At_colptr, At_rowidx);
+    if (lane_id() == 0) Ccount[j] = c;
 }
 
 // --- hash bins: LDS open addressing (linear probing), count inserts -------
 template <int T, int G>
 struct SymHashLds {
     int keys[T];
-    EntryStage<G, float> st;
+    TermStage<G, float> st;
 };
 
 template <int T, int G>
@@ -170,8 +199,8 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
     group_sync<G>();
     int inserted = 0;
     for_each_term<G, float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, &L.st,
-                            gt, [&](int64_t p, float) {
-                                const int32_t r = At_rowidx[p];
+                            gt, [&](int64_t p) { return At_rowidx[p]; },
+                            [&](int32_t r, float) {
                                 uint32_t h = hash_slot<T>(r);
                                 while (true) {
                                     const int old = atomicCAS(&L.keys[h], -1, r);
@@ -194,7 +223,7 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
 
 // --- dense bin: bitmap of all m rows in LDS ---------------------------------
 struct SymDenseLds {
-    EntryStage<kDenseThreads, float> st;
+    TermStage<kDenseThreads, float> st;
     int red[kDenseThreads / kWave + 2];
 };
 
@@ -212,11 +241,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int gt = threadIdx.x;
     for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
     __syncthreads();
-    for_each_term<kDenseThreads, float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map,
-                                        At_colptr, &L.st, gt, [&](int64_t p, float) {
-                                            const int32_t r = At_rowidx[p];
-                                            atomicOr(&s_bits[r >> 5], 1u << (r & 31));
-                                        });
+    for_each_term<kDenseThreads, float>(
+        Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, &L.st, gt,
+        [&](int64_t p) { return At_rowidx[p]; },
+        [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
     int c = 0;
     for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
     int total;
@@ -283,14 +311,23 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+template <int S>
+static int flop_bin_launch(Plan &p) {
+    constexpr int COLS = kFlopThreads / S;
+    const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
+    hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
+                       p.Browidx, p.map, p.At_colptr, p.th, p.flop, p.sym_bin, p.sym_list,
+                       p.C_colptr, p.st_colptr, p.n_col_tiles, p.ctr);
+    SPG_LAUNCHED("k_flop_bin");
+    return SPGEMM_OK;
+}
+
 int launch_flop_bin(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
-    const unsigned g = (unsigned)((p.n + kFlopCols - 1) / kFlopCols);
-    hipLaunchKernelGGL(k_flop_bin, dim3(g), dim3(kFlopCols), 0, p.stream, p.n, p.Bcolptr, p.Browidx,
-                       p.map, p.At_colptr, p.th, p.flop, p.sym_bin, p.sym_list, p.C_colptr,
-                       p.st_colptr, p.n_col_tiles, p.ctr);
-    SPG_HIP(hipGetLastError());
-    return SPGEMM_OK;
+    const double avg = (double)p.nnzB / (double)p.n;
+    if (avg <= 4.0) return flop_bin_launch<1>(p);
+    if (avg <= 32.0) return flop_bin_launch<4>(p);
+    return flop_bin_launch<16>(p);
 }
 
 template <int T, int G>
@@ -314,7 +351,9 @@ int launch_symbolic_bins(Plan &p) {
         const unsigned g = (unsigned)((p.sym_count[kBinTiny] + 3) / 4);
         hipLaunchKernelGGL(k_sym_tiny, dim3(g), dim3(256), 0, p.stream,
                            p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
-                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.C_colptr);
+                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.flop,
+                           p.C_colptr);
+        SPG_LAUNCHED("k_sym_tiny");
     }
     int rc;
     if ((rc = sym_hash_launch<kSymTable[0], 64>(p, kBinH0))) return rc;

@@ -8,44 +8,56 @@
 
 namespace spg {
 
+// Entries of B(:,j) whose column of A~ holds more than kShortLen entries
+// are "long": a team of lanes walks them with consecutive (coalesced)
+// positions.  Shorter ones are walked by the thread that loaded the entry.
+constexpr int kShortLen = 32;
+
 // LDS staging for one chunk of G entries of B(:,j).
 template <int G, typename V>
-struct EntryStage {
-    int pref[G];          // exclusive prefix of the entries' term counts
-    long long start[G];   // first position of the entry's column in A~
-    V bv[G];              // b_kj
+struct TermStage {
+    long long lstart[G];  // long entries: first position in A~ still to visit
+    long long lend[G];    // one past the entry's last position
+    V lbv[G];             // b_kj
+    int llen[G];          // length of the entry's column of A~
+    int lq[G];            // entry index relative to the column's first entry
+    int nlong;
     int tmp[G / kWave + 2];
 };
 
-// Largest o in [0, n) with pref[o] <= s (pref non-decreasing from 0).
-__device__ __forceinline__ int owner_of(const int *pref, int n, int s) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pref[mid] <= s)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
+// A term's row id and a_ik.
+template <typename V>
+struct RowVal {
+    int32_t r;
+    V v;
+};
 
-// Visits every term of column j, spread evenly over the G threads of a group
-// (gt = thread index inside the group).  f(p, bv) gets the position p of
-// a_ik in A~ and b_kj.  All G threads must call it (it synchronises the
-// group).  Terms of one chunk of G entries are handed out round-robin, so
-// consecutive threads read consecutive entries of A~.
-template <int G, typename V, typename F>
+// Loads in flight per thread while walking terms: a walker first issues
+// kUnroll independent loads (ld), then applies them (ap).
+constexpr int kUnroll = 4;
+
+// Visits every term of column j with the G threads of a group (gt = thread
+// index inside the group).  For each term at position p of A~ (with b_kj =
+// bv) it calls ap(ld(p), bv); ld does the global loads, ap the LDS work, so
+// kUnroll loads per thread are in flight before the first use.  All G
+// threads must call it (it synchronises the group).
+template <int G, typename V, typename LD, typename AP>
 __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1,
                                               const int32_t *__restrict__ Browidx,
                                               const V *__restrict__ Bvals,
                                               const int32_t *__restrict__ map,
                                               const int64_t *__restrict__ At_colptr,
-                                              EntryStage<G, V> *st, int gt, F &&f) {
+                                              TermStage<G, V> *st, int gt, LD &&ld, AP &&ap) {
+    using Item = decltype(ld((int64_t)0));
+    constexpr int TEAM = G < kWave ? G : kWave;
+    constexpr int NTEAM = G / TEAM;
+    const int team = gt / TEAM, tl = gt % TEAM;
     for (int64_t qb = q0; qb < q1; qb += G) {
+        if (gt == 0) st->nlong = 0;
+        group_sync<G>();
         const int64_t q = qb + gt;
-        int len = 0;
         long long start = 0;
+        int len = 0;
         V bv = V(0);
         if (q < q1) {
             const int32_t jt = map[Browidx[q]];
@@ -55,84 +67,141 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1,
                 if (Bvals) bv = Bvals[q];
             }
         }
-        int total;
-        const int excl = group_excl_scan<G>(len, st->tmp, &total);
-        st->pref[gt] = excl;
-        st->start[gt] = start;
-        st->bv[gt] = bv;
+        if (len > kShortLen) {
+            const int slot = atomicAdd(&st->nlong, 1);
+            st->lstart[slot] = start;
+            st->lend[slot] = start + len;
+            st->lbv[slot] = bv;
+        } else {
+            for (int e = 0; e < len; e += kUnroll) {
+                Item it[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (e + u < len) it[u] = ld((int64_t)(start + e + u));
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (e + u < len) ap(it[u], bv);
+            }
+        }
         group_sync<G>();
-        for (int s = gt; s < total; s += G) {
-            const int o = owner_of(st->pref, G, s);
-            f((int64_t)(st->start[o] + (s - st->pref[o])), st->bv[o]);
+        const int nl = st->nlong;
+        for (int li = team; li < nl; li += NTEAM) {
+            const long long s = st->lstart[li], t = st->lend[li];
+            const V b = st->lbv[li];
+            for (long long e = s + tl; e < t; e += kUnroll * TEAM) {
+                Item it[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (e + u * TEAM < t) it[u] = ld((int64_t)(e + u * TEAM));
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (e + u * TEAM < t) ap(it[u], b);
+            }
         }
         group_sync<G>();
     }
 }
 
-// Same, restricted to the terms whose row lies in [r_lo, r_hi): each entry's
-// sub-range is found by binary search in its (row-sorted) column of A~.
-template <int G, typename V, typename F>
-__device__ __forceinline__ void for_each_term_rows(int64_t q0, int64_t q1, int32_t r_lo,
-                                                   int32_t r_hi,
-                                                   const int32_t *__restrict__ Browidx,
-                                                   const V *__restrict__ Bvals,
-                                                   const int32_t *__restrict__ map,
-                                                   const int64_t *__restrict__ At_colptr,
-                                                   const int32_t *__restrict__ At_rowidx,
-                                                   EntryStage<G, V> *st, int gt, F &&f) {
+// Visits the terms of column j whose row is below r_hi and that no earlier
+// call visited: cursor[q - q0] keeps, per entry of B(:,j), how far the
+// entry's column of A~ has been walked (rows ascend, so each call resumes
+// where the previous one stopped).  first == true starts every cursor at 0.
+// For each such term: ap(row, ldv(p), bv).  G >= 64 (teams are whole waves).
+template <int G, typename V, typename LDV, typename AP>
+__device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int32_t r_hi,
+                                                    bool first,
+                                                    const int32_t *__restrict__ Browidx,
+                                                    const V *__restrict__ Bvals,
+                                                    const int32_t *__restrict__ map,
+                                                    const int64_t *__restrict__ At_colptr,
+                                                    const int32_t *__restrict__ At_rowidx,
+                                                    int32_t *__restrict__ cursor,
+                                                    TermStage<G, V> *st, int gt, LDV &&ldv,
+                                                    AP &&ap) {
+    static_assert(G >= kWave, "teams are whole waves");
+    constexpr int NTEAM = G / kWave;
+    const int team = gt / kWave, tl = lane_id();
     for (int64_t qb = q0; qb < q1; qb += G) {
+        if (gt == 0) st->nlong = 0;
+        group_sync<G>();
         const int64_t q = qb + gt;
-        int len = 0;
-        long long start = 0;
-        V bv = V(0);
         if (q < q1) {
             const int32_t jt = map[Browidx[q]];
             if (jt >= 0) {
-                int64_t lo = At_colptr[jt], hi = At_colptr[jt + 1];
-                // first position with row >= r_lo
-                int64_t a = lo, b = hi;
-                while (a < b) {
-                    const int64_t mid = (a + b) >> 1;
-                    if (At_rowidx[mid] < r_lo) a = mid + 1; else b = mid;
+                const long long c0 = At_colptr[jt];
+                const long long end = At_colptr[jt + 1];
+                const int rel = first ? 0 : cursor[q - q0];
+                const V bv = Bvals[q];
+                if (end - c0 > kShortLen) {
+                    const int slot = atomicAdd(&st->nlong, 1);
+                    st->lstart[slot] = c0 + rel;
+                    st->lend[slot] = end;
+                    st->lbv[slot] = bv;
+                    st->llen[slot] = (int)(end - c0);
+                    st->lq[slot] = (int)(q - q0);
+                } else {
+                    long long pos = c0 + rel;
+                    while (pos < end) {
+                        const int32_t r = At_rowidx[pos];
+                        if (r >= r_hi) break;
+                        ap(r, ldv((int64_t)pos), bv);
+                        ++pos;
+                    }
+                    cursor[q - q0] = (int32_t)(pos - c0);
                 }
-                const int64_t s0 = a;
-                b = hi;
-                while (a < b) {
-                    const int64_t mid = (a + b) >> 1;
-                    if (At_rowidx[mid] < r_hi) a = mid + 1; else b = mid;
-                }
-                start = s0;
-                len = (int)(a - s0);
-                if (Bvals) bv = Bvals[q];
             }
         }
-        int total;
-        const int excl = group_excl_scan<G>(len, st->tmp, &total);
-        st->pref[gt] = excl;
-        st->start[gt] = start;
-        st->bv[gt] = bv;
         group_sync<G>();
-        for (int s = gt; s < total; s += G) {
-            const int o = owner_of(st->pref, G, s);
-            f((int64_t)(st->start[o] + (s - st->pref[o])), st->bv[o]);
+        const int nl = st->nlong;
+        for (int li = team; li < nl; li += NTEAM) {
+            long long pos = st->lstart[li];
+            const long long t = st->lend[li];
+            const V b = st->lbv[li];
+            while (pos < t) {
+                int32_t r[kUnroll];
+                V v[kUnroll];
+                int cnt = 0;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const long long e = pos + u * kWave + tl;
+                    r[u] = e < t ? At_rowidx[e] : 0x7fffffff;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const long long e = pos + u * kWave + tl;
+                    if (r[u] < r_hi) v[u] = ldv((int64_t)e);
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (r[u] < r_hi) ap(r[u], v[u], b);
+                    // rows ascend inside the column, so lanes below r_hi are a prefix
+                    cnt += __popcll(__ballot(r[u] < r_hi));
+                }
+                pos += cnt;
+                if (cnt < kUnroll * kWave) break;
+            }
+            if (tl == 0) cursor[st->lq[li]] = (int32_t)(pos - (t - st->llen[li]));
         }
         group_sync<G>();
     }
 }
 
-// The terms of a column with at most 64 of them, one per lane of a wave:
-// lane s receives term s (p = its position in A~, bv = b_kj), lanes past the
-// last term get p = -1.  All 64 lanes must call it.
-template <typename V>
-__device__ __forceinline__ void tiny_terms(int64_t q0, int64_t q1,
+// The terms of a column with at most 64*E of them, spread over one wave:
+// slot r of lane l receives term r*64 + l (p = its position in A~, bv =
+// b_kj); slots past the last term get p = -1.  All 64 lanes must call it.
+template <int E, typename V>
+__device__ __forceinline__ void wave_terms(int64_t q0, int64_t q1,
                                            const int32_t *__restrict__ Browidx,
                                            const V *__restrict__ Bvals,
                                            const int32_t *__restrict__ map,
-                                           const int64_t *__restrict__ At_colptr, int64_t &p,
-                                           V &bv) {
+                                           const int64_t *__restrict__ At_colptr,
+                                           int64_t (&p)[E], V (&bv)[E]) {
     const int lane = lane_id();
-    p = -1;
-    bv = V(0);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        p[r] = -1;
+        bv[r] = V(0);
+    }
     int base = 0;
     for (int64_t qb = q0; qb < q1; qb += kWave) {
         const int64_t q = qb + lane;
@@ -149,59 +218,74 @@ __device__ __forceinline__ void tiny_terms(int64_t q0, int64_t q1,
         }
         const int incl = wave_incl_scan(len);
         const int S = __shfl(incl, kWave - 1);
-        const int s = lane - base;
-        // first lane e with incl[e] > s
-        int lo = 0, hi = kWave - 1;
 #pragma unroll
-        for (int it = 0; it < 6; ++it) {
-            const int mid = (lo + hi) >> 1;
-            const int v = __shfl(incl, mid);
-            if (v > s) hi = mid; else lo = mid + 1;
-        }
-        const int e = lo;
-        const int excl_e = __shfl(incl - len, e);
-        const long long start_e = __shfl(start, e);
-        const V b_e = __shfl(b, e);
-        if (s >= 0 && s < S) {
-            p = start_e + (s - excl_e);
-            bv = b_e;
+        for (int r = 0; r < E; ++r) {
+            const int s = r * kWave + lane - base;
+            // first lane e with incl[e] > s
+            int lo = 0, hi = kWave - 1;
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const int mid = (lo + hi) >> 1;
+                const int v = __shfl(incl, mid);
+                if (v > s) hi = mid; else lo = mid + 1;
+            }
+            const int excl_e = __shfl(incl - len, lo);
+            const long long start_e = __shfl(start, lo);
+            const V b_e = __shfl(b, lo);
+            if (s >= 0 && s < S) {
+                p[r] = start_e + (s - excl_e);
+                bv[r] = b_e;
+            }
         }
         base += S;
     }
 }
 
-// Ascending bitonic sort of one (key, value) pair per lane across a wave.
-template <typename V>
-__device__ __forceinline__ void wave_sort_pairs(int &key, V &val) {
-    const int l = lane_id();
+// Ascending bitonic sort of 64*E (key, value) pairs held by one wave; lane l
+// holds elements l*E .. l*E+E-1 in slots 0..E-1.  Pairs at distance below E
+// sit in one lane; the others are exchanged across lanes.
+template <int E, bool kVals, typename V>
+__device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
+    const int lane = lane_id();
 #pragma unroll
-    for (int kk = 2; kk <= kWave; kk <<= 1) {
+    for (int kk = 2; kk <= kWave * E; kk <<= 1) {
 #pragma unroll
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const int ok = __shfl_xor(key, jj);
-            const V ov = __shfl_xor(val, jj);
-            const bool up = (l & kk) == 0;
-            const bool lower = (l & jj) == 0;
-            const bool take = (lower == up) ? (ok < key) : (ok > key);
-            if (take) {
-                key = ok;
-                val = ov;
+            if (jj < E) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    if ((r & jj) == 0) {
+                        const int i = lane * E + r;
+                        const bool up = (i & kk) == 0;
+                        const int a = key[r], b = key[r ^ jj];
+                        if ((a > b) == up) {
+                            key[r] = b;
+                            key[r ^ jj] = a;
+                            if constexpr (kVals) {
+                                const V t = val[r];
+                                val[r] = val[r ^ jj];
+                                val[r ^ jj] = t;
+                            }
+                        }
+                    }
+                }
+            } else {
+                const int ld = jj / E;
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int i = lane * E + r;
+                    const int ok = __shfl_xor(key[r], ld);
+                    V ov = V(0);
+                    if constexpr (kVals) ov = __shfl_xor(val[r], ld);
+                    const bool up = (i & kk) == 0;
+                    const bool lower = (i & jj) == 0;
+                    const bool take = (lower == up) ? (ok < key[r]) : (ok > key[r]);
+                    if (take) {
+                        key[r] = ok;
+                        if constexpr (kVals) val[r] = ov;
+                    }
+                }
             }
-        }
-    }
-}
-
-__device__ __forceinline__ void wave_sort_keys(int &key) {
-    const int l = lane_id();
-#pragma unroll
-    for (int kk = 2; kk <= kWave; kk <<= 1) {
-#pragma unroll
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const int ok = __shfl_xor(key, jj);
-            const bool up = (l & kk) == 0;
-            const bool lower = (l & jj) == 0;
-            const bool take = (lower == up) ? (ok < key) : (ok > key);
-            if (take) key = ok;
         }
     }
 }

@@ -45,7 +45,7 @@ def test_default_tuning_and_version(lib):
     from paper_2408_14558_amd import _lib
     t = _lib.Tuning()
     assert lib.spgemm_default_tuning(ctypes.byref(t)) == 0
-    assert t.tiny_max_flop == 64 and t.hash_max_flop == 4096 and t.hash_max_nnz == 2048
+    assert t.tiny_max_flop == 256 and t.hash_max_flop == 4096 and t.hash_max_nnz == 2048
     assert lib.spgemm_default_tuning(None) == _lib.EINVAL
     assert b"gfx950" in lib.spgemm_version()
 
@@ -102,7 +102,7 @@ def test_host_side_rejections(lib, case):
         tun = _lib.Tuning()
         lib.spgemm_default_tuning(ctypes.byref(tun))
         if case == "tiny_tuning":
-            tun.tiny_max_flop = 65
+            tun.tiny_max_flop = 513
         else:
             tun.hash_max_nnz = 4096
     rc, h = _plan(lib, A, B, offs, P, b, tun, dtype)
