@@ -11,7 +11,7 @@
  *   spgemm_symbolic  sparse flops per column, binning, nnz per column, scan
  *   spgemm_numeric   values of C_i (rows ascending inside every column)
  *   spgemm_backward  (dC*B_i^T) o pattern(A) and (A^T*dC) o pattern(B_i)
- *   spgemm_batched   numeric of many planned products in one persistent launch
+ *   spgemm_batched   numeric of many planned products as one DAG (or one hipGraph)
  *
  * Conventions for every entry point:
  *   - Matrices are CSC: colptr int64[ncols+1], rowidx int32[nnz] with row ids
@@ -75,6 +75,10 @@ typedef struct {
     int32_t own_partition_whole;/* ... and 1 selects that partition's nonzero columns whole */
     int32_t medium_kernel;      /* medium numeric bins: 0 = choose by m, 1 = LDS hash and
                                    sort, 2 = LDS bitmap and rank */
+    int32_t batch_streams;      /* batched: side streams independent products spread over
+                                   (0 = 4, at most 8) */
+    int32_t batch_persistent;   /* must be 0: the single-launch persistent form of the
+                                   batch is switched off (SPGEMM_EUNSUPPORTED) */
     int64_t workspace_limit;    /* bytes of device workspace a plan may take; 0 = no limit */
 } spgemm_tuning;
 
@@ -221,13 +225,17 @@ int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *
 int spgemm_plan_destroy(spgemm_plan_t plan);
 
 /* ---------------------------------------------------------------------------
- * Batched numeric: many planned products (uneven sizes, optionally chained
- * like the two products of each AMG Galerkin level) in ONE persistent kernel
- * launch, optionally captured once into a hipGraph and replayed.
+ * Batched numeric (the Galerkin products of an AMG setup, Sec. II-C and
+ * Sec. IV-B, and any set of independent products): the numeric phase of many
+ * planned products of uneven sizes, optionally chained (the C of one product
+ * is the A or B of a later one), enqueued as one dependency DAG and
+ * optionally captured once into a hipGraph and replayed with new values in
+ * the same buffers.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    const void *A_vals;   /* dtype[nnz(A)] or NULL = plan's values */
-    const void *B_vals;   /* dtype[nnz(B)] or NULL = plan's values */
+    const void *A_vals;   /* dtype[nnz(A)]: new values of A, gathered into A~ before the
+                             product (NULL = keep A~ as the plan gathered it) */
+    const void *B_vals;   /* dtype[nnz(B)] or NULL = the plan's values of B_i */
     int32_t *C_rowidx;    /* int32[nnzC] of this product */
     void *C_vals;         /* dtype[nnzC] */
     int32_t dep_A;        /* index of an earlier product whose C is this A, or -1 */
@@ -237,25 +245,35 @@ typedef struct {
 typedef struct spgemm_batch_s *spgemm_batch_t;
 
 /*
- * Builds a batch over `count` plans that have all finished spgemm_symbolic
- * and share one dtype.  Dependencies must point to lower indices.  The work
- * list (value gathers and per-bin column tiles of every product) is built on
- * the host once; plans must outlive the batch.  Synchronises plans' streams.
+ * Builds a batch over `count` distinct plans that have all finished
+ * spgemm_symbolic and share one dtype.  Dependencies must point to lower
+ * indices, and a product that reads another's C must name it (dep_A/dep_B)
+ * and pass that C's value buffer as A_vals/B_vals.  Products of one
+ * dependency depth run concurrently on up to tuning->batch_streams side
+ * streams.  The io table is copied; plans and buffers must outlive the
+ * batch.  Synchronises the plans' streams once.  Errors: EINVAL (bad table,
+ * repeated plan), ESTATE (no symbolic), EUNSUPPORTED (batch_persistent != 0),
+ * EHIP.
  */
 int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
                         const spgemm_tuning *tuning, spgemm_batch_t *out);
 
 /*
- * Runs the batch on `stream`:
- *   mode 0  launch the persistent kernel directly;
- *   mode 1  capture that launch into a hipGraph, instantiate it and launch it;
+ * Runs the batch on `stream` (side streams fork from it and join back, so
+ * every product has finished when `stream` reaches the end of the call):
+ *   mode 0  enqueue the DAG's kernels directly;
+ *   mode 1  capture the DAG into a hipGraph, instantiate it and launch it;
  *   mode 2  relaunch the instantiated graph (SPGEMM_ESTATE without mode 1).
- * Launches of one batch must not overlap (they share queue counters).
+ * Runs of one batch must not overlap (they share the plans' A~ and scratch).
+ * Work on the plans' own streams is not ordered with the batch.
  */
 int spgemm_batched(spgemm_batch_t batch, int32_t mode, void *stream);
 
-/* Workgroups the persistent kernel uses, and the number of work items. */
-int spgemm_batch_info(spgemm_batch_t batch, int64_t *workgroups, int64_t *items);
+/* Side streams the batch uses, and kernels one run enqueues. */
+int spgemm_batch_info(spgemm_batch_t batch, int64_t *streams, int64_t *launches);
+
+/* Synchronises the device and returns SPGEMM_EHIP if a launch failed. */
+int spgemm_batch_check(spgemm_batch_t batch);
 
 int spgemm_batch_destroy(spgemm_batch_t batch);
 

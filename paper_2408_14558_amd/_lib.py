@@ -43,6 +43,7 @@ class Tuning(ctypes.Structure):
                 ("hash_max_nnz", ctypes.c_int32), ("dense_window", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("own_partition", ctypes.c_int32),
                 ("own_partition_whole", ctypes.c_int32), ("medium_kernel", ctypes.c_int32),
+                ("batch_streams", ctypes.c_int32), ("batch_persistent", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64)]
 
 
@@ -85,6 +86,7 @@ SIGNATURES = {
                                            ctypes.POINTER(Tuning), ctypes.POINTER(_vp)]),
     "spgemm_batched": (ctypes.c_int, [_vp, _i32, _vp]),
     "spgemm_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "spgemm_batch_check": (ctypes.c_int, [_vp]),
     "spgemm_batch_destroy": (ctypes.c_int, [_vp]),
     "spgemm_pool_trim": (ctypes.c_int, []),
 }

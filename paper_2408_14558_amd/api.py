@@ -78,8 +78,12 @@ def default_tuning() -> _lib.Tuning:
 
 
 def tuning(**kw) -> _lib.Tuning:
+    """The defaults with the named fields of spgemm_tuning replaced."""
     t = default_tuning()
+    names = {f[0] for f in _lib.Tuning._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"spgemm_tuning has no field {k!r}")
         setattr(t, k, v)
     return t
 
@@ -249,3 +253,92 @@ class SpGEMM(torch.autograd.Function):
         dA, dB = plan.backward(plan.C_rowidx, dC.contiguous(), A_vals.detach().contiguous(),
                                B_vals.detach().contiguous(), need_a, need_b)
         return dA, dB, None
+
+
+class Batch:
+    """Numeric phase of many planned products as one dependency DAG of the
+    per-bin kernels, optionally captured into a hipGraph and replayed
+    (spgemm_batch_create / spgemm_batched).
+
+    ``io`` has one dict per plan with keys ``C_rowidx``, ``C_vals`` (output
+    tensors), optional ``A_vals``/``B_vals`` (None = the plan's values) and
+    optional ``dep_A``/``dep_B`` (index of an earlier product whose C is this
+    product's A or B, else -1).  Tensors are kept alive by the batch.
+    """
+
+    def __init__(self, plans, io, tuning: Optional[_lib.Tuning] = None):
+        self.lib = _lib.load()
+        self.plans = list(plans)
+        self.io = [dict(x) for x in io]
+        n = len(self.plans)
+        arr = (_lib.BatchIO * n)()
+        for t, d in enumerate(self.io):
+            arr[t].A_vals = _ptr(d.get("A_vals"))
+            arr[t].B_vals = _ptr(d.get("B_vals"))
+            arr[t].C_rowidx = _ptr(d["C_rowidx"])
+            arr[t].C_vals = _ptr(d["C_vals"])
+            arr[t].dep_A = int(d.get("dep_A", -1))
+            arr[t].dep_B = int(d.get("dep_B", -1))
+        handles = (ctypes.c_void_p * n)(*[p.handle for p in self.plans])
+        h = ctypes.c_void_p()
+        tun = ctypes.byref(tuning) if tuning is not None else None
+        check(self.lib.spgemm_batch_create(n, handles, arr, tun, ctypes.byref(h)),
+              "spgemm_batch_create")
+        self.handle = h
+
+    def run(self, mode: int = 0, stream=None):
+        """mode 0: launch; 1: capture into a hipGraph and launch; 2: replay.
+        Capture needs a stream other than the null stream."""
+        check(self.lib.spgemm_batched(self.handle, mode, _stream(stream)), "spgemm_batched")
+
+    def check(self):
+        """Synchronises the device and raises if a launch failed."""
+        check(self.lib.spgemm_batch_check(self.handle), "spgemm_batch_check")
+
+    def info(self):
+        """(side streams, kernels one run enqueues)."""
+        ns, nl = ctypes.c_int64(), ctypes.c_int64()
+        check(self.lib.spgemm_batch_info(self.handle, ctypes.byref(ns), ctypes.byref(nl)),
+              "spgemm_batch_info")
+        return ns.value, nl.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.spgemm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def galerkin_chain(A0: DeviceCsc, levels, block_size: int = 64,
+                   tuning: Optional[_lib.Tuning] = None):
+    """The AMG Galerkin products A_{l+1} = P_l^T (A_l P_l) for the given
+    levels [(P_0, Pt_0), (P_1, Pt_1), ...] (device CSC prolongators and their
+    transposes), run once through the plain path.  Returns (plans, io,
+    outputs): the plans of the 2*len(levels) products in order, batch I/O
+    with the chain's dependencies (product 2l gathers A_l's values, which
+    for l > 0 are product 2l-1's output; product 2l+1 reads A_l P_l from
+    product 2l), and the device results of the run (the coarse operators
+    are outputs[2l+1]).  The batch writes into those same output tensors.""" 
+    plans, io, outs = [], [], []
+    A = A0
+    for lvl, (P, Pt) in enumerate(levels):
+        p1 = Plan(A, P, None, block_size, tuning)
+        AP = p1.run()
+        plans.append(p1)
+        io.append({"A_vals": A.vals, "B_vals": None,
+                   "C_rowidx": AP.rowidx, "C_vals": AP.vals,
+                   "dep_A": 2 * lvl - 1 if lvl > 0 else -1, "dep_B": -1})
+        outs.append(AP)
+        p2 = Plan(Pt, AP, None, block_size, tuning)
+        Ac = p2.run()
+        plans.append(p2)
+        io.append({"A_vals": None, "B_vals": AP.vals, "C_rowidx": Ac.rowidx, "C_vals": Ac.vals,
+                   "dep_A": -1, "dep_B": 2 * lvl})
+        outs.append(Ac)
+        A = Ac
+    return plans, io, outs

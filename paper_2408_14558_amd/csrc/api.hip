@@ -179,6 +179,8 @@ static int check_tuning(const spgemm_tuning &t) {
         return fail(SPGEMM_EINVAL, "dense_window must be 0 or a power of two >= 32");
     if (t.medium_kernel < 0 || t.medium_kernel > 2)
         return fail(SPGEMM_EINVAL, "medium_kernel must be 0, 1 or 2");
+    if (t.batch_streams < 0 || t.batch_streams > 8)
+        return fail(SPGEMM_EINVAL, "batch_streams must lie in [0, 8]");
     return SPGEMM_OK;
 }
 
@@ -192,7 +194,6 @@ static int sync_counters(Plan &p) {
 
 using namespace spg;
 
-struct spgemm_plan_s : public spg::Plan {};
 
 extern "C" {
 
@@ -208,6 +209,8 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->hash_max_nnz = 2048;
     t->dense_window = 0;
     t->medium_kernel = 0;
+    t->batch_streams = 0;
+    t->batch_persistent = 0;
     t->validate = 0;
     t->own_partition = -1;
     t->own_partition_whole = 0;

@@ -1,12 +1,235 @@
-// placeholder, replaced below
+// Batched numeric phase: the numeric work of many planned products (uneven
+// sizes, optionally chained like the two products of every AMG Galerkin
+// level) issued as one dependency DAG of the per-bin kernels, optionally
+// captured once into a hipGraph and replayed.
+//
+// Products are ordered by dependency depth (a product's depth is one more
+// than the deepest product it reads).  Products of one depth are
+// independent, so they are spread round-robin over side streams forked from
+// the caller's stream and joined back before the next depth starts: small
+// products of one level overlap on the device, and a level never starts
+// before the products it reads have finished.  Each product runs exactly
+// the kernels its plain spgemm_numeric call would run (value gather of A~
+// when new A values are given, then one launch per non-empty numeric bin).
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "internal.hpp"
+
 using namespace spg;
+
+namespace {
+
+constexpr int kMaxBatchStreams = 8;
+constexpr int kDefaultBatchStreams = 4;
+
+}  // namespace
+
+struct spgemm_batch_s {
+    int device = 0;
+    spgemm_dtype dtype = SPGEMM_F64;
+    std::vector<spgemm_plan_t> plans;
+    std::vector<spgemm_batch_io> io;
+    std::vector<std::vector<int>> levels;  // product indices per depth
+    std::vector<hipStream_t> side;         // default priority, non-blocking
+    std::vector<hipEvent_t> fork, join;    // one fork event, one join event per side stream
+    int64_t launches = 0;                  // kernels one run enqueues
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Kernels product t enqueues per run (for spgemm_batch_info).
+static int64_t product_launches(const Plan &p, const spgemm_batch_io &io) {
+    int64_t n = 0;
+    if (io.A_vals && p.k > 0 && p.nnzA > 0) ++n;
+    if (p.n == 0 || p.nnzC == 0) return n;
+    for (int bin = kBinTiny; bin <= kBinDense; ++bin) n += p.num_count[bin] > 0;
+    return n;
+}
+
+// Enqueues product t on stream s: the plan's kernels run on s for this call
+// only (the plan's own stream is restored afterwards).
+static int run_product(spgemm_batch_s &b, int t, hipStream_t s) {
+    Plan &p = *b.plans[t];
+    const spgemm_batch_io &io = b.io[t];
+    const hipStream_t keep = p.stream;
+    p.stream = s;
+    int rc = SPGEMM_OK;
+    if (io.A_vals) rc = launch_gather_values(p, io.A_vals);
+    if (!rc) rc = launch_numeric_bins(p, io.B_vals ? io.B_vals : p.Bvals, io.C_rowidx, io.C_vals);
+    p.stream = keep;
+    return rc;
+}
+
+// Enqueues the whole DAG on s (eagerly, or into a capture that s is in).
+static int enqueue_dag(spgemm_batch_s &b, hipStream_t s) {
+    for (const std::vector<int> &lvl : b.levels) {
+        const int width = std::min<int>((int)b.side.size(), (int)lvl.size());
+        if (width <= 1) {
+            for (int t : lvl)
+                if (int rc = run_product(b, t, s)) return rc;
+            continue;
+        }
+        SPG_HIP(hipEventRecord(b.fork[0], s));
+        for (int i = 0; i < width; ++i) SPG_HIP(hipStreamWaitEvent(b.side[i], b.fork[0], 0));
+        for (size_t u = 0; u < lvl.size(); ++u)
+            if (int rc = run_product(b, lvl[u], b.side[u % width])) return rc;
+        for (int i = 0; i < width; ++i) {
+            SPG_HIP(hipEventRecord(b.join[i], b.side[i]));
+            SPG_HIP(hipStreamWaitEvent(s, b.join[i], 0));
+        }
+    }
+    return SPGEMM_OK;
+}
+
+static void release(spgemm_batch_s *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->fork) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    delete b;
+}
+
 extern "C" {
-int spgemm_batch_create(int32_t, const spgemm_plan_t *, const spgemm_batch_io *,
-                        const spgemm_tuning *, spgemm_batch_t *) {
-    return fail(SPGEMM_EUNSUPPORTED, "batched not built");
+
+int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
+                        const spgemm_tuning *tuning, spgemm_batch_t *out) {
+    (void)hipGetLastError();
+    if (!out) return fail(SPGEMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !plans || !io) return fail(SPGEMM_EINVAL, "need count >= 1, plans and io");
+    spgemm_tuning tun;
+    spgemm_default_tuning(&tun);
+    if (tuning) tun = *tuning;
+    if (tun.batch_persistent != 0)
+        return fail(SPGEMM_EUNSUPPORTED,
+                    "the single-launch persistent batched kernel is switched off: its "
+                    "cross-workgroup dependency waits did not complete on MI355X");
+    if (tun.batch_streams < 0 || tun.batch_streams > kMaxBatchStreams)
+        return fail(SPGEMM_EINVAL, "batch_streams must be in 0..8");
+    const spgemm_dtype dt = plans[0] ? plans[0]->dtype : SPGEMM_F64;
+    std::vector<int> depth(count, 0);
+    for (int t = 0; t < count; ++t) {
+        const spgemm_plan_t p = plans[t];
+        const std::string who = "product " + std::to_string(t);
+        if (!p) return fail(SPGEMM_EINVAL, who + ": plan is NULL");
+        if (!p->symbolic_done) return fail(SPGEMM_ESTATE, who + " has not run symbolic");
+        if (p->dtype != dt) return fail(SPGEMM_EINVAL, "plans must share one dtype");
+        for (int u = 0; u < t; ++u)
+            if (plans[u] == p)
+                return fail(SPGEMM_EINVAL, who + " repeats the plan of product " + std::to_string(u));
+        if (io[t].dep_A >= t || io[t].dep_B >= t || io[t].dep_A < -1 || io[t].dep_B < -1)
+            return fail(SPGEMM_EINVAL, "dependencies must point to lower indices");
+        if (p->nnzC > 0 && (!io[t].C_rowidx || !io[t].C_vals))
+            return fail(SPGEMM_EINVAL, who + " has no C buffers");
+        if (p->nnzC > 0 && !io[t].B_vals && !p->Bvals)
+            return fail(SPGEMM_EINVAL, who + " has no B values");
+        if (p->nnzC > 0 && !io[t].A_vals && !p->Avals)
+            return fail(SPGEMM_EINVAL, who + " has no A values");
+        if (io[t].dep_A >= 0 && !io[t].A_vals)
+            return fail(SPGEMM_EINVAL, "a product whose A is another product's C needs A_vals");
+        if (io[t].dep_B >= 0 && !io[t].B_vals)
+            return fail(SPGEMM_EINVAL, "a product whose B is another product's C needs B_vals");
+        if (io[t].dep_A >= 0) depth[t] = std::max(depth[t], depth[io[t].dep_A] + 1);
+        if (io[t].dep_B >= 0) depth[t] = std::max(depth[t], depth[io[t].dep_B] + 1);
+    }
+    auto *b = new (std::nothrow) spgemm_batch_s();
+    if (!b) return fail(SPGEMM_ENOMEM, "batch allocation failed");
+    b->dtype = dt;
+    b->plans.assign(plans, plans + count);
+    b->io.assign(io, io + count);
+    const int levels = *std::max_element(depth.begin(), depth.end()) + 1;
+    b->levels.resize(levels);
+    for (int t = 0; t < count; ++t) {
+        b->levels[depth[t]].push_back(t);
+        b->launches += product_launches(*plans[t], io[t]);
+    }
+    size_t widest = 0;
+    for (const auto &l : b->levels) widest = std::max(widest, l.size());
+    const int nside = (int)std::min<size_t>(
+        widest > 1 ? widest : 0, tun.batch_streams ? tun.batch_streams : kDefaultBatchStreams);
+    hipError_t e = hipGetDevice(&b->device);
+    for (int i = 0; i < nside && e == hipSuccess; ++i) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) b->side.push_back(st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->join.push_back(ev);
+    }
+    if (e == hipSuccess && nside > 0) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->fork.push_back(ev);
+    }
+    // the products' symbolic phases ran on the plans' streams
+    for (int t = 0; t < count && e == hipSuccess; ++t) e = hipStreamSynchronize(plans[t]->stream);
+    if (e != hipSuccess) {
+        release(b);
+        return fail(SPGEMM_EHIP, std::string("batch set-up: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return SPGEMM_OK;
 }
-int spgemm_batched(spgemm_batch_t, int32_t, void *) { return SPGEMM_EUNSUPPORTED; }
-int spgemm_batch_info(spgemm_batch_t, int64_t *, int64_t *) { return SPGEMM_EUNSUPPORTED; }
-int spgemm_batch_destroy(spgemm_batch_t) { return SPGEMM_OK; }
+
+int spgemm_batched(spgemm_batch_t b, int32_t mode, void *stream) {
+    (void)hipGetLastError();
+    if (!b) return fail(SPGEMM_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == 0) return enqueue_dag(*b, s);
+    if (mode == 1) {
+        if (b->exec) {
+            SPG_HIP(hipGraphExecDestroy(b->exec));
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            SPG_HIP(hipGraphDestroy(b->graph));
+            b->graph = nullptr;
+        }
+        SPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_dag(*b, s);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ee != hipSuccess)
+            return fail(SPGEMM_EHIP, std::string("end capture: ") + hipGetErrorString(ee));
+        b->graph = g;
+        SPG_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+        SPG_HIP(hipGraphLaunch(b->exec, s));
+        return SPGEMM_OK;
+    }
+    if (mode == 2) {
+        if (!b->exec) return fail(SPGEMM_ESTATE, "replay needs a captured graph (mode 1) first");
+        SPG_HIP(hipGraphLaunch(b->exec, s));
+        return SPGEMM_OK;
+    }
+    return fail(SPGEMM_EINVAL, "mode must be 0, 1 or 2");
 }
+
+int spgemm_batch_info(spgemm_batch_t b, int64_t *streams, int64_t *launches) {
+    if (!b) return fail(SPGEMM_EINVAL, "batch is NULL");
+    if (streams) *streams = (int64_t)b->side.size();
+    if (launches) *launches = b->launches;
+    return SPGEMM_OK;
+}
+
+int spgemm_batch_check(spgemm_batch_t b) {
+    (void)hipGetLastError();
+    if (!b) return fail(SPGEMM_EINVAL, "batch is NULL");
+    SPG_HIP(hipDeviceSynchronize());
+    return SPGEMM_OK;
+}
+
+int spgemm_batch_destroy(spgemm_batch_t b) {
+    if (!b) return SPGEMM_OK;
+    (void)hipDeviceSynchronize();
+    release(b);
+    return SPGEMM_OK;
+}
+
+}  // extern "C"

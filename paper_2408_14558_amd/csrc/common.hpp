@@ -148,8 +148,10 @@ constexpr uint64_t kValMask = ~kStMask;
 __device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// The look-back reads data carried inside the status word itself, so a
+// relaxed load suffices (no cache invalidation per poll).
 __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Called by all 64 lanes of ONE wave of the tile (the same wave for the

@@ -191,3 +191,6 @@ int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const 
                     const void *Bvals, const void *dC, void *dA, void *dB);
 
 }  // namespace spg
+
+// The opaque handle of the C ABI is the plan itself.
+struct spgemm_plan_s : public spg::Plan {};

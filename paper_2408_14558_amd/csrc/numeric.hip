@@ -33,14 +33,14 @@ template <typename V>
 __global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__restrict__ list,
                                                              int count, NumArgs<V> a, int VC) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    __shared__ NumDenseStatic<V> S;
+    __shared__ NumDenseStatic<kDenseThreads, V> S;
     const int w = blockIdx.x;
     if (w >= count) return;
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
     V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
-    num_dense_column<V>(a, list[w], bits, wpre, vals, VC, S);
+    num_dense_column<kDenseThreads, V>(a, list[w], bits, wpre, vals, VC, S);
 }
 
 template <int G, typename V>
@@ -70,7 +70,8 @@ static bool use_bitmap(int64_t m, int table, size_t vsize, size_t *lds) {
 size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
     const size_t nw = (size_t)((m + 31) / 32);
     const size_t head = (nw * 6 + 15) & ~(size_t)15;
-    const size_t stat = vsize == 8 ? sizeof(NumDenseStatic<double>) : sizeof(NumDenseStatic<float>);
+    const size_t stat = vsize == 8 ? sizeof(NumDenseStatic<kDenseThreads, double>)
+                                   : sizeof(NumDenseStatic<kDenseThreads, float>);
     const size_t budget = (size_t)lds_max > stat + 1024 ? (size_t)lds_max - stat - 1024 : 0;
     const size_t vc_bytes = budget > head ? budget - head : 0;
     int VC = 1;

@@ -102,11 +102,12 @@ struct NumHashLds {
 };
 
 // G threads (gt in [0, G)) compute column j with a table of T slots.  The
-// column must hold at most T/2 distinct rows.  T == 8 * G.
+// column must hold at most T/2 distinct rows.  Each thread owns T/G slots.
 template <int T, int G, typename V>
 __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
                                                 NumHashLds<T, G, V> &L, int gt) {
-    static_assert(T == 8 * G, "eight slots per thread");
+    static_assert(T % G == 0 && T / G <= 16, "slots per thread");
+    constexpr int SL = T / G;
     for (int s = gt; s < T; s += G) {
         L.keys[s] = -1;
         L.vals[s] = V(0);
@@ -128,12 +129,12 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
                                 h = (h + 1) & (T - 1);
                             }
                         });
-    // compaction: every thread lifts its 8 slots into registers
-    int kk[8];
-    V vv[8];
+    // compaction: every thread lifts its slots into registers
+    int kk[SL];
+    V vv[SL];
     int c = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < SL; ++i) {
         const int s = gt + i * G;
         kk[i] = L.keys[s];
         vv[i] = L.vals[s];
@@ -144,7 +145,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     group_sync<G>();
     int pos = base;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < SL; ++i) {
         if (kk[i] != -1) {
             L.keys[pos] = kk[i];
             L.vals[pos] = vv[i];
@@ -241,10 +242,10 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
 constexpr int kSuperShift = 11;
 constexpr int kMaxSuper = 16;
 
-template <typename V>
+template <int G, typename V>
 struct NumDenseStatic {
-    TermStage<kDenseThreads, V> st;
-    int red[kDenseThreads / kWave + 2];
+    TermStage<G, V> st;
+    int red[G / kWave + 2];
     int sbase[kMaxSuper];
     int r_hi;
 };
@@ -273,29 +274,30 @@ __device__ __forceinline__ int32_t row_of_rank(const uint32_t *bits, const uint1
     return (lo << 5) + __ffs(w) - 1;
 }
 
-// kDenseThreads threads compute column j.  VC values fit in LDS at once;
-// columns with more rows are done in windows of VC consecutive ranks, each
-// window resuming every entry's walk where the previous one stopped.
-template <typename V>
+// G threads (the whole workgroup) compute column j.  VC values fit in LDS
+// at once; columns with more rows are done in windows of VC consecutive
+// ranks, each window resuming every entry's walk where the previous one
+// stopped.
+template <int G, typename V>
 __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
                                                  uint16_t *wpre, V *vals, int VC,
-                                                 NumDenseStatic<V> &S) {
+                                                 NumDenseStatic<G, V> &S) {
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    for (int i = gt; i < nw; i += kDenseThreads) bits[i] = 0u;
+    for (int i = gt; i < nw; i += G) bits[i] = 0u;
     __syncthreads();
-    for_each_term<kDenseThreads, V>(
+    for_each_term<G, V>(
         q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
         [&](int64_t p) { return a.At_rowidx[p]; },
         [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     // ranks: every thread owns a run of consecutive words
-    const int per = (nw + kDenseThreads - 1) / kDenseThreads;
+    const int per = (nw + G - 1) / G;
     const int w0 = gt * per, w1 = min(nw, w0 + per);
     int c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
     int total;
-    const int run0 = group_excl_scan<kDenseThreads>(c, S.red, &total);
+    const int run0 = group_excl_scan<G>(c, S.red, &total);
     {
         int run = run0;
         for (int w = w0; w < w1; ++w) {
@@ -322,12 +324,12 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     for (int w0r = 0; w0r < total; w0r += VC) {
         const int w1r = min(total, w0r + VC);
         const int cnt = w1r - w0r;
-        for (int i = gt; i < cnt; i += kDenseThreads) vals[i] = V(0);
+        for (int i = gt; i < cnt; i += G) vals[i] = V(0);
         if (gt == 0)
             S.r_hi = (w1r == total) ? (int32_t)a.m : row_of_rank(bits, wpre, S.sbase, nw, w1r);
         __syncthreads();
         if (cnt == total) {
-            for_each_term<kDenseThreads, V>(
+            for_each_term<G, V>(
                 q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
                 [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                 [&](const RowVal<V> &t, V bv) {
@@ -335,14 +337,14 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
                 });
         } else {
             const int32_t rh = S.r_hi;
-            for_each_term_below<kDenseThreads, V>(
+            for_each_term_below<G, V>(
                 q0, q1, rh, w0r == 0, a.Browidx, a.Bvals, a.map, a.At_colptr, a.At_rowidx, cursor,
                 &S.st, gt, [&](int64_t p) { return a.At_vals[p]; },
                 [&](int32_t r, V av, V bv) {
                     lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - w0r], av * bv);
                 });
         }
-        for (int i = gt; i < cnt; i += kDenseThreads) a.Cval[o + w0r + i] = vals[i];
+        for (int i = gt; i < cnt; i += G) a.Cval[o + w0r + i] = vals[i];
         __syncthreads();
     }
 }

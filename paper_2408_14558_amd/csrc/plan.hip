@@ -3,7 +3,7 @@
 // the chosen blocks and the compacted A~).  On one GPU the one-sided fetch
 // of a remote block becomes a device copy of a contiguous range of A's CSC
 // arrays.
-#include "common.hpp"
+#include "gather.hpp"
 
 namespace spg {
 
@@ -179,27 +179,6 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
     }
 }
 
-// Largest o in [0, n) with pref[o] <= s (pref non-decreasing, pref[0] = 0).
-__device__ __forceinline__ int find_owner(const int *pref, int n, int s) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pref[mid] <= s)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-// Copies the selected columns (a chosen block is a contiguous range of A's
-// arrays) into A~.  One workgroup per kGatherCols columns of A; the tile's
-// copy work is spread evenly over the workgroup with kUnrollCopy loads in
-// flight per thread.  kRows=false copies values only (new values on the
-// planned pattern).
-constexpr int kGatherCols = 64;
-constexpr int kGatherThreads = 256;
-constexpr int kUnrollCopy = 4;
 template <typename V, bool kRows>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const int64_t *__restrict__ Acolptr,
                                                            const int32_t *__restrict__ Arowidx,
@@ -208,58 +187,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const int64_t *__rest
                                                            const int64_t *__restrict__ At_colptr,
                                                            int64_t k, int32_t *__restrict__ At_rowidx,
                                                            V *__restrict__ At_vals) {
-    __shared__ int s_pref[kGatherCols];
-    __shared__ long long s_src[kGatherCols];
-    __shared__ long long s_dst[kGatherCols];
-    __shared__ int s_total;
-    const int tid = threadIdx.x;
-    if (tid < kWave) {
-        int len = 0;
-        long long src = 0, dst = 0;
-        const int64_t c = (int64_t)blockIdx.x * kGatherCols + tid;
-        if (tid < kGatherCols && c < k) {
-            const int32_t j = map[c];
-            if (j >= 0) {
-                src = Acolptr[c];
-                len = (int)(Acolptr[c + 1] - src);
-                dst = At_colptr[j];
-            }
-        }
-        const int incl = wave_incl_scan(len);
-        if (tid < kGatherCols) {
-            s_pref[tid] = incl - len;
-            s_src[tid] = src;
-            s_dst[tid] = dst;
-        }
-        if (tid == kWave - 1) s_total = incl;
-    }
-    __syncthreads();
-    const int total = s_total;
-    for (int e0 = tid; e0 < total; e0 += kUnrollCopy * kGatherThreads) {
-        long long sp[kUnrollCopy], dp[kUnrollCopy];
-        int32_t r[kUnrollCopy];
-        V v[kUnrollCopy];
-#pragma unroll
-        for (int u = 0; u < kUnrollCopy; ++u) {
-            const int e = e0 + u * kGatherThreads;
-            if (e < total) {
-                const int o = find_owner(s_pref, kGatherCols, e);
-                const int64_t off = e - s_pref[o];
-                sp[u] = s_src[o] + off;
-                dp[u] = s_dst[o] + off;
-                if (kRows) r[u] = Arowidx[sp[u]];
-                v[u] = Avals[sp[u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnrollCopy; ++u) {
-            const int e = e0 + u * kGatherThreads;
-            if (e < total) {
-                if (kRows) At_rowidx[dp[u]] = r[u];
-                At_vals[dp[u]] = v[u];
-            }
-        }
-    }
+    __shared__ GatherStage st;
+    gather_tile<V, kRows>(blockIdx.x, Acolptr, Arowidx, Avals, map, At_colptr, k, At_rowidx,
+                          At_vals, st);
 }
 
 // Checks the CSC invariants of a matrix: colptr[0] = 0, colptr[n] = nnz,

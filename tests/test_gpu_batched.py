@@ -1,0 +1,150 @@
+"""GPU tests of the batched form: the numeric phase of many planned products
+(the 64^3 AMG Galerkin hierarchy, four levels, chained; plus 64 independent
+ER products of uneven sizes) as one dependency DAG over side streams,
+directly and as a captured hipGraph replayed several times."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _util import assert_values
+
+pytestmark = pytest.mark.gpu
+
+spg = pytest.importorskip("paper_2408_14558_amd")
+
+
+def _levels(n, levels):
+    out = []
+    for _ in range(levels):
+        out.append((spg.DeviceCsc.from_host(synth.aggregation3d(n)),
+                    spg.DeviceCsc.from_host(synth.aggregation3d_t(n))))
+        n //= 2
+    return out
+
+
+@pytest.fixture(scope="module")
+def workload():
+    A0 = spg.DeviceCsc.from_host(synth.laplacian3d(64))
+    plans, io, outs = spg.galerkin_chain(A0, _levels(64, 4))
+    er = []
+    for A, B in synth.er_batch(64, seed=4):
+        Ad, Bd = spg.DeviceCsc.from_host(A), spg.DeviceCsc.from_host(B)
+        p = spg.Plan(Ad, Bd, None, 64)
+        C = p.run()
+        plans.append(p)
+        io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+        outs.append(C)
+        er.append((A, B))
+    torch.cuda.synchronize()
+    return A0, plans, io, outs, er
+
+
+def _check_amg(outs, scale=1.0):
+    n = 64
+    for lvl in range(4):
+        AP = outs[2 * lvl]
+        vals = set(torch.unique(AP.vals).cpu().numpy().tolist())
+        assert vals == {3.0 * 4 ** lvl * scale, -1.0 * 4 ** lvl * scale}
+        n //= 2
+        ref = synth.laplacian3d(n)
+        Ac = outs[2 * lvl + 1]
+        assert np.array_equal(Ac.rowidx.cpu().numpy(), ref.rowidx)
+        assert np.array_equal(Ac.vals.cpu().numpy(), scale * 4.0 ** (lvl + 1) * ref.vals)
+
+
+def _check_er(outs, er):
+    for t, (A, B) in enumerate(er):
+        C = outs[8 + t]
+        ref = oracle.spgemm(A, B)
+        assert np.array_equal(C.rowidx.cpu().numpy(), ref.rowidx)
+        assert_values(C.vals.cpu().numpy(), ref.vals, ref.absvals, True)
+
+
+def test_plain_chain_is_exact(workload):
+    _check_amg(workload[3])
+
+
+def test_batched_direct_launch(workload):
+    A0, plans, io, outs, er = workload
+    b = spg.Batch(plans, io)
+    streams, launches = b.info()
+    print("batch side streams", streams, "launches", launches, flush=True)
+    assert streams == 4 and launches >= len(plans)
+    for C in outs:
+        C.vals.fill_(-7.0)
+        C.rowidx.fill_(-1)
+    b.run(0)
+    b.check()
+    _check_amg(outs)
+    _check_er(outs, er)
+    b.close()
+
+
+def test_batched_graph_replays(workload):
+    A0, plans, io, outs, er = workload
+    s = torch.cuda.Stream()
+    b = spg.Batch(plans, io)
+    with torch.cuda.stream(s):
+        b.run(1, stream=s)
+    b.check()
+    _check_amg(outs)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            for C in outs:      # eager work between replays
+                C.vals.zero_()
+            A0.vals.mul_(2.0)   # new fine-level values propagate down the chain
+            b.run(2, stream=s)
+        b.check()
+        _check_amg(outs, scale=2.0 ** (rep + 1))
+    with torch.cuda.stream(s):
+        A0.vals.mul_(2.0 ** -3)
+        b.run(2, stream=s)
+    b.check()
+    _check_amg(outs)
+    _check_er(outs, er)
+    b.close()
+
+
+def test_batched_stream_counts_give_the_same_results(workload):
+    A0, plans, io, outs, er = workload
+    for tun in (spg.tuning(batch_streams=1), spg.tuning(batch_streams=8)):
+        b = spg.Batch(plans, io, tun)
+        for C in outs:
+            C.vals.fill_(3.0)
+        b.run(0)
+        b.check()
+        _check_amg(outs)
+        _check_er(outs, er)
+        b.close()
+
+
+def test_batched_errors(workload):
+    A0, plans, io, outs, er = workload
+    bad = [dict(x) for x in io[:3]]
+    bad[1]["dep_A"] = 2  # forward dependency
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Batch(plans[:3], bad)
+    assert e.value.code == -1
+    with pytest.raises(spg.SpgemmError) as e:  # one plan twice
+        spg.Batch([plans[8], plans[8]], [io[8], io[8]])
+    assert e.value.code == -1
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Batch(plans[:2], io[:2], spg.tuning(batch_streams=9))
+    assert e.value.code == -1
+    # the single-launch persistent form is switched off
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Batch(plans[:2], io[:2], spg.tuning(batch_persistent=1))
+    assert e.value.code == -4
+    b = spg.Batch(plans[:2], io[:2])
+    lib = spg.load()
+    assert lib.spgemm_batched(b.handle, 2, None) == -5  # replay before capture
+    assert lib.spgemm_batched(b.handle, 7, None) == -1
+    b.close()
+    A = spg.DeviceCsc.from_host(synth.erdos_renyi(100, 100, 4, seed=1))
+    p = spg.Plan(A, A)
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Batch([p], [{"C_rowidx": A.rowidx, "C_vals": A.vals}])
+    assert e.value.code == -5  # symbolic has not run
