@@ -61,6 +61,7 @@ __all__ = [
     "uniform_values",
     "partition_offsets",
     "column_slice",
+    "transpose",
     "from_triplets",
     "workload",
 ]
@@ -113,6 +114,15 @@ def column_slice(M: CSC, lo: int, hi: int) -> CSC:
     a, b = int(M.colptr[lo]), int(M.colptr[hi])
     return CSC(M.nrows, hi - lo, (M.colptr[lo:hi + 1] - a).astype(np.int64),
                M.rowidx[a:b].copy(), M.vals[a:b].copy())
+
+
+def transpose(M: CSC) -> CSC:
+    """M^T in CSC (a stable counting sort of the entries by row)."""
+    cols = np.repeat(np.arange(M.ncols, dtype=np.int64), np.diff(M.colptr))
+    order = np.argsort(M.rowidx, kind="stable")
+    colptr = np.zeros(M.nrows + 1, dtype=np.int64)
+    colptr[1:] = np.cumsum(np.bincount(M.rowidx, minlength=M.nrows))
+    return CSC(M.ncols, M.nrows, colptr, cols[order].astype(np.int32), M.vals[order].copy())
 
 
 def partition_offsets(k: int, P: int) -> np.ndarray:
