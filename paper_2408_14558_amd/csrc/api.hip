@@ -328,6 +328,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_slist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_cur = cv.take<int32_t>(pl.nnzB);
+    const size_t o_tst = cv.take<int64_t>(pl.nnzB);
+    const size_t o_tln = cv.take<int32_t>(pl.nnzB);
     const size_t ws_bytes = cv.off;
     if (tun.workspace_limit > 0 && (int64_t)ws_bytes > tun.workspace_limit) {
         delete p;
@@ -373,6 +375,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.sym_list = (int32_t *)(w + o_slist);
     pl.num_list = (int32_t *)(w + o_nlist);
     pl.cursor = (int32_t *)(w + o_cur);
+    pl.tstart = (int64_t *)(w + o_tst);
+    pl.tlen = (int32_t *)(w + o_tln);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);
     std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
@@ -495,11 +499,8 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
         *nnzC = 0;
         return SPGEMM_OK;
     }
-    // reset the symbolic counters: colptr ticket, flops .. num_count
-    SPG_HIP(hipMemsetAsync(&p.ctr->tickets[kTkColptr], 0, sizeof(unsigned long long), p.stream));
-    SPG_HIP(hipMemsetAsync(&p.ctr->nnzC, 0, sizeof(long long), p.stream));
-    SPG_HIP(hipMemsetAsync(&p.ctr->flops, 0, sizeof(DevCounters) - offsetof(DevCounters, flops),
-                           p.stream));
+    // the plan's init cleared the symbolic counters; a later run clears them itself
+    if (p.symbolic_runs++ > 0 && (rc = launch_symbolic_reset(p))) return rc;
     if ((rc = launch_flop_bin(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));

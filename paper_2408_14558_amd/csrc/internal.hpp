@@ -78,6 +78,16 @@ struct DevCounters {
 
 enum Ticket { kTkRank = 0, kTkSelect = 1, kTkColptr = 2, kTkExport = 3 };
 
+// Where the products of entry q of B_i live in A~: positions [start[q],
+// start[q] + len[q]) of A~'s arrays, i.e. the column map[row of q] (len is 0
+// when A~ holds no column for that row).  Filled once per symbolic phase by
+// the flops kernel, so the term walkers reach A~ with one load per entry
+// instead of the chain row id -> map -> column pointers.
+struct TermRange {
+    const int64_t *start;
+    const int32_t *len;
+};
+
 struct Thresholds {
     int tiny_max_flop;
     int sym_hash_max[4];  // flop limit per symbolic hash bin (0 = bin unused)
@@ -139,6 +149,9 @@ struct Plan {
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
+    int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
+    int32_t *tlen = nullptr;      // nnzB
+    TermRange term_range() const { return TermRange{tstart, tlen}; }
     int lds_max = 65536;          // LDS bytes one workgroup may use on this device
 
     // host view of the counters (inside the pinned block)
@@ -146,6 +159,7 @@ struct Plan {
 
     // symbolic results
     bool symbolic_done = false;
+    int symbolic_runs = 0;  // the plan's init clears the counters for the first run
     int64_t *C_colptr = nullptr;
     int64_t nnzC = -1;
     int64_t flops = -1;
@@ -186,6 +200,7 @@ int launch_export_blocks(Plan &p, int64_t *blocks);
 int launch_flop_bin(Plan &p);
 int launch_symbolic_bins(Plan &p);
 int launch_colptr_scan(Plan &p);
+int launch_symbolic_reset(Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);

@@ -3,19 +3,31 @@
 
 namespace spg {
 
-// Up to 64*8 terms per column: one wave per column, four columns per
-// workgroup, 64*8 LDS slots per wave for merging equal rows.
-constexpr int kWaveSortMax = 8 * kWave;
-
-template <typename V>
+// Up to 64*EMAX terms per column: one wave per column, four columns per
+// workgroup, 64*EMAX LDS slots per wave for merging equal rows.  EMAX = 4
+// (tiny columns up to 256 products, the default) keeps the register file
+// small enough for four waves per SIMD.
+template <typename V, int EMAX, bool kPacked>
 __global__ __launch_bounds__(256) void k_num_tiny(const int32_t *__restrict__ list, int count,
                                                   NumArgs<V> a) {
-    __shared__ int s_rows[4][kWaveSortMax];
-    __shared__ V s_vals[4][kWaveSortMax];
+    __shared__ int s_rows[4][EMAX * kWave];
+    __shared__ V s_vals[4][EMAX * kWave];
     const int wv = threadIdx.x >> 6;
     const int w = blockIdx.x * 4 + wv;
     if (w >= count) return;
-    num_wave_dispatch<V>(a, list[w], s_rows[wv], s_vals[wv]);
+    num_wave_dispatch<V, EMAX, kPacked>(a, list[w], s_rows[wv], s_vals[wv]);
+}
+
+template <typename V, int EMAX>
+static void num_tiny_launch(const Plan &p, const int32_t *list, const NumArgs<V> &a) {
+    const int cnt = p.num_count[kBinTiny];
+    const dim3 grid((cnt + 3) / 4);
+    if (p.m < kPackedRowLimit)
+        hipLaunchKernelGGL((k_num_tiny<V, EMAX, true>), grid, dim3(256), 0, p.stream, list, cnt,
+                           a);
+    else
+        hipLaunchKernelGGL((k_num_tiny<V, EMAX, false>), grid, dim3(256), 0, p.stream, list, cnt,
+                           a);
 }
 
 template <int T, int G, typename V>
@@ -105,15 +117,16 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
 
 template <typename V>
 static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
-    NumArgs<V> a{p.m,         p.Bcolptr,  p.Browidx,           Bvals,      p.map,
-                 p.At_colptr, p.At_rowidx, (const V *)p.At_vals, p.C_colptr, Crow,
-                 Cval,        p.flop,      p.cursor};
+    NumArgs<V> a{p.m,        p.Bcolptr, p.term_range(), Bvals, p.At_rowidx, (const V *)p.At_vals,
+                 p.C_colptr, Crow,      Cval,           p.flop, p.cursor};
     const int64_t n = p.n;
     auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
     if (p.num_count[kBinTiny] > 0)
     {
-        hipLaunchKernelGGL(k_num_tiny<V>, dim3((p.num_count[kBinTiny] + 3) / 4), dim3(256), 0,
-                           p.stream, list(kBinTiny), p.num_count[kBinTiny], a);
+        if (p.th.tiny_max_flop <= 4 * kWave)
+            num_tiny_launch<V, 4>(p, list(kBinTiny), a);
+        else
+            num_tiny_launch<V, 8>(p, list(kBinTiny), a);
         SPG_LAUNCHED("k_num_tiny");
     }
     int rc;

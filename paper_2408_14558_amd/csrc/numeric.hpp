@@ -13,10 +13,8 @@ template <typename V>
 struct NumArgs {
     int64_t m;
     const int64_t *Bcolptr;
-    const int32_t *Browidx;
+    TermRange tr;  // per entry of B_i: its products' positions in A~
     const V *Bvals;
-    const int32_t *map;
-    const int64_t *At_colptr;
     const int32_t *At_rowidx;
     const V *At_vals;
     const int64_t *Ccolptr;
@@ -30,13 +28,22 @@ struct NumArgs {
 // Terms are gathered into registers, sorted by row across the wave, equal
 // rows are merged by LDS atomics at their output slot, and the column is
 // written out coalesced.  s_rows/s_vals: this wave's 64*E LDS slots.
-template <int E, typename V>
+//
+// kPacked (rows below 2^22): the key of a term is (row << 9) | slot, where
+// slot (< 64*8) is where the term's value waits in LDS, so the sort moves one
+// 32-bit word per term instead of a key and a value; after the sort every
+// lane fetches its values from LDS by slot.
+constexpr int kSlotBits = 9;
+constexpr int64_t kPackedRowLimit = int64_t(1) << (31 - kSlotBits);
+
+template <int E, typename V, bool kPacked>
 __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, int *s_rows,
                                                 V *s_vals) {
+    static_assert(E * kWave <= (1 << kSlotBits), "slot ids need kSlotBits bits");
     int64_t p[E];
     V bv[E];
-    wave_terms<E, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.Browidx, a.Bvals, a.map, a.At_colptr, p,
-                     bv);
+    wave_terms<E, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.tr, a.Bvals, p, bv);
+    const int lane = lane_id();
     int key[E];
     V val[E];
 #pragma unroll
@@ -44,12 +51,32 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, 
         key[r] = kNoRow;
         val[r] = V(0);
         if (p[r] >= 0) {
-            key[r] = a.At_rowidx[p[r]];
-            val[r] = a.At_vals[p[r]] * bv[r];
+            const int32_t row = a.At_rowidx[p[r]];
+            const V v = a.At_vals[p[r]] * bv[r];
+            if constexpr (kPacked) {
+                const int slot = r * kWave + lane;
+                key[r] = (row << kSlotBits) | slot;
+                s_vals[slot] = v;
+            } else {
+                key[r] = row;
+                val[r] = v;
+            }
         }
     }
-    wave_sort<E, true, V>(key, val);
-    const int lane = lane_id();
+    if constexpr (kPacked) {
+        wave_sort<E, false, V>(key, val);
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (key[r] != kNoRow) {
+                val[r] = s_vals[key[r] & ((1 << kSlotBits) - 1)];
+                key[r] >>= kSlotBits;
+            }
+        }
+        wave_sync();  // every value is read before the slots are reused below
+    } else {
+        wave_sort<E, true, V>(key, val);
+    }
     const int prev_last = __shfl_up(key[E - 1], 1);
     bool hd[E];
     int nh = 0;
@@ -83,14 +110,17 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, 
     wave_sync();
 }
 
-template <typename V>
+// Picks the register width from the column's flops; EMAX bounds it (a
+// kernel built for EMAX = 4 needs no registers for 8 terms per lane).
+template <typename V, int EMAX, bool kPacked>
 __device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j, int *s_rows,
                                                   V *s_vals) {
+    static_assert(EMAX == 4 || EMAX == 8, "EMAX is 4 or 8");
     const int64_t f = a.flop[j];
-    if (f <= kWave) num_wave_column<1, V>(a, j, s_rows, s_vals);
-    else if (f <= 2 * kWave) num_wave_column<2, V>(a, j, s_rows, s_vals);
-    else if (f <= 4 * kWave) num_wave_column<4, V>(a, j, s_rows, s_vals);
-    else num_wave_column<8, V>(a, j, s_rows, s_vals);
+    if (f <= kWave) num_wave_column<1, V, kPacked>(a, j, s_rows, s_vals);
+    else if (f <= 2 * kWave) num_wave_column<2, V, kPacked>(a, j, s_rows, s_vals);
+    else if (EMAX == 4 || f <= 4 * kWave) num_wave_column<4, V, kPacked>(a, j, s_rows, s_vals);
+    else num_wave_column<EMAX, V, kPacked>(a, j, s_rows, s_vals);
 }
 
 // --- hash: LDS table, compaction, bitonic sort -----------------------------
@@ -113,7 +143,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
         L.vals[s] = V(0);
     }
     group_sync<G>();
-    for_each_term<G, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.Browidx, a.Bvals, a.map, a.At_colptr,
+    for_each_term<G, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.tr, a.Bvals,
                         &L.st, gt,
                         [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                         [&](const RowVal<V> &t, V bv) {
@@ -203,7 +233,7 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
     for (int i = gt; i < nw; i += G) bits[i] = 0u;
     __syncthreads();
-    for_each_term<G, V>(q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
+    for_each_term<G, V>(q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
                         [&](int64_t p) { return a.At_rowidx[p]; },
                         [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     const int per = (nw + G - 1) / G;
@@ -224,7 +254,7 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     }
     for (int i = gt; i < total; i += G) vals[i] = V(0);
     __syncthreads();
-    for_each_term<G, V>(q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
+    for_each_term<G, V>(q0, q1, a.tr, a.Bvals, &S.st, gt,
                         [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                         [&](const RowVal<V> &t, V bv) {
                             const uint32_t w = bits[t.r >> 5];
@@ -288,7 +318,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     for (int i = gt; i < nw; i += G) bits[i] = 0u;
     __syncthreads();
     for_each_term<G, V>(
-        q0, q1, a.Browidx, (const V *)nullptr, a.map, a.At_colptr, &S.st, gt,
+        q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
         [&](int64_t p) { return a.At_rowidx[p]; },
         [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     // ranks: every thread owns a run of consecutive words
@@ -330,7 +360,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
         __syncthreads();
         if (cnt == total) {
             for_each_term<G, V>(
-                q0, q1, a.Browidx, a.Bvals, a.map, a.At_colptr, &S.st, gt,
+                q0, q1, a.tr, a.Bvals, &S.st, gt,
                 [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                 [&](const RowVal<V> &t, V bv) {
                     lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, t.r)], t.v * bv);
@@ -338,7 +368,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
         } else {
             const int32_t rh = S.r_hi;
             for_each_term_below<G, V>(
-                q0, q1, rh, w0r == 0, a.Browidx, a.Bvals, a.map, a.At_colptr, a.At_rowidx, cursor,
+                q0, q1, rh, w0r == 0, a.tr, a.Bvals, a.At_rowidx, cursor,
                 &S.st, gt, [&](int64_t p) { return a.At_vals[p]; },
                 [&](int32_t r, V av, V bv) {
                     lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - w0r], av * bv);

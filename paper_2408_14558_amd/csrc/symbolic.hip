@@ -43,7 +43,27 @@ __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const
     }
 }
 
-// Sparse flops of every column of B_i and its symbolic bin.  S lanes walk
+// Records where entry q of B_i finds its products in A~ (the column of A~
+// that map assigns to q's row) and returns their number.
+__device__ __forceinline__ int term_range(int64_t q, const int32_t *__restrict__ Browidx,
+                                          const int32_t *__restrict__ map,
+                                          const int64_t *__restrict__ At_colptr,
+                                          int64_t *__restrict__ tstart,
+                                          int32_t *__restrict__ tlen) {
+    const int32_t jt = map[Browidx[q]];
+    long long start = 0;
+    int len = 0;
+    if (jt >= 0) {
+        start = At_colptr[jt];
+        len = (int)(At_colptr[jt + 1] - start);
+    }
+    tstart[q] = start;
+    tlen[q] = len;
+    return len;
+}
+
+// Sparse flops of every column of B_i and its symbolic bin, and the term
+// range of every entry of B_i.  S lanes walk
 // one column (S picked from the average column length); columns with more
 // than 16*S entries are summed by a whole wave afterwards.
 constexpr int kFlopThreads = 256;
@@ -51,6 +71,7 @@ template <int S>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
+    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
     DevCounters *__restrict__ ctr) {
@@ -84,10 +105,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         const int64_t q0 = Bcolptr[j0 + lc], q1 = Bcolptr[j0 + lc + 1];
         if (q1 - q0 <= 16 * S) {
 #pragma unroll 4
-            for (int64_t q = q0 + sub; q < q1; q += S) {
-                const int32_t jt = map[Browidx[q]];
-                if (jt >= 0) acc += At_colptr[jt + 1] - At_colptr[jt];
-            }
+            for (int64_t q = q0 + sub; q < q1; q += S) acc += term_range(q, Browidx, map, At_colptr, tstart, tlen);
         } else {
             deferred = true;
         }
@@ -103,10 +121,8 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         const int t = s_long[li];
         const int64_t q1 = Bcolptr[j0 + t + 1];
         long long a2 = 0;
-        for (int64_t q = Bcolptr[j0 + t] + lane; q < q1; q += kWave) {
-            const int32_t jt = map[Browidx[q]];
-            if (jt >= 0) a2 += At_colptr[jt + 1] - At_colptr[jt];
-        }
+        for (int64_t q = Bcolptr[j0 + t] + lane; q < q1; q += kWave)
+            a2 += term_range(q, Browidx, map, At_colptr, tstart, tlen);
         a2 = wave_sum(a2);
         if (lane == 0) s_f[t] = a2;
     }
@@ -129,14 +145,11 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
 
 // --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
 template <int E>
-__device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1,
-                                              const int32_t *__restrict__ Browidx,
-                                              const int32_t *__restrict__ map,
-                                              const int64_t *__restrict__ At_colptr,
+__device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1, TermRange tr,
                                               const int32_t *__restrict__ At_rowidx) {
     int64_t p[E];
     float bv[E];
-    wave_terms<E, float>(q0, q1, Browidx, nullptr, map, At_colptr, p, bv);
+    wave_terms<E, float>(q0, q1, tr, nullptr, p, bv);
     int key[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) key[r] = p[r] >= 0 ? At_rowidx[p[r]] : kNoRow;
@@ -151,11 +164,10 @@ __device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1,
     return wave_sum(nh);
 }
 
+template <int EMAX>
 __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ list, int count,
                                                   const int64_t *__restrict__ Bcolptr,
-                                                  const int32_t *__restrict__ Browidx,
-                                                  const int32_t *__restrict__ map,
-                                                  const int64_t *__restrict__ At_colptr,
+                                                  TermRange tr,
                                                   const int32_t *__restrict__ At_rowidx,
                                                   const int64_t *__restrict__ flop,
                                                   int64_t *__restrict__ Ccount) {
@@ -164,10 +176,10 @@ __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ li
     const int32_t j = list[w];
     const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1], f = flop[j];
     int c;
-    if (f <= kWave) c = sym_wave_count<1>(q0, q1, Browidx, map, At_colptr, At_rowidx);
-    else if (f <= 2 * kWave) c = sym_wave_count<2>(q0, q1, Browidx, map, At_colptr, At_rowidx);
-    else if (f <= 4 * kWave) c = sym_wave_count<4>(q0, q1, Browidx, map, At_colptr, At_rowidx);
-    else c = sym_wave_count<8>(q0, q1, Browidx, map, At_colptr, At_rowidx);
+    if (f <= kWave) c = sym_wave_count<1>(q0, q1, tr, At_rowidx);
+    else if (f <= 2 * kWave) c = sym_wave_count<2>(q0, q1, tr, At_rowidx);
+    else if (EMAX == 4 || f <= 4 * kWave) c = sym_wave_count<4>(q0, q1, tr, At_rowidx);
+    else c = sym_wave_count<EMAX>(q0, q1, tr, At_rowidx);
     if (lane_id() == 0) Ccount[j] = c;
 }
 
@@ -181,9 +193,7 @@ struct SymHashLds {
 template <int T, int G>
 __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
     const int32_t *__restrict__ list, int count, const int64_t *__restrict__ Bcolptr,
-    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
-    const int64_t *__restrict__ At_colptr, const int32_t *__restrict__ At_rowidx,
-    int64_t *__restrict__ Ccount) {
+    TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount) {
     constexpr int CPW = G < 256 ? 256 / G : 1;
     __shared__ SymHashLds<T, G> lds[CPW];
     const int grp = threadIdx.x / G, gt = threadIdx.x % G;
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
     for (int s = gt; s < T; s += G) L.keys[s] = -1;
     group_sync<G>();
     int inserted = 0;
-    for_each_term<G, float>(Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, &L.st,
+    for_each_term<G, float>(Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st,
                             gt, [&](int64_t p) { return At_rowidx[p]; },
                             [&](int32_t r, float) {
                                 uint32_t h = hash_slot<T>(r);
@@ -229,9 +239,7 @@ struct SymDenseLds {
 
 __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
-    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
-    const int64_t *__restrict__ At_colptr, const int32_t *__restrict__ At_rowidx,
-    int64_t *__restrict__ Ccount) {
+    TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount) {
     extern __shared__ uint32_t s_bits[];
     __shared__ SymDenseLds L;
     const int w = blockIdx.x;
@@ -242,7 +250,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
     __syncthreads();
     for_each_term<kDenseThreads, float>(
-        Bcolptr[j], Bcolptr[j + 1], Browidx, nullptr, map, At_colptr, &L.st, gt,
+        Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
         [&](int64_t p) { return At_rowidx[p]; },
         [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
     int c = 0;
@@ -308,15 +316,37 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->num_count, num_list, n);
 }
 
+// Clears what one symbolic phase accumulates (the colptr scan ticket, nnzC,
+// flops and the bin counters), for a second symbolic run on one plan.
+__global__ void k_symbolic_reset(DevCounters *__restrict__ ctr) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ctr->tickets[kTkColptr] = 0;
+        ctr->nnzC = 0;
+        ctr->flops.v = 0;
+    }
+    if (t < kNumBins) {
+        ctr->sym_count[t].v = 0;
+        ctr->num_count[t].v = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+int launch_symbolic_reset(Plan &p) {
+    hipLaunchKernelGGL(k_symbolic_reset, dim3(1), dim3(64), 0, p.stream, p.ctr);
+    SPG_LAUNCHED("k_symbolic_reset");
+    return SPGEMM_OK;
+}
+
 template <int S>
 static int flop_bin_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
     const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
-                       p.Browidx, p.map, p.At_colptr, p.th, p.flop, p.sym_bin, p.sym_list,
+                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.flop,
+                       p.sym_bin, p.sym_list,
                        p.C_colptr, p.st_colptr, p.n_col_tiles, p.ctr);
     SPG_LAUNCHED("k_flop_bin");
     return SPGEMM_OK;
@@ -338,8 +368,8 @@ static int sym_hash_launch(Plan &p, int bin) {
     constexpr int threads = G < 256 ? 256 : G;
     const unsigned g = (unsigned)((cnt + CPW - 1) / CPW);
     hipLaunchKernelGGL((k_sym_hash<T, G>), dim3(g), dim3(threads), 0, p.stream,
-                       p.sym_list + (int64_t)bin * p.n, cnt, p.Bcolptr, p.Browidx, p.map,
-                       p.At_colptr, p.At_rowidx, p.C_colptr);
+                       p.sym_list + (int64_t)bin * p.n, cnt, p.Bcolptr, p.term_range(),
+                       p.At_rowidx, p.C_colptr);
     SPG_LAUNCHED("k_sym_hash<" + std::to_string(T) + ">");
     return SPGEMM_OK;
 }
@@ -349,10 +379,14 @@ int launch_symbolic_bins(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     if (p.sym_count[kBinTiny] > 0) {
         const unsigned g = (unsigned)((p.sym_count[kBinTiny] + 3) / 4);
-        hipLaunchKernelGGL(k_sym_tiny, dim3(g), dim3(256), 0, p.stream,
-                           p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
-                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.flop,
-                           p.C_colptr);
+        if (p.th.tiny_max_flop <= 4 * kWave)
+            hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream,
+                               p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
+                               p.Bcolptr, p.term_range(), p.At_rowidx, p.flop, p.C_colptr);
+        else
+            hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream,
+                               p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
+                               p.Bcolptr, p.term_range(), p.At_rowidx, p.flop, p.C_colptr);
         SPG_LAUNCHED("k_sym_tiny");
     }
     int rc;
@@ -368,7 +402,7 @@ int launch_symbolic_bins(Plan &p) {
         hipLaunchKernelGGL(k_sym_dense, dim3((unsigned)p.sym_count[kBinDense]),
                            dim3(kDenseThreads), lds, p.stream,
                            p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
-                           p.Bcolptr, p.Browidx, p.map, p.At_colptr, p.At_rowidx, p.C_colptr);
+                           p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr);
         SPG_LAUNCHED("k_sym_dense");
     }
     return SPGEMM_OK;

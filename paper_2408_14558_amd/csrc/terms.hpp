@@ -42,11 +42,8 @@ constexpr int kUnroll = 4;
 // kUnroll loads per thread are in flight before the first use.  All G
 // threads must call it (it synchronises the group).
 template <int G, typename V, typename LD, typename AP>
-__device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1,
-                                              const int32_t *__restrict__ Browidx,
+__device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange tr,
                                               const V *__restrict__ Bvals,
-                                              const int32_t *__restrict__ map,
-                                              const int64_t *__restrict__ At_colptr,
                                               TermStage<G, V> *st, int gt, LD &&ld, AP &&ap) {
     using Item = decltype(ld((int64_t)0));
     constexpr int TEAM = G < kWave ? G : kWave;
@@ -60,12 +57,9 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1,
         int len = 0;
         V bv = V(0);
         if (q < q1) {
-            const int32_t jt = map[Browidx[q]];
-            if (jt >= 0) {
-                start = At_colptr[jt];
-                len = (int)(At_colptr[jt + 1] - start);
-                if (Bvals) bv = Bvals[q];
-            }
+            start = tr.start[q];
+            len = tr.len[q];
+            if (Bvals) bv = Bvals[q];
         }
         if (len > kShortLen) {
             const int slot = atomicAdd(&st->nlong, 1);
@@ -109,11 +103,8 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1,
 // For each such term: ap(row, ldv(p), bv).  G >= 64 (teams are whole waves).
 template <int G, typename V, typename LDV, typename AP>
 __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int32_t r_hi,
-                                                    bool first,
-                                                    const int32_t *__restrict__ Browidx,
+                                                    bool first, TermRange tr,
                                                     const V *__restrict__ Bvals,
-                                                    const int32_t *__restrict__ map,
-                                                    const int64_t *__restrict__ At_colptr,
                                                     const int32_t *__restrict__ At_rowidx,
                                                     int32_t *__restrict__ cursor,
                                                     TermStage<G, V> *st, int gt, LDV &&ldv,
@@ -126,10 +117,10 @@ __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int3
         group_sync<G>();
         const int64_t q = qb + gt;
         if (q < q1) {
-            const int32_t jt = map[Browidx[q]];
-            if (jt >= 0) {
-                const long long c0 = At_colptr[jt];
-                const long long end = At_colptr[jt + 1];
+            const int len = tr.len[q];
+            if (len > 0) {
+                const long long c0 = tr.start[q];
+                const long long end = c0 + len;
                 const int rel = first ? 0 : cursor[q - q0];
                 const V bv = Bvals[q];
                 if (end - c0 > kShortLen) {
@@ -190,11 +181,8 @@ __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int3
 // slot r of lane l receives term r*64 + l (p = its position in A~, bv =
 // b_kj); slots past the last term get p = -1.  All 64 lanes must call it.
 template <int E, typename V>
-__device__ __forceinline__ void wave_terms(int64_t q0, int64_t q1,
-                                           const int32_t *__restrict__ Browidx,
+__device__ __forceinline__ void wave_terms(int64_t q0, int64_t q1, TermRange tr,
                                            const V *__restrict__ Bvals,
-                                           const int32_t *__restrict__ map,
-                                           const int64_t *__restrict__ At_colptr,
                                            int64_t (&p)[E], V (&bv)[E]) {
     const int lane = lane_id();
 #pragma unroll
@@ -209,12 +197,9 @@ __device__ __forceinline__ void wave_terms(int64_t q0, int64_t q1,
         long long start = 0;
         V b = V(0);
         if (q < q1) {
-            const int32_t jt = map[Browidx[q]];
-            if (jt >= 0) {
-                start = At_colptr[jt];
-                len = (int)(At_colptr[jt + 1] - start);
-                if (Bvals) b = Bvals[q];
-            }
+            start = tr.start[q];
+            len = tr.len[q];
+            if (Bvals) b = Bvals[q];
         }
         const int incl = wave_incl_scan(len);
         const int S = __shfl(incl, kWave - 1);

@@ -219,6 +219,41 @@ def test_numeric_rerun_with_new_values():
         assert_values(vals.cpu().numpy(), ref.vals, ref.absvals, True)
 
 
+@pytest.mark.parametrize("tiny", [256, 512])
+def test_symbolic_rerun_on_one_plan(tiny):
+    """A second symbolic phase on the same plan (it clears its own counters)
+    gives the same pointers, bins and product; both tiny register widths."""
+    A = synth.rmat(12, 8, 0.57, 0.19, 0.19, 0.05, seed=9)
+    ref = oracle.spgemm(A, A)
+    Ad = _dev(A, torch.float64)
+    with spg.Plan(Ad, Ad, None, 64, tuning=spg.tuning(tiny_max_flop=tiny)) as p:
+        c1 = p.symbolic().cpu().numpy()
+        f1, s1, n1 = [t.cpu().numpy() for t in p.export_bins()]
+        st1 = p.stats()
+        r1, v1 = p.numeric()
+        c2 = p.symbolic().cpu().numpy()
+        f2, s2, n2 = [t.cpu().numpy() for t in p.export_bins()]
+        st2 = p.stats()
+        r2, v2 = p.numeric()
+    assert np.array_equal(c1, ref.colptr) and np.array_equal(c2, ref.colptr)
+    assert np.array_equal(f1, f2) and np.array_equal(s1, s2) and np.array_equal(n1, n2)
+    assert st1["flops"] == st2["flops"] and st1["num_bins"] == st2["num_bins"]
+    assert st1["sym_bins"] == st2["sym_bins"] and st2["nnz_C"] == ref.colptr[-1]
+    for r, v in ((r1, v1), (r2, v2)):
+        assert np.array_equal(r.cpu().numpy(), ref.rowidx)
+        assert_values(v.cpu().numpy(), ref.vals, ref.absvals, True)
+
+
+@pytest.mark.parametrize("tiny,d", [(256, 24), (512, 40)])
+def test_tall_a_uses_unpacked_tiny_keys(tiny, d):
+    """m above 2^22 rows: the tiny-column sort carries (row, value) pairs
+    instead of packed (row, slot) keys; 8*d products per column take 4 or 8
+    terms per lane."""
+    A = synth.erdos_renyi(5_000_000, 1500, 8, seed=21)
+    B = synth.erdos_renyi(1500, 300, d, seed=22)
+    check_local(A, B, synth.partition_offsets(1500, 3), 32, tun=spg.tuning(tiny_max_flop=tiny))
+
+
 def test_validation_on_device_rejects_unsorted_rows():
     A = synth.erdos_renyi(100, 50, 4, seed=1)
     bad = synth.CSC(A.nrows, A.ncols, A.colptr, A.rowidx.copy(), A.vals)
