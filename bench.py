@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and backward measurements")
+    ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
+                    help="override a spgemm_tuning field for the main workload (repeatable)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes, 5 times "
                          "(reference for HBM byte counters), and print its bandwidth")
@@ -270,8 +272,11 @@ def main():
 
     ev = []  # (numeric start, numeric end) per timed step
 
+    tun = spg.tuning(**{k: int(v) for k, v in (t.split("=", 1) for t in args.tune)}) \
+        if args.tune else None
+
     def step(record):
-        p = spg.Plan(Ad, Bd, w["offs"], w["b"])
+        p = spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun)
         p.symbolic()
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
@@ -298,7 +303,7 @@ def main():
     # sizes of the workload (from the library's own statistics), and the
     # numeric phase alone: back-to-back launches on one plan between two
     # events, so the launch gap of a lone call does not count
-    with spg.Plan(Ad, Bd, w["offs"], w["b"]) as p:
+    with spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun) as p:
         p.symbolic()
         rows, vals = p.numeric()
         st = p.stats()
@@ -320,7 +325,8 @@ def main():
         "vs_baseline": None,
         "dtype": w["dtype"],
         "data": "synthetic",
-        "config": {"workload": w["desc"], **w["config"]},
+        "config": {"workload": w["desc"], **w["config"],
+                   **({"tuning": dict(t.split("=", 1) for t in args.tune)} if args.tune else {})},
         "roofline": {
             "bound": "hbm",
             "kernel": "numeric phase (spgemm_numeric)",

@@ -71,14 +71,17 @@ typedef struct {
     int32_t dense_window;       /* most output rows one dense-bin pass holds in LDS
                                    (0 = as many as LDS allows, else a power of 2 >= 32) */
     int32_t validate;           /* 1: check the CSC invariants of A and B_i on the device */
-    int32_t own_partition;      /* >= 0: B_i belongs to this partition of A ... */
-    int32_t own_partition_whole;/* ... and 1 selects that partition's nonzero columns whole */
+    int32_t own_partition;      /* >= 0: B_i's own partition of A (local to the caller) ... */
+    int32_t own_partition_whole;/* ... and 1 takes all of its nonzero columns into A~ (every
+                                   group of it chosen) instead of applying the block rule of
+                                   Alg. 2 to it as to the remote partitions; C_i is the same */
     int32_t medium_kernel;      /* medium numeric bins: 0 = choose by m, 1 = LDS hash and
                                    sort, 2 = LDS bitmap and rank */
     int32_t batch_streams;      /* batched: side streams independent products spread over
                                    (0 = 4, at most 8) */
     int32_t batch_persistent;   /* must be 0: the single-launch persistent form of the
                                    batch is switched off (SPGEMM_EUNSUPPORTED) */
+    int32_t reserved[2];        /* must be 0 */
     int64_t workspace_limit;    /* bytes of device workspace a plan may take; 0 = no limit */
 } spgemm_tuning;
 

@@ -62,8 +62,8 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_rows_of_b.argtypes = [ctypes.c_int64, ctypes.c_int64, _i32p, _u8p]
     lib.oracle_block_select.argtypes = [ctypes.c_int64, _i64p, _u8p, ctypes.c_int32, _i64p,
-                                        ctypes.c_int64, _u8p, _i32p, _i64p, _i64p,
-                                        ctypes.c_int64, _i64p, _i64p]
+                                        ctypes.c_int64, ctypes.c_int32, _u8p, _i32p, _i64p,
+                                        _i64p, ctypes.c_int64, _i64p, _i64p]
     lib.oracle_gather.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _i32p, _i64p, _i32p, _f64p]
     lib.oracle_column_flops.argtypes = [ctypes.c_int64, _i64p, ctypes.c_int64, _i64p, _i32p, _i64p]
     lib.oracle_spgemm_count.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p,
@@ -124,7 +124,7 @@ class Selection(NamedTuple):
     K: int
 
 
-def block_select(A, H: np.ndarray, offsets, b: int) -> Selection:
+def block_select(A, H: np.ndarray, offsets, b: int, own_whole: int = -1) -> Selection:
     _, k, Ac, _, _ = _arrays(A)
     H = np.ascontiguousarray(H, dtype=np.uint8)
     offs = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -137,7 +137,7 @@ def block_select(A, H: np.ndarray, offsets, b: int) -> Selection:
     cap = k + P
     blocks = np.zeros((max(cap, 1), 2), dtype=np.int64)
     _check(_load().oracle_block_select(k, _p(Ac, _i64p), _p(H, _u8p), P, _p(offs, _i64p), b,
-                                       _p(sel, _u8p), _p(mp, _i32p), ctypes.byref(kt),
+                                       int(own_whole), _p(sel, _u8p), _p(mp, _i32p), ctypes.byref(kt),
                                        _p(blocks, _i64p), cap, ctypes.byref(M),
                                        ctypes.byref(K)), "block_select")
     return Selection(sel, mp, kt.value, blocks[:M.value].copy(), K.value)
@@ -245,12 +245,12 @@ class Local(NamedTuple):
     C: Product
 
 
-def local_product(A, Bi, offsets, b: int, cols=None) -> Local:
+def local_product(A, Bi, offsets, b: int, cols=None, own_whole: int = -1) -> Local:
     """One partition's step of Alg. 1: H_i, block selection, A~, flops and
     C_i.  C_i is computed from the original A, not from A~, so agreement with
     a path that multiplies A~ also shows the gather lost nothing."""
     H = rows_of_b(int(A.ncols), Bi)
-    s = block_select(A, H, offsets, b)
+    s = block_select(A, H, offsets, b, own_whole)
     At = gather(A, s.map, s.kt)
     flop = column_flops(A, Bi)
     C = spgemm(A, Bi, cols)

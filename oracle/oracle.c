@@ -57,7 +57,10 @@ int oracle_rows_of_b(int64_t k, int64_t nnzB, const int32_t *Browidx, uint8_t *H
  *     the last run possibly shorter, so K_r = ceil(nzc_r / b);
  *   - a group is chosen when any of its columns has H = 1; a chosen group
  *     adds the pair (first column, last column) to R and M grows by one;
- *   - the same rule is applied to every partition, the caller's own included.
+ *   - the same rule is applied to every partition, the caller's own included,
+ *     unless own_whole names a partition: that partition is local to the
+ *     caller (Sec. III-A: only remote blocks are fetched), so all of its
+ *     groups are chosen and its nonzero columns enter A~ whole.
  *
  * Outputs:
  *   sel[c]  = 1 when column c lies in a chosen group, else 0 (length k)
@@ -68,7 +71,7 @@ int oracle_rows_of_b(int64_t k, int64_t nnzB, const int32_t *Browidx, uint8_t *H
  *   *M      = number of chosen groups, *K = total number of groups
  */
 int oracle_block_select(int64_t k, const int64_t *Acolptr, const uint8_t *H,
-                        int32_t P, const int64_t *offsets, int64_t b,
+                        int32_t P, const int64_t *offsets, int64_t b, int32_t own_whole,
                         uint8_t *sel, int32_t *map, int64_t *kt,
                         int64_t *blocks, int64_t blocks_cap,
                         int64_t *M, int64_t *K)
@@ -100,8 +103,8 @@ int oracle_block_select(int64_t k, const int64_t *Acolptr, const uint8_t *H,
         for (int64_t g = 0; g < groups; ++g) {
             int64_t lo = g * b;
             int64_t hi = lo + b < nzc ? lo + b : nzc;
-            int choose = 0;
-            for (int64_t j = lo; j < hi; ++j) {
+            int choose = r == own_whole;
+            for (int64_t j = lo; j < hi && !choose; ++j) {
                 if (H[ids[j]]) {
                     choose = 1;
                     break;

@@ -44,6 +44,7 @@ class Tuning(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("own_partition", ctypes.c_int32),
                 ("own_partition_whole", ctypes.c_int32), ("medium_kernel", ctypes.c_int32),
                 ("batch_streams", ctypes.c_int32), ("batch_persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2),
                 ("workspace_limit", ctypes.c_int64)]
 
 
@@ -95,14 +96,16 @@ _lib = None
 
 
 def load():
-    """Loads libspgemm.so once; raises if it is missing."""
+    """Loads libspgemm.so once (or the build named by the SPGEMM_LIBRARY
+    environment variable); raises if it is missing."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built: the HIP library is required "
+    path = os.environ.get("SPGEMM_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: the HIP library is required "
                            "(build it with __graft_entry__.build())")
-    lib = ctypes.CDLL(LIB_PATH)
+    lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.restype = res

@@ -181,7 +181,36 @@ static int check_tuning(const spgemm_tuning &t) {
         return fail(SPGEMM_EINVAL, "medium_kernel must be 0, 1 or 2");
     if (t.batch_streams < 0 || t.batch_streams > 8)
         return fail(SPGEMM_EINVAL, "batch_streams must lie in [0, 8]");
+    if (t.reserved[0] != 0 || t.reserved[1] != 0)
+        return fail(SPGEMM_EINVAL, "reserved tuning fields must be 0");
     return SPGEMM_OK;
+}
+
+// Room for the symbolic phase to keep the row bitmap of each of its dense
+// columns, so the numeric phase loads it instead of walking the products
+// again.  Optional: without it (too large, above workspace_limit, or the
+// allocation fails) the numeric phase rebuilds the bitmaps.
+constexpr size_t kDenseBitsMax = size_t(8) << 30;
+
+static void reserve_dense_bits(Plan &p) {
+    const size_t nw = (size_t)((p.m + 31) / 32);
+    const size_t need = (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
+    const bool fits = need > 0 && need <= kDenseBitsMax &&
+                      (p.tun.workspace_limit <= 0 ||
+                       p.ws_bytes + need <= (size_t)p.tun.workspace_limit);
+    if (fits && p.dense_bits_bytes >= need) return;
+    pool_put(p.dense_bits, p.dense_bits_bytes, false, p.device, p.stream);
+    p.dense_bits = nullptr;
+    p.dense_bits_bytes = 0;
+    if (!fits) return;
+    void *ptr = nullptr;
+    size_t got = 0;
+    if (pool_get(need, false, p.device, p.stream, &ptr, &got) == SPGEMM_OK) {
+        p.dense_bits = (uint32_t *)ptr;
+        p.dense_bits_bytes = got;
+    } else {
+        (void)hipGetLastError();
+    }
 }
 
 static int sync_counters(Plan &p) {
@@ -211,6 +240,7 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->medium_kernel = 0;
     t->batch_streams = 0;
     t->batch_persistent = 0;
+    t->reserved[0] = t->reserved[1] = 0;
     t->validate = 0;
     t->own_partition = -1;
     t->own_partition_whole = 0;
@@ -246,8 +276,6 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     if ((rc = check_tuning(tun))) return rc;
     if (tun.own_partition_whole && (tun.own_partition < 0 || tun.own_partition >= P))
         return fail(SPGEMM_EINVAL, "own_partition_whole needs own_partition in [0, P)");
-    if (tun.own_partition_whole)
-        return fail(SPGEMM_EUNSUPPORTED, "own_partition_whole is not available in this build");
 
     auto *p = new (std::nothrow) spgemm_plan_s();
     if (!p) return fail(SPGEMM_ENOMEM, "plan allocation failed");
@@ -329,6 +357,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_cur = cv.take<int32_t>(pl.nnzB);
     const size_t o_tst = cv.take<int64_t>(pl.nnzB);
+    const size_t o_dsl = cv.take<int32_t>(pl.n);
     const size_t o_tln = cv.take<int32_t>(pl.nnzB);
     const size_t ws_bytes = cv.off;
     if (tun.workspace_limit > 0 && (int64_t)ws_bytes > tun.workspace_limit) {
@@ -376,6 +405,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.num_list = (int32_t *)(w + o_nlist);
     pl.cursor = (int32_t *)(w + o_cur);
     pl.tstart = (int64_t *)(w + o_tst);
+    pl.dense_slot = (int32_t *)(w + o_dsl);
     pl.tlen = (int32_t *)(w + o_tln);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);
@@ -505,6 +535,7 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));
     for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
+    reserve_dense_bits(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
     if ((rc = launch_colptr_scan(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
@@ -556,6 +587,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     Plan &p = *plan;
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
     pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream);
+    pool_put(p.dense_bits, p.dense_bits_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;
 }

@@ -149,6 +149,9 @@ struct Plan {
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
+    int32_t *dense_slot = nullptr;  // n: the column's bitmap in dense_bits, or -1
+    uint32_t *dense_bits = nullptr; // symbolic's row bitmaps of its dense columns (pooled)
+    size_t dense_bits_bytes = 0;
     int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
     int32_t *tlen = nullptr;      // nnzB
     TermRange term_range() const { return TermRange{tstart, tlen}; }

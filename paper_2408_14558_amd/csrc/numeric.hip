@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__re
 
 template <int G, typename V>
 __global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ list, int count,
-                                                  NumArgs<V> a) {
+                                                  NumArgs<V> a, int vcap) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ NumBitmapStatic<G, V> S;
     if ((int)blockIdx.x >= count) return;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ li
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
     V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
-    num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, S);
+    num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, vcap, S);
 }
 
 // Bitmap instead of hash for a medium bin when the bitmap is not much
@@ -76,9 +76,9 @@ static bool use_bitmap(int64_t m, int table, size_t vsize, size_t *lds) {
     return nw <= (size_t)8 * table && *lds <= 96 * 1024;
 }
 
-// Dynamic LDS of the dense kernel and the number of values (a power of
-// two) one rank window holds: whatever the device's per-workgroup LDS leaves
-// after the bitmap, the word ranks and the kernel's static part.
+// Dynamic LDS of the dense kernel and the number of values one rank window
+// holds: whatever the device's per-workgroup LDS leaves after the bitmap,
+// the word ranks and the kernel's static part.
 size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
     const size_t nw = (size_t)((m + 31) / 32);
     const size_t head = (nw * 6 + 15) & ~(size_t)15;
@@ -86,8 +86,7 @@ size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
                                    : sizeof(NumDenseStatic<kDenseThreads, float>);
     const size_t budget = (size_t)lds_max > stat + 1024 ? (size_t)lds_max - stat - 1024 : 0;
     const size_t vc_bytes = budget > head ? budget - head : 0;
-    int VC = 1;
-    while ((size_t)(VC * 2) * vsize <= vc_bytes && VC < (1 << 16)) VC *= 2;
+    const int VC = (int)std::max<size_t>(1, std::min<size_t>(vc_bytes / vsize, 1 << 20));
     *VC_out = VC;
     return head + (size_t)VC * vsize;
 }
@@ -102,7 +101,7 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     if ((mk == 0 && fits) || (mk == 2 && lds <= 96 * 1024)) {
         constexpr int GB = T <= 512 ? 128 : 256;
         hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(cnt), dim3(GB), lds, p.stream,
-                           p.num_list + (int64_t)bin * p.n, cnt, a);
+                           p.num_list + (int64_t)bin * p.n, cnt, a, T / 2);
         SPG_LAUNCHED("k_num_bitmap<" + std::to_string(GB) + ">");
         return SPGEMM_OK;
     }
@@ -117,8 +116,9 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
 
 template <typename V>
 static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
-    NumArgs<V> a{p.m,        p.Bcolptr, p.term_range(), Bvals, p.At_rowidx, (const V *)p.At_vals,
-                 p.C_colptr, Crow,      Cval,           p.flop, p.cursor};
+    NumArgs<V> a{p.m,        p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, (const V *)p.At_vals,
+                 p.C_colptr, Crow,      Cval,           p.flop, p.cursor,    p.dense_slot,
+                 p.dense_bits};
     const int64_t n = p.n;
     auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
     if (p.num_count[kBinTiny] > 0)

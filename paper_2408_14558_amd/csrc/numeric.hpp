@@ -22,6 +22,8 @@ struct NumArgs {
     V *Cval;
     const int64_t *flop;  // sparse flops per column (picks the wave-sort width)
     int32_t *cursor;      // nnz(B_i) scratch for windowed dense columns
+    const int32_t *dense_slot;   // per column: its row bitmap in dense_bits, or -1
+    const uint32_t *dense_bits;  // row bitmaps kept by the symbolic phase
 };
 
 // --- wave sort: <= 64*E terms, one wave, registers ---------------------------
@@ -213,6 +215,97 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     group_sync<G>();
 }
 
+// --- bitmap ranks -------------------------------------------------------------
+// A bitmap of the column's rows in LDS (bits[nw]) gives every row its output
+// position: its rank, the number of set bits before it.  wpre[w] holds the
+// rank of word w's first bit, relative to its superblock of 2048 words,
+// whose rank is sbase[w >> 11] (no superblocks: sbase == nullptr and ranks
+// must stay below 65536).
+constexpr int kSuperShift = 11;
+constexpr int kMaxSuper = 16;
+
+// Fills wpre (and sbase), stages the row ids of ranks [0, cap) in stage[]
+// (LDS, int32) and returns the number of set bits.  Every wave takes a
+// power-of-two range of consecutive words (at most 2048 when superblocks are
+// used, so every superblock starts a wave's range) and its lanes consecutive
+// words, so the LDS accesses are free of bank conflicts.  All G threads
+// call; ends with a group barrier.  red: G/64 + 2 ints of LDS.
+template <int G>
+__device__ __forceinline__ int bitmap_ranks(const uint32_t *bits, uint16_t *wpre, int *sbase,
+                                            int nw, int *red, int32_t *stage, int cap) {
+    constexpr int NW = G / kWave;
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    int per = kWave;
+    while (per * NW < nw) per <<= 1;
+    const int wb = min(nw, wv * per), we = min(nw, wb + per);
+    int mine = 0;
+    for (int w = wb + lane; w < we; w += kWave) mine += __popc(bits[w]);
+    const int wave_total = wave_sum(mine);
+    int total;
+    const int pre = group_excl_scan<G>(lane == 0 ? wave_total : 0, red, &total);
+    const int off = __shfl(pre, 0);
+    int sb = 0;
+    if (sbase) {
+        if (lane == 0 && wb < we && (wb & ((1 << kSuperShift) - 1)) == 0)
+            sbase[wb >> kSuperShift] = off;
+        __syncthreads();
+        if (wb < we) sb = sbase[wb >> kSuperShift];
+    }
+    int run = off;
+    for (int w0 = wb; w0 < we; w0 += kWave) {
+        const int w = w0 + lane;
+        uint32_t b = w < we ? bits[w] : 0u;
+        const int c = __popc(b);
+        const int incl = wave_incl_scan(c);
+        int rk = run + incl - c;
+        if (w < we) {
+            wpre[w] = (uint16_t)(rk - sb);
+            while (b && rk < cap) {
+                stage[rk] = (w << 5) + __ffs(b) - 1;
+                ++rk;
+                b &= b - 1;
+            }
+        }
+        run += __shfl(incl, kWave - 1);
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ int word_rank(const uint16_t *wpre, const int *sbase, int w) {
+    return (sbase ? sbase[w >> kSuperShift] : 0) + wpre[w];
+}
+
+// Writes the set rows of the bitmap in ascending order to out[0, total):
+// ranks [0, cap) were staged by bitmap_ranks; later ones are staged here,
+// cap at a time.  Copies are coalesced.  All G threads call; ends with a
+// group barrier.
+template <int G>
+__device__ __forceinline__ void bitmap_rows_out(const uint32_t *bits, const uint16_t *wpre,
+                                                const int *sbase, int nw, int total,
+                                                int32_t *stage, int cap,
+                                                int32_t *__restrict__ out) {
+    for (int r0 = 0; r0 < total; r0 += cap) {
+        const int r1 = min(total, r0 + cap);
+        if (r0 > 0) {
+            for (int w = threadIdx.x; w < nw; w += G) {
+                uint32_t b = bits[w];
+                if (!b) continue;
+                int rk = word_rank(wpre, sbase, w);
+                if (rk >= r1 || rk + __popc(b) <= r0) continue;
+                while (b) {
+                    if (rk >= r0 && rk < r1) stage[rk - r0] = (w << 5) + __ffs(b) - 1;
+                    ++rk;
+                    b &= b - 1;
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < r1 - r0; i += G) out[r0 + i] = stage[i];
+        __syncthreads();
+    }
+}
+
 // --- bitmap: medium columns when m is small --------------------------------
 // A bitmap of all m rows plus per-word prefix counts in LDS give every row
 // of the column its final position (its rank), so values are accumulated at
@@ -226,7 +319,7 @@ struct NumBitmapStatic {
 
 template <int G, typename V>
 __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
-                                                  uint16_t *wpre, V *vals,
+                                                  uint16_t *wpre, V *vals, int vcap,
                                                   NumBitmapStatic<G, V> &S) {
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
@@ -236,22 +329,12 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     for_each_term<G, V>(q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
                         [&](int64_t p) { return a.At_rowidx[p]; },
                         [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
-    const int per = (nw + G - 1) / G;
-    const int w0 = gt * per, w1 = min(nw, w0 + per);
-    int c = 0;
-    for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
-    int total;
-    int run = group_excl_scan<G>(c, S.red, &total);
+    // vals holds every value of the column: as int32 slots it stages the row ids
+    const int cap = vcap * (int)(sizeof(V) / sizeof(int32_t));
+    int32_t *stage = reinterpret_cast<int32_t *>(vals);
+    const int total = bitmap_ranks<G>(bits, wpre, nullptr, nw, S.red, stage, cap);
     const int64_t o = a.Ccolptr[j];
-    for (int w = w0; w < w1; ++w) {
-        wpre[w] = (uint16_t)run;
-        uint32_t b = bits[w];
-        while (b) {
-            a.Crow[o + run] = (w << 5) + __ffs(b) - 1;
-            ++run;
-            b &= b - 1;
-        }
-    }
+    bitmap_rows_out<G>(bits, wpre, nullptr, nw, total, stage, cap, a.Crow + o);
     for (int i = gt; i < total; i += G) vals[i] = V(0);
     __syncthreads();
     for_each_term<G, V>(q0, q1, a.tr, a.Bvals, &S.st, gt,
@@ -266,23 +349,30 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
 }
 
 // --- dense: bitmap of all m rows + rank windows -----------------------------
+// Loads in flight per lane on the long A~ columns of dense output columns
+// (a windowed walk re-reads what lies past a window's end, so it stays short).
+#ifndef SPG_DENSE_UNROLL
+#define SPG_DENSE_UNROLL 4
+#endif
+constexpr int kDenseUnroll = SPG_DENSE_UNROLL;
+// Entries of B(:,j) staged at once by the dense kernel (its 1024 threads all
+// walk the long ones): a small stage leaves LDS for larger value windows.
+#ifndef SPG_DENSE_CHUNK
+#define SPG_DENSE_CHUNK 256
+#endif
+constexpr int kDenseChunk = SPG_DENSE_CHUNK;
 // LDS (dynamic): bits[nw] u32 | wpre[nw] u16 | vals[VC].  wpre holds each
 // word's rank relative to its superblock of 2048 words (65536 rows), whose
 // absolute rank is in sbase, so ranks above 65535 need no 32-bit table.
-constexpr int kSuperShift = 11;
-constexpr int kMaxSuper = 16;
 
 template <int G, typename V>
 struct NumDenseStatic {
-    TermStage<G, V> st;
+    TermStageCursor<kDenseChunk < G ? kDenseChunk : G, V> st;
     int red[G / kWave + 2];
     int sbase[kMaxSuper];
     int r_hi;
 };
 
-__device__ __forceinline__ int word_rank(const uint16_t *wpre, const int *sbase, int w) {
-    return sbase[w >> kSuperShift] + wpre[w];
-}
 
 __device__ __forceinline__ int rank_of(const uint32_t *bits, const uint16_t *wpre,
                                        const int *sbase, int32_t r) {
@@ -315,41 +405,24 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    for (int i = gt; i < nw; i += G) bits[i] = 0u;
-    __syncthreads();
-    for_each_term<G, V>(
-        q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
-        [&](int64_t p) { return a.At_rowidx[p]; },
-        [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
-    // ranks: every thread owns a run of consecutive words
-    const int per = (nw + G - 1) / G;
-    const int w0 = gt * per, w1 = min(nw, w0 + per);
-    int c = 0;
-    for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
-    int total;
-    const int run0 = group_excl_scan<G>(c, S.red, &total);
-    {
-        int run = run0;
-        for (int w = w0; w < w1; ++w) {
-            if ((w & ((1 << kSuperShift) - 1)) == 0) S.sbase[w >> kSuperShift] = run;
-            run += __popc(bits[w]);
-        }
+    const int slot = a.dense_slot[j];
+    if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
+        const uint32_t *src = a.dense_bits + (size_t)slot * nw;
+        for (int i = gt; i < nw; i += G) bits[i] = src[i];
+        __syncthreads();
+    } else {
+        for (int i = gt; i < nw; i += G) bits[i] = 0u;
+        __syncthreads();
+        for_each_term<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
+            q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
+            [&](int64_t p) { return a.At_rowidx[p]; },
+            [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     }
-    __syncthreads();
+    const int cap = (int)(((size_t)VC * sizeof(V)) / sizeof(int32_t));
+    int32_t *stage = reinterpret_cast<int32_t *>(vals);
+    const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, stage, cap);
     const int64_t o = a.Ccolptr[j];
-    {
-        int run = run0;
-        for (int w = w0; w < w1; ++w) {
-            wpre[w] = (uint16_t)(run - S.sbase[w >> kSuperShift]);
-            uint32_t b = bits[w];
-            while (b) {
-                a.Crow[o + run] = (w << 5) + __ffs(b) - 1;
-                ++run;
-                b &= b - 1;
-            }
-        }
-    }
-    __syncthreads();
+    bitmap_rows_out<G>(bits, wpre, S.sbase, nw, total, stage, cap, a.Crow + o);
     int32_t *cursor = a.cursor + q0;
     for (int w0r = 0; w0r < total; w0r += VC) {
         const int w1r = min(total, w0r + VC);
@@ -359,7 +432,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
             S.r_hi = (w1r == total) ? (int32_t)a.m : row_of_rank(bits, wpre, S.sbase, nw, w1r);
         __syncthreads();
         if (cnt == total) {
-            for_each_term<G, V>(
+            for_each_term<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
                 q0, q1, a.tr, a.Bvals, &S.st, gt,
                 [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                 [&](const RowVal<V> &t, V bv) {
@@ -367,7 +440,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
                 });
         } else {
             const int32_t rh = S.r_hi;
-            for_each_term_below<G, V>(
+            for_each_term_below<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
                 q0, q1, rh, w0r == 0, a.tr, a.Bvals, a.At_rowidx, cursor,
                 &S.st, gt, [&](int64_t p) { return a.At_vals[p]; },
                 [&](int32_t r, V av, V bv) {

@@ -39,13 +39,16 @@ __global__ void k_mark_rows(const int32_t *__restrict__ Browidx, int64_t nnzB,
 // Rank of every nonzero column among the nonzero columns of its partition
 // (a scan segmented at partition starts), its Alg. 2 group
 // g = group_base[part] + rank / b, and the group's hit flag (any column of
-// the group named by H).  Also records each group's first and last column
-// and counts |H|, nzc and the number of groups K.
+// the group named by H; every group of partition own_whole when that
+// partition is the caller's own and is taken whole).  Also records each
+// group's first and last column and counts |H|, nzc and the number of
+// groups K.
 __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
     const int64_t *__restrict__ Acolptr, const uint8_t *__restrict__ H,
     const RankTile *__restrict__ tiles, const int64_t *__restrict__ group_base, int64_t b,
     int32_t *__restrict__ gid, uint8_t *__restrict__ hit, int32_t *__restrict__ gfirst,
-    int32_t *__restrict__ glast, uint64_t *__restrict__ status, DevCounters *__restrict__ ctr) {
+    int32_t *__restrict__ glast, uint64_t *__restrict__ status, int32_t own_whole,
+    DevCounters *__restrict__ ctr) {
     __shared__ long long s_ticket;
     __shared__ int s_tmp[kScanThreads / kWave + 1];
     __shared__ long long s_prefix;
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
         if (nz[i]) {
             const int64_t g = base + rank / b;
             gid[c] = (int32_t)g;
-            if (H[c]) hit[g] = 1;
+            if (H[c] || d.part == own_whole) hit[g] = 1;
             const long long r = rank % b;
             if (r == 0) gfirst[g] = (int32_t)c;
             if (r == b - 1 || rank == part_last) glast[g] = (int32_t)c;
@@ -286,7 +289,8 @@ int launch_plan_kernels(Plan &p) {
     if (p.n_rank_tiles > 0)
         hipLaunchKernelGGL(k_rank_groups, dim3((unsigned)p.n_rank_tiles), dim3(kScanThreads), 0,
                            p.stream, p.Acolptr, p.H, p.rank_tiles, p.group_base, p.b, p.gid,
-                           p.hit, p.gfirst, p.glast, p.st_rank, p.ctr);
+                           p.hit, p.gfirst, p.glast, p.st_rank,
+                           p.tun.own_partition_whole ? p.tun.own_partition : -1, p.ctr);
     if (p.n_sel_tiles > 0)
         hipLaunchKernelGGL(k_select, dim3((unsigned)p.n_sel_tiles), dim3(kScanThreads), 0,
                            p.stream, p.Acolptr, p.k, p.gid, p.hit, p.gfirst, p.map, p.colid,

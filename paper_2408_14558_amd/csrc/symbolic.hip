@@ -71,7 +71,7 @@ template <int S>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
-    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen,
+    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ dense_slot,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
     DevCounters *__restrict__ ctr) {
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         const int64_t j = j0 + tid;
         const long long f = s_f[tid];
         flop[j] = f;
+        dense_slot[j] = -1;
         const int b = sym_bin_of(f, th);
         sym_bin[j] = b;
         s_bin[tid] = b;
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
 }
 
 // --- dense bin: bitmap of all m rows in LDS ---------------------------------
+constexpr int kSymDenseUnroll = 8;  // row loads in flight per lane on long A~ columns
 struct SymDenseLds {
     TermStage<kDenseThreads, float> st;
     int red[kDenseThreads / kWave + 2];
@@ -239,7 +241,8 @@ struct SymDenseLds {
 
 __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
-    TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount) {
+    TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
+    uint32_t *__restrict__ keep_bits, int32_t *__restrict__ dense_slot) {
     extern __shared__ uint32_t s_bits[];
     __shared__ SymDenseLds L;
     const int w = blockIdx.x;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int gt = threadIdx.x;
     for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
     __syncthreads();
-    for_each_term<kDenseThreads, float>(
+    for_each_term<kDenseThreads, float, kSymDenseUnroll>(
         Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
         [&](int64_t p) { return At_rowidx[p]; },
         [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
@@ -258,6 +261,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     int total;
     (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
     if (gt == 0) Ccount[j] = total;
+    if (keep_bits) {  // the numeric phase reuses this bitmap
+        uint32_t *dst = keep_bits + (size_t)w * nw;
+        for (int i = gt; i < nw; i += kDenseThreads) dst[i] = s_bits[i];
+        if (gt == 0) dense_slot[j] = w;
+    }
 }
 
 // Exclusive scan of the per-column counts into C_i's column pointers (in
@@ -345,7 +353,8 @@ static int flop_bin_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
     const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
-                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.flop,
+                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.dense_slot,
+                       p.flop,
                        p.sym_bin, p.sym_list,
                        p.C_colptr, p.st_colptr, p.n_col_tiles, p.ctr);
     SPG_LAUNCHED("k_flop_bin");
@@ -402,7 +411,8 @@ int launch_symbolic_bins(Plan &p) {
         hipLaunchKernelGGL(k_sym_dense, dim3((unsigned)p.sym_count[kBinDense]),
                            dim3(kDenseThreads), lds, p.stream,
                            p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
-                           p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr);
+                           p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr, p.dense_bits,
+                           p.dense_slot);
         SPG_LAUNCHED("k_sym_dense");
     }
     return SPGEMM_OK;

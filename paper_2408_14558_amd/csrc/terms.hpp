@@ -13,17 +13,51 @@ namespace spg {
 // positions.  Shorter ones are walked by the thread that loaded the entry.
 constexpr int kShortLen = 32;
 
-// LDS staging for one chunk of G entries of B(:,j).
-template <int G, typename V>
+// Row id above every real row (row ids are below 2^31 - 1).
+constexpr int kNoRow = 0x7fffffff;
+
+// Most waves one group holds (1024 threads).
+constexpr int kMaxGroupWaves = 16;
+
+// LDS staging for one chunk of CH entries of B(:,j).
+template <int CH, typename V>
 struct TermStage {
-    long long lstart[G];  // long entries: first position in A~ still to visit
-    long long lend[G];    // one past the entry's last position
-    V lbv[G];             // b_kj
-    int llen[G];          // length of the entry's column of A~
-    int lq[G];            // entry index relative to the column's first entry
+    long long lstart[CH];  // long entries: first position in A~ still to visit
+    long long lend[CH];    // one past the entry's last position
+    V lbv[CH];             // b_kj
+    int lnext[CH];         // offset (from lstart) of the entry's next unclaimed piece
     int nlong;
-    int tmp[G / kWave + 2];
+    int tmp[kMaxGroupWaves + 2];  // scratch for a group scan of the caller
 };
+
+// The same plus what a windowed walk needs to resume every entry.
+template <int CH, typename V>
+struct TermStageCursor : TermStage<CH, V> {
+    int llen[CH];  // length of the entry's column of A~
+    int lq[CH];    // entry index relative to the column's first entry
+    int lcut[CH];  // offset from lstart of the first term at or past the window
+};
+
+// Long entries of a chunk are dealt to the group's waves round-robin, each
+// walked in pieces of U*64 consecutive terms claimed from the entry's lnext
+// counter.  A wave that has finished its own entries claims pieces of the
+// others, so a few very long columns of A~ (hubs of a power-law matrix) do
+// not leave the other waves idle.  Stealing is tried when the chunk has at
+// most kStealFactor long entries per wave (more entries balance by
+// themselves).
+#ifndef SPG_STEAL_FACTOR
+#define SPG_STEAL_FACTOR 4
+#endif
+constexpr int kStealFactor = SPG_STEAL_FACTOR;
+
+// Claims the next piece of long entry li for the calling wave: the offset of
+// its first term from lstart (wave-uniform).
+template <int CH, typename V>
+__device__ __forceinline__ int claim_piece(TermStage<CH, V> *st, int li, int piece) {
+    int off = 0;
+    if (lane_id() == 0) off = atomicAdd(&st->lnext[li], piece);
+    return __shfl(off, 0);
+}
 
 // A term's row id and a_ik.
 template <typename V>
@@ -41,22 +75,23 @@ constexpr int kUnroll = 4;
 // bv) it calls ap(ld(p), bv); ld does the global loads, ap the LDS work, so
 // kUnroll loads per thread are in flight before the first use.  All G
 // threads must call it (it synchronises the group).
-template <int G, typename V, typename LD, typename AP>
+template <int G, typename V, int U = kUnroll, int CH = G, typename LD, typename AP>
 __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange tr,
                                               const V *__restrict__ Bvals,
-                                              TermStage<G, V> *st, int gt, LD &&ld, AP &&ap) {
+                                              TermStage<CH, V> *st, int gt, LD &&ld, AP &&ap) {
+    static_assert(CH <= G && G <= kMaxGroupWaves * kWave, "chunk and group sizes");
     using Item = decltype(ld((int64_t)0));
     constexpr int TEAM = G < kWave ? G : kWave;
     constexpr int NTEAM = G / TEAM;
     const int team = gt / TEAM, tl = gt % TEAM;
-    for (int64_t qb = q0; qb < q1; qb += G) {
+    for (int64_t qb = q0; qb < q1; qb += CH) {
         if (gt == 0) st->nlong = 0;
         group_sync<G>();
         const int64_t q = qb + gt;
         long long start = 0;
         int len = 0;
         V bv = V(0);
-        if (q < q1) {
+        if (gt < CH && q < q1) {
             start = tr.start[q];
             len = tr.len[q];
             if (Bvals) bv = Bvals[q];
@@ -79,17 +114,43 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
         }
         group_sync<G>();
         const int nl = st->nlong;
-        for (int li = team; li < nl; li += NTEAM) {
-            const long long s = st->lstart[li], t = st->lend[li];
-            const V b = st->lbv[li];
-            for (long long e = s + tl; e < t; e += kUnroll * TEAM) {
-                Item it[kUnroll];
+        if constexpr (G > kWave) {
+            constexpr int PS = U * kWave;
+            if (gt < nl) st->lnext[gt] = 0;
+            group_sync<G>();
+            auto walk = [&](int li) {
+                const long long s0 = st->lstart[li];
+                const int len = (int)(st->lend[li] - s0);
+                const V b = st->lbv[li];
+                while (true) {
+                    const int off = claim_piece<CH, V>(st, li, PS);
+                    if (off >= len) break;
+                    const long long s = s0 + off, t = s0 + min(len, off + PS);
+                    Item it[U];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (e + u * TEAM < t) it[u] = ld((int64_t)(e + u * TEAM));
+                    for (int u = 0; u < U; ++u)
+                        if (s + u * kWave + tl < t) it[u] = ld((int64_t)(s + u * kWave + tl));
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (e + u * TEAM < t) ap(it[u], b);
+                    for (int u = 0; u < U; ++u)
+                        if (s + u * kWave + tl < t) ap(it[u], b);
+                }
+            };
+            for (int li = team; li < nl; li += NTEAM) walk(li);
+            if (nl <= kStealFactor * NTEAM)
+                for (int k = 1; k < nl; ++k) walk((team + k) % nl);
+        } else {
+            for (int li = team; li < nl; li += NTEAM) {
+                const long long s = st->lstart[li], t = st->lend[li];
+                const V b = st->lbv[li];
+                for (long long e = s + tl; e < t; e += U * TEAM) {
+                    Item it[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (e + u * TEAM < t) it[u] = ld((int64_t)(e + u * TEAM));
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (e + u * TEAM < t) ap(it[u], b);
+                }
             }
         }
         group_sync<G>();
@@ -100,23 +161,26 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
 // call visited: cursor[q - q0] keeps, per entry of B(:,j), how far the
 // entry's column of A~ has been walked (rows ascend, so each call resumes
 // where the previous one stopped).  first == true starts every cursor at 0.
-// For each such term: ap(row, ldv(p), bv).  G >= 64 (teams are whole waves).
-template <int G, typename V, typename LDV, typename AP>
+// For each such term: ap(row, ldv(p), bv).  G >= 64 (long entries are
+// walked by whole waves).
+template <int G, typename V, int U = kUnroll, int CH = G, typename LDV, typename AP>
 __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int32_t r_hi,
                                                     bool first, TermRange tr,
                                                     const V *__restrict__ Bvals,
                                                     const int32_t *__restrict__ At_rowidx,
                                                     int32_t *__restrict__ cursor,
-                                                    TermStage<G, V> *st, int gt, LDV &&ldv,
+                                                    TermStageCursor<CH, V> *st, int gt,
+                                                    LDV &&ldv,
                                                     AP &&ap) {
     static_assert(G >= kWave, "teams are whole waves");
     constexpr int NTEAM = G / kWave;
     const int team = gt / kWave, tl = lane_id();
-    for (int64_t qb = q0; qb < q1; qb += G) {
+    static_assert(CH <= G && G <= kMaxGroupWaves * kWave, "chunk and group sizes");
+    for (int64_t qb = q0; qb < q1; qb += CH) {
         if (gt == 0) st->nlong = 0;
         group_sync<G>();
         const int64_t q = qb + gt;
-        if (q < q1) {
+        if (gt < CH && q < q1) {
             const int len = tr.len[q];
             if (len > 0) {
                 const long long c0 = tr.start[q];
@@ -144,35 +208,54 @@ __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int3
         }
         group_sync<G>();
         const int nl = st->nlong;
-        for (int li = team; li < nl; li += NTEAM) {
-            long long pos = st->lstart[li];
-            const long long t = st->lend[li];
+        constexpr int PS = U * kWave;
+        if (gt < nl) {
+            st->lnext[gt] = 0;
+            st->lcut[gt] = (int)(st->lend[gt] - st->lstart[gt]);
+        }
+        group_sync<G>();
+        auto walk = [&](int li) {
+            const long long s0 = st->lstart[li];
+            const int len = (int)(st->lend[li] - s0);
             const V b = st->lbv[li];
-            while (pos < t) {
-                int32_t r[kUnroll];
-                V v[kUnroll];
-                int cnt = 0;
+            while (true) {
+                const int off = claim_piece<CH, V>(st, li, PS);
+                // rows ascend inside an entry: once a piece has met r_hi, the
+                // entry's later pieces hold nothing for this window
+                if (off >= st->lcut[li]) break;
+                const long long s = s0 + off, t = s0 + min(len, off + PS);
+                int32_t r[U];
+                V v[U];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const long long e = pos + u * kWave + tl;
-                    r[u] = e < t ? At_rowidx[e] : 0x7fffffff;
+                for (int u = 0; u < U; ++u) {
+                    const long long e = s + u * kWave + tl;
+                    r[u] = e < t ? At_rowidx[e] : kNoRow;
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const long long e = pos + u * kWave + tl;
+                for (int u = 0; u < U; ++u) {
+                    const long long e = s + u * kWave + tl;
                     if (r[u] < r_hi) v[u] = ldv((int64_t)e);
                 }
+                int cnt = 0;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < U; ++u) {
                     if (r[u] < r_hi) ap(r[u], v[u], b);
-                    // rows ascend inside the column, so lanes below r_hi are a prefix
+                    // the positions below r_hi are a prefix of the piece
                     cnt += __popcll(__ballot(r[u] < r_hi));
                 }
-                pos += cnt;
-                if (cnt < kUnroll * kWave) break;
+                if (s + cnt < t) {
+                    if (tl == 0) atomicMin(&st->lcut[li], off + cnt);
+                    break;
+                }
             }
-            if (tl == 0) cursor[st->lq[li]] = (int32_t)(pos - (t - st->llen[li]));
-        }
+        };
+        for (int li = team; li < nl; li += NTEAM) walk(li);
+        if (nl <= kStealFactor * NTEAM)
+            for (int k = 1; k < nl; ++k) walk((team + k) % nl);
+        group_sync<G>();
+        if (gt < nl)
+            cursor[st->lq[gt]] =
+                (int32_t)(st->lstart[gt] + st->lcut[gt] - (st->lend[gt] - st->llen[gt]));
         group_sync<G>();
     }
 }
@@ -275,6 +358,5 @@ __device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
     }
 }
 
-constexpr int kNoRow = 0x7fffffff;
 
 }  // namespace spg

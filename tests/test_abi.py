@@ -46,6 +46,8 @@ def test_default_tuning_and_version(lib):
     t = _lib.Tuning()
     assert lib.spgemm_default_tuning(ctypes.byref(t)) == 0
     assert t.tiny_max_flop == 256 and t.hash_max_flop == 4096 and t.hash_max_nnz == 2048
+    assert t.batch_streams == 0 and t.batch_persistent == 0 and list(t.reserved) == [0, 0]
+    assert ctypes.sizeof(_lib.Tuning) == 56
     assert lib.spgemm_default_tuning(None) == _lib.EINVAL
     assert b"gfx950" in lib.spgemm_version()
 
@@ -68,7 +70,8 @@ def _plan(lib, A, B, offs, P, b, tun=None, dtype=1):
 
 @pytest.mark.parametrize("case", ["nullA", "dims", "P0", "b0", "offs_start", "offs_end",
                                   "offs_decrease", "dtype", "neg", "big", "rows_missing",
-                                  "tiny_tuning", "hash_tuning", "nnz_no_rows"])
+                                  "tiny_tuning", "hash_tuning", "nnz_no_rows",
+                                  "reserved_tuning", "streams_tuning"])
 def test_host_side_rejections(lib, case):
     from paper_2408_14558_amd import _lib
     A = _csc(10, 8, 5)
@@ -98,13 +101,17 @@ def test_host_side_rejections(lib, case):
         A = _csc(10, 8, 5, rowidx=None)
     elif case == "nnz_no_rows":
         A = _csc(0, 8, 5)
-    elif case in ("tiny_tuning", "hash_tuning"):
+    elif case.endswith("_tuning"):
         tun = _lib.Tuning()
         lib.spgemm_default_tuning(ctypes.byref(tun))
         if case == "tiny_tuning":
             tun.tiny_max_flop = 513
-        else:
+        elif case == "hash_tuning":
             tun.hash_max_nnz = 4096
+        elif case == "reserved_tuning":
+            tun.reserved[1] = 1
+        else:
+            tun.batch_streams = 9
     rc, h = _plan(lib, A, B, offs, P, b, tun, dtype)
     want = _lib.EUNSUPPORTED if case == "dtype" else _lib.EINVAL
     assert rc == want

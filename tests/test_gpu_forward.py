@@ -24,13 +24,13 @@ def _dev(M, dtype):
     return spg.DeviceCsc.from_host(M, dtype=dtype)
 
 
-def check_local(A, Bi, offs, b, dtype=torch.float64, tun=None, cols=None):
+def check_local(A, Bi, offs, b, dtype=torch.float64, tun=None, cols=None, own_whole=-1):
     """Runs the GPU path for one partition and compares every stage."""
     Ad, Bd = _dev(A, dtype), _dev(Bi, dtype)
     if dtype == torch.float32:
         A = synth.as_fp32(A)
         Bi = synth.as_fp32(Bi)
-    ref = oracle.local_product(A, Bi, offs, b)
+    ref = oracle.local_product(A, Bi, offs, b, own_whole=own_whole)
     with spg.Plan(Ad, Bd, offs, b, tuning=tun) as p:
         ex = p.export()
         st = ex["stats"]
@@ -142,7 +142,7 @@ def test_every_bin_gives_the_same_product(name):
     tun = _bin_tunings()[name]
     st, sbin, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 1), 64, tun=tun)
     print(name, "sym bins", st["sym_bins"], "num bins", st["num_bins"], flush=True)
-    if name == "all_dense":
+    if name in ("all_dense", "all_dense_windows"):
         assert set(np.unique(nbin)) <= {0, 6}
 
 
@@ -190,6 +190,17 @@ def test_er65536_partition0_block_sizes(b):
     st, _, _ = check_local(w["A"], Bi, offs, b)
     if b >= 64:
         assert st["kt"] == 65536 and st["nnz_At"] == w["A"].nnz  # every block is hit
+
+
+@pytest.mark.parametrize("own", [0, 2])
+def test_own_partition_taken_whole(own):
+    """The own partition's nonzero columns all enter A~; the rest follows
+    Alg. 2; C_i is unchanged."""
+    A = synth.rmat(12, 8, 0.57, 0.19, 0.19, 0.05, seed=13)
+    offs = synth.partition_offsets(A.ncols, 4)
+    Bi = synth.column_slice(A, int(offs[own]), int(offs[own + 1]))
+    tun = spg.tuning(own_partition=own, own_partition_whole=1)
+    check_local(A, Bi, offs, 16, tun=tun, own_whole=own)
 
 
 @pytest.mark.parametrize("i", [1, 7, 15])

@@ -172,6 +172,32 @@ def test_block_select_extremes():
         assert np.array_equal(sbig.sel[lo:hi].astype(bool), nz[lo:hi] & any_hit)
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_block_select_own_partition_whole(seed):
+    """Naming the caller's own partition selects all of its nonzero columns
+    (every one of its groups is chosen, in order), whatever H says, and
+    leaves the other partitions' choice as without it."""
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(8, 70))
+    A = rand_csc(rng, 15, k, 0.2, empty_cols=(0,))
+    H = (rng.random(k) < 0.15).astype(np.uint8)
+    offs = synth.partition_offsets(k, 3)
+    b = int(rng.integers(1, 6))
+    own = int(rng.integers(0, 3))
+    base = oracle.block_select(A, H, offs, b)
+    s = oracle.block_select(A, H, offs, b, own_whole=own)
+    nz = _nonzero_cols(A)
+    lo, hi = offs[own], offs[own + 1]
+    want = base.sel.copy()
+    want[lo:hi] = nz[lo:hi]
+    assert np.array_equal(s.sel, want)
+    ids = np.nonzero(nz[lo:hi])[0] + lo
+    own_blocks = [[ids[g], ids[min(g + b, ids.size) - 1]] for g in range(0, ids.size, b)]
+    other = [blk for blk in base.blocks.tolist() if not lo <= blk[0] < hi]
+    assert sorted(s.blocks.tolist()) == sorted(other + own_blocks)
+    assert s.K == base.K and s.blocks.shape[0] == len(other) + len(own_blocks)
+
+
 def test_gather_copies_selected_columns_bitwise():
     rng = np.random.default_rng(4)
     A = rand_csc(rng, 30, 50, 0.15)
