@@ -110,7 +110,14 @@ const char *spgemm_last_error(void);
 /* Library version string. */
 const char *spgemm_version(void);
 
-/* Fills *t with the default tuning.  Returns SPGEMM_EINVAL for NULL. */
+/*
+ * Fills *t with the default tuning.  Environment variables override single
+ * fields (decimal integers; unparsable values are ignored, ranges are
+ * checked when a plan uses the tuning): SPGEMM_TINY_MAX_FLOP,
+ * SPGEMM_HASH_MAX_FLOP, SPGEMM_HASH_MAX_NNZ, SPGEMM_DENSE_WINDOW,
+ * SPGEMM_MEDIUM_KERNEL, SPGEMM_BATCH_STREAMS, SPGEMM_VALIDATE,
+ * SPGEMM_WORKSPACE_LIMIT.  Returns SPGEMM_EINVAL for NULL.
+ */
 int spgemm_default_tuning(spgemm_tuning *t);
 
 /*

@@ -2,6 +2,8 @@
 // object and its workspace, the pooled allocator, and the order of launches.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <climits>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -230,6 +232,16 @@ const char *spgemm_last_error(void) { return spg::t_last_error.c_str(); }
 
 const char *spgemm_version(void) { return "spgemm-mi355x 0.1 (gfx950)"; }
 
+// SPGEMM_<FIELD> environment variables override the built-in defaults
+// (an unparsable value is ignored; the plan validates ranges).
+static void env_override(const char *name, int32_t *field) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return;
+    char *end = nullptr;
+    const long long x = std::strtoll(v, &end, 10);
+    if (end && *end == '\0' && x >= INT32_MIN && x <= INT32_MAX) *field = (int32_t)x;
+}
+
 int spgemm_default_tuning(spgemm_tuning *t) {
     if (!t) return fail(SPGEMM_EINVAL, "tuning is NULL");
     std::memset(t, 0, sizeof(*t));
@@ -245,6 +257,18 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->own_partition = -1;
     t->own_partition_whole = 0;
     t->workspace_limit = 0;
+    env_override("SPGEMM_TINY_MAX_FLOP", &t->tiny_max_flop);
+    env_override("SPGEMM_HASH_MAX_FLOP", &t->hash_max_flop);
+    env_override("SPGEMM_HASH_MAX_NNZ", &t->hash_max_nnz);
+    env_override("SPGEMM_DENSE_WINDOW", &t->dense_window);
+    env_override("SPGEMM_MEDIUM_KERNEL", &t->medium_kernel);
+    env_override("SPGEMM_BATCH_STREAMS", &t->batch_streams);
+    env_override("SPGEMM_VALIDATE", &t->validate);
+    if (const char *v = std::getenv("SPGEMM_WORKSPACE_LIMIT"); v && *v) {
+        char *end = nullptr;
+        const long long x = std::strtoll(v, &end, 10);
+        if (end && *end == '\0') t->workspace_limit = x;
+    }
     return SPGEMM_OK;
 }
 

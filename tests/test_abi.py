@@ -52,6 +52,19 @@ def test_default_tuning_and_version(lib):
     assert b"gfx950" in lib.spgemm_version()
 
 
+def test_default_tuning_environment_overrides(lib, monkeypatch):
+    from paper_2408_14558_amd import _lib
+    monkeypatch.setenv("SPGEMM_TINY_MAX_FLOP", "128")
+    monkeypatch.setenv("SPGEMM_MEDIUM_KERNEL", "2")
+    monkeypatch.setenv("SPGEMM_WORKSPACE_LIMIT", "123456789012")
+    monkeypatch.setenv("SPGEMM_HASH_MAX_NNZ", "not-a-number")
+    t = _lib.Tuning()
+    assert lib.spgemm_default_tuning(ctypes.byref(t)) == 0
+    assert t.tiny_max_flop == 128 and t.medium_kernel == 2
+    assert t.workspace_limit == 123456789012
+    assert t.hash_max_nnz == 2048  # ignored
+
+
 def _csc(nrows, ncols, nnz, colptr=1, rowidx=1):
     from paper_2408_14558_amd import _lib
     return _lib.Csc(nrows, ncols, nnz, colptr, rowidx, None)
