@@ -223,6 +223,48 @@ def bench_backward(spg, reps=10):
     }
 
 
+def study_gather_volume(spg, blocks=(1, 16, 64, 256, 1024, 4096), P=16, reps=3):
+    """Gather volume of the block-fetch rule (Alg. 2) against the block size b
+    and the ordering of the input: R-MAT 18 (C = A*A, B_i = A's i-th column
+    block of P) in its generated order and under a seeded random symmetric
+    permutation, and the 2D Laplacian 64x64 (P = 4).  Per (input, order, b):
+    nnz(A~)/nnz(A) averaged over the partitions (the paper's CV/memA), the
+    block (message) count M summed over the partitions, and the plan time
+    (H_i, Alg. 2, map and the gather of A~) averaged over the partitions."""
+    import torch
+    import synth
+    inputs = []
+    R = synth.workload("rmat18")["A"]
+    inputs.append(("rmat18", "original", R, P))
+    inputs.append(("rmat18", "random_symmetric_perm", synth.permute_symmetric(R, seed=11), P))
+    L = synth.laplacian2d(64)
+    inputs.append(("lap2d_64", "original", L, 4))
+    inputs.append(("lap2d_64", "random_symmetric_perm", synth.permute_symmetric(L, seed=11), 4))
+    rows = []
+    s = torch.cuda.current_stream()
+    for name, order, M, parts in inputs:
+        Ad = spg.DeviceCsc.from_host(M)
+        offs = synth.partition_offsets(M.ncols, parts)
+        Bis = [spg.DeviceCsc.from_host(synth.column_slice(M, int(offs[i]), int(offs[i + 1])))
+               for i in range(parts)]
+        for b in blocks:
+            cv, msgs, ms = [], 0, []
+            for Bi in Bis:
+                def plan():
+                    return spg.Plan(Ad, Bi, offs, b)
+                with plan() as p:
+                    st = p.stats()
+                cv.append(st["nnz_At"] / max(1, M.nnz))
+                msgs += st["M"]
+                t = _time_on(s, lambda: plan().close(), reps)
+                ms.append(t)
+            rows.append({"input": name, "order": order, "P": parts, "b": b,
+                         "cv_memA_mean": round(sum(cv) / len(cv), 4),
+                         "messages_M": int(msgs), "plan_ms_mean": round(sum(ms) / len(ms), 4)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and backward measurements")
+    ap.add_argument("--study", choices=["gather-volume"],
+                    help="instead of the benchmark, run a study and print its table as JSON")
     ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
                     help="override a spgemm_tuning field for the main workload (repeatable)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
@@ -261,6 +305,11 @@ def main():
         return
 
     import paper_2408_14558_amd as spg
+
+    if args.study == "gather-volume":
+        print(json.dumps({"study": "gather_volume_vs_block_size_and_order",
+                          "rows": study_gather_volume(spg)}), flush=True)
+        return
 
     w = workload(args.workload)
     tdt = torch.float64 if w["dtype"] == "f64" else torch.float32

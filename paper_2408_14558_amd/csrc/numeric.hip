@@ -15,12 +15,14 @@ __global__ __launch_bounds__(256) void k_num_tiny(const int32_t *__restrict__ li
     const int wv = threadIdx.x >> 6;
     const int w = blockIdx.x * 4 + wv;
     if (w >= count) return;
-    num_wave_dispatch<V, EMAX, kPacked>(a, list[w], s_rows[wv], s_vals[wv]);
+    // a NULL list: every column of B_i is in this bin, column w is the w-th
+    num_wave_dispatch<V, EMAX, kPacked>(a, list ? list[w] : w, s_rows[wv], s_vals[wv]);
 }
 
 template <typename V, int EMAX>
 static void num_tiny_launch(const Plan &p, const int32_t *list, const NumArgs<V> &a) {
     const int cnt = p.num_count[kBinTiny];
+    if (cnt == p.n) list = nullptr;  // the bin holds every column: skip the indirection
     const dim3 grid((cnt + 3) / 4);
     if (p.m < kPackedRowLimit)
         hipLaunchKernelGGL((k_num_tiny<V, EMAX, true>), grid, dim3(256), 0, p.stream, list, cnt,

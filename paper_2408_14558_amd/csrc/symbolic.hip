@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ li
                                                   int64_t *__restrict__ Ccount) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= count) return;  // whole wave leaves together
-    const int32_t j = list[w];
+    const int32_t j = list ? list[w] : w;  // NULL list: every column is tiny
     const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1], f = flop[j];
     int c;
     if (f <= kWave) c = sym_wave_count<1>(q0, q1, tr, At_rowidx);
@@ -388,14 +388,17 @@ int launch_symbolic_bins(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     if (p.sym_count[kBinTiny] > 0) {
         const unsigned g = (unsigned)((p.sym_count[kBinTiny] + 3) / 4);
+        // the bin holds every column: the kernel takes column w directly
+        const int32_t *list =
+            p.sym_count[kBinTiny] == p.n ? nullptr : p.sym_list + (int64_t)kBinTiny * p.n;
         if (p.th.tiny_max_flop <= 4 * kWave)
-            hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream,
-                               p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
-                               p.Bcolptr, p.term_range(), p.At_rowidx, p.flop, p.C_colptr);
+            hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream, list,
+                               p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
+                               p.flop, p.C_colptr);
         else
-            hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream,
-                               p.sym_list + (int64_t)kBinTiny * p.n, p.sym_count[kBinTiny],
-                               p.Bcolptr, p.term_range(), p.At_rowidx, p.flop, p.C_colptr);
+            hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream, list,
+                               p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
+                               p.flop, p.C_colptr);
         SPG_LAUNCHED("k_sym_tiny");
     }
     int rc;

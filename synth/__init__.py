@@ -62,6 +62,7 @@ __all__ = [
     "partition_offsets",
     "column_slice",
     "transpose",
+    "permute_symmetric",
     "from_triplets",
     "workload",
 ]
@@ -123,6 +124,16 @@ def transpose(M: CSC) -> CSC:
     colptr = np.zeros(M.nrows + 1, dtype=np.int64)
     colptr[1:] = np.cumsum(np.bincount(M.rowidx, minlength=M.nrows))
     return CSC(M.ncols, M.nrows, colptr, cols[order].astype(np.int32), M.vals[order].copy())
+
+
+def permute_symmetric(M: CSC, seed: int) -> CSC:
+    """Q M Q^T for a seeded uniformly random permutation Q (square M): entry
+    (i, j) moves to (q[i], q[j])."""
+    if M.nrows != M.ncols:
+        raise ValueError("a symmetric permutation needs a square matrix")
+    q = np.random.default_rng(seed).permutation(M.nrows).astype(np.int64)
+    cols = np.repeat(np.arange(M.ncols, dtype=np.int64), np.diff(M.colptr))
+    return from_triplets(M.nrows, M.ncols, q[M.rowidx.astype(np.int64)], q[cols], M.vals)
 
 
 def partition_offsets(k: int, P: int) -> np.ndarray:

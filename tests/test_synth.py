@@ -93,3 +93,13 @@ def test_er_batch_shapes_stay_in_range():
         assert 1000 <= A.nrows <= 50000
         d = int(A.colptr[1] - A.colptr[0])
         assert 4 <= d <= 32 and np.all(np.diff(B.colptr) == d)
+
+
+def test_permute_symmetric_is_a_relabelling():
+    A = synth.erdos_renyi(60, 60, 4, seed=5)
+    Q = synth.permute_symmetric(A, seed=9)
+    _canonical(Q)
+    q = np.random.default_rng(9).permutation(60)
+    D, E = A.to_dense(), Q.to_dense()
+    assert np.array_equal(E[np.ix_(q, q)], D)
+    assert Q.nnz == A.nnz
