@@ -215,6 +215,30 @@ static void reserve_dense_bits(Plan &p) {
     }
 }
 
+// Room for the symbolic phase to keep the sorted order of every tiny
+// column's products (64 or 128 bytes per column and 64 products), so the
+// numeric phase does not sort again.  Optional, like the dense bitmaps.
+static void reserve_tiny_perm(Plan &p) {
+    const int slots = p.th.tiny_max_flop <= 256 ? 256 : 512;  // the tiny kernels' 64*EMAX
+    const size_t need = (size_t)p.sym_count[kBinTiny] * slots * sizeof(uint16_t);
+    const bool fits = need > 0 && p.m < kPackedRowLimit && need <= kDenseBitsMax &&
+                      (p.tun.workspace_limit <= 0 ||
+                       p.ws_bytes + p.dense_bits_bytes + need <= (size_t)p.tun.workspace_limit);
+    if (fits && p.tiny_perm_bytes >= need) return;
+    pool_put(p.tiny_perm, p.tiny_perm_bytes, false, p.device, p.stream);
+    p.tiny_perm = nullptr;
+    p.tiny_perm_bytes = 0;
+    if (!fits) return;
+    void *ptr = nullptr;
+    size_t got = 0;
+    if (pool_get(need, false, p.device, p.stream, &ptr, &got) == SPGEMM_OK) {
+        p.tiny_perm = (uint16_t *)ptr;
+        p.tiny_perm_bytes = got;
+    } else {
+        (void)hipGetLastError();
+    }
+}
+
 static int sync_counters(Plan &p) {
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));
@@ -429,7 +453,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.num_list = (int32_t *)(w + o_nlist);
     pl.cursor = (int32_t *)(w + o_cur);
     pl.tstart = (int64_t *)(w + o_tst);
-    pl.dense_slot = (int32_t *)(w + o_dsl);
+    pl.col_slot = (int32_t *)(w + o_dsl);
     pl.tlen = (int32_t *)(w + o_tln);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);
@@ -560,6 +584,7 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     SPG_HIP(hipStreamSynchronize(p.stream));
     for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
     reserve_dense_bits(p);
+    reserve_tiny_perm(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
     if ((rc = launch_colptr_scan(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
@@ -612,6 +637,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
     pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream);
     pool_put(p.dense_bits, p.dense_bits_bytes, false, p.device, p.stream);
+    pool_put(p.tiny_perm, p.tiny_perm_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;
 }

@@ -88,6 +88,13 @@ struct TermRange {
     const int32_t *len;
 };
 
+// Tiny columns (at most 64*8 products) sort their products by a 32-bit key
+// (row << kSlotBits) | slot when the rows fit (m below kPackedRowLimit); the
+// symbolic phase keeps the sorted slots (kNoSlot past the last product).
+constexpr int kSlotBits = 9;
+constexpr int64_t kPackedRowLimit = int64_t(1) << (31 - kSlotBits);
+constexpr uint16_t kNoSlot = 0xFFFF;
+
 struct Thresholds {
     int tiny_max_flop;
     int sym_hash_max[4];  // flop limit per symbolic hash bin (0 = bin unused)
@@ -149,9 +156,13 @@ struct Plan {
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
-    int32_t *dense_slot = nullptr;  // n: the column's bitmap in dense_bits, or -1
-    uint32_t *dense_bits = nullptr; // symbolic's row bitmaps of its dense columns (pooled)
+    // What the symbolic phase keeps for the numeric phase, per column: its
+    // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
+    int32_t *col_slot = nullptr;    // n
+    uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns (pooled)
     size_t dense_bits_bytes = 0;
+    uint16_t *tiny_perm = nullptr;  // sorted order of the terms of tiny columns (pooled)
+    size_t tiny_perm_bytes = 0;
     int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
     int32_t *tlen = nullptr;      // nnzB
     TermRange term_range() const { return TermRange{tstart, tlen}; }

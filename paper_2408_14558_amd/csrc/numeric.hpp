@@ -22,8 +22,9 @@ struct NumArgs {
     V *Cval;
     const int64_t *flop;  // sparse flops per column (picks the wave-sort width)
     int32_t *cursor;      // nnz(B_i) scratch for windowed dense columns
-    const int32_t *dense_slot;   // per column: its row bitmap in dense_bits, or -1
+    const int32_t *col_slot;     // per column: its slot in dense_bits or tiny_perm, or -1
     const uint32_t *dense_bits;  // row bitmaps kept by the symbolic phase
+    const uint16_t *tiny_perm;   // sorted term order of tiny columns kept by the symbolic phase
 };
 
 // --- wave sort: <= 64*E terms, one wave, registers ---------------------------
@@ -35,12 +36,10 @@ struct NumArgs {
 // slot (< 64*8) is where the term's value waits in LDS, so the sort moves one
 // 32-bit word per term instead of a key and a value; after the sort every
 // lane fetches its values from LDS by slot.
-constexpr int kSlotBits = 9;
-constexpr int64_t kPackedRowLimit = int64_t(1) << (31 - kSlotBits);
 
 template <int E, typename V, bool kPacked>
 __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, int *s_rows,
-                                                V *s_vals) {
+                                                V *s_vals, const uint16_t *perm) {
     static_assert(E * kWave <= (1 << kSlotBits), "slot ids need kSlotBits bits");
     int64_t p[E];
     V bv[E];
@@ -48,6 +47,28 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, 
     const int lane = lane_id();
     int key[E];
     V val[E];
+    if (perm) {
+        // the symbolic phase kept the sorted order of the slots: rows and
+        // values wait in LDS by slot and are read back in that order
+        uint16_t sl[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) sl[r] = perm[lane * E + r];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (p[r] >= 0) {
+                const int slot = r * kWave + lane;
+                s_rows[slot] = a.At_rowidx[p[r]];
+                s_vals[slot] = a.At_vals[p[r]] * bv[r];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            key[r] = sl[r] != kNoSlot ? s_rows[sl[r]] : kNoRow;
+            val[r] = sl[r] != kNoSlot ? s_vals[sl[r]] : V(0);
+        }
+        wave_sync();  // every slot is read before the buffers are reused below
+    } else {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         key[r] = kNoRow;
@@ -78,6 +99,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, 
         wave_sync();  // every value is read before the slots are reused below
     } else {
         wave_sort<E, true, V>(key, val);
+    }
     }
     const int prev_last = __shfl_up(key[E - 1], 1);
     bool hd[E];
@@ -119,10 +141,13 @@ __device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j
                                                   V *s_vals) {
     static_assert(EMAX == 4 || EMAX == 8, "EMAX is 4 or 8");
     const int64_t f = a.flop[j];
-    if (f <= kWave) num_wave_column<1, V, kPacked>(a, j, s_rows, s_vals);
-    else if (f <= 2 * kWave) num_wave_column<2, V, kPacked>(a, j, s_rows, s_vals);
-    else if (EMAX == 4 || f <= 4 * kWave) num_wave_column<4, V, kPacked>(a, j, s_rows, s_vals);
-    else num_wave_column<EMAX, V, kPacked>(a, j, s_rows, s_vals);
+    const int slot = a.tiny_perm ? a.col_slot[j] : -1;
+    const uint16_t *perm = slot >= 0 ? a.tiny_perm + (size_t)slot * (EMAX * kWave) : nullptr;
+    if (f <= kWave) num_wave_column<1, V, kPacked>(a, j, s_rows, s_vals, perm);
+    else if (f <= 2 * kWave) num_wave_column<2, V, kPacked>(a, j, s_rows, s_vals, perm);
+    else if (EMAX == 4 || f <= 4 * kWave)
+        num_wave_column<4, V, kPacked>(a, j, s_rows, s_vals, perm);
+    else num_wave_column<EMAX, V, kPacked>(a, j, s_rows, s_vals, perm);
 }
 
 // --- hash: LDS table, compaction, bitonic sort -----------------------------
@@ -404,7 +429,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    const int slot = a.dense_slot[j];
+    const int slot = a.col_slot[j];
     if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
         const uint32_t *src = a.dense_bits + (size_t)slot * nw;
         for (int i = gt; i < nw; i += G) bits[i] = src[i];

@@ -71,7 +71,7 @@ template <int S>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
-    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ dense_slot,
+    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
     DevCounters *__restrict__ ctr) {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         const int64_t j = j0 + tid;
         const long long f = s_f[tid];
         flop[j] = f;
-        dense_slot[j] = -1;
+        col_slot[j] = -1;
         const int b = sym_bin_of(f, th);
         sym_bin[j] = b;
         s_bin[tid] = b;
@@ -145,22 +145,39 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
 }
 
 // --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
+// perm (rows below kPackedRowLimit only, else NULL): the sort key of a term
+// is (row << kSlotBits) | slot, and the sorted slots are kept (kNoSlot past
+// the last term), so the numeric phase orders the column without sorting.
 template <int E>
 __device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1, TermRange tr,
-                                              const int32_t *__restrict__ At_rowidx) {
+                                              const int32_t *__restrict__ At_rowidx,
+                                              uint16_t *__restrict__ perm) {
     int64_t p[E];
     float bv[E];
     wave_terms<E, float>(q0, q1, tr, nullptr, p, bv);
+    const int lane = lane_id();
     int key[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) key[r] = p[r] >= 0 ? At_rowidx[p[r]] : kNoRow;
+    for (int r = 0; r < E; ++r) {
+        key[r] = kNoRow;
+        if (p[r] >= 0)
+            key[r] = perm ? (At_rowidx[p[r]] << kSlotBits) | (r * kWave + lane) : At_rowidx[p[r]];
+    }
     wave_sort<E, false, float>(key, bv);
+    if (perm) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            perm[lane * E + r] =
+                key[r] != kNoRow ? (uint16_t)(key[r] & ((1 << kSlotBits) - 1)) : kNoSlot;
+            if (key[r] != kNoRow) key[r] >>= kSlotBits;
+        }
+    }
     const int prev_last = __shfl_up(key[E - 1], 1);
     int nh = 0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const int prev = r == 0 ? prev_last : key[r - 1];
-        nh += key[r] != kNoRow && ((r == 0 && lane_id() == 0) || key[r] != prev);
+        nh += key[r] != kNoRow && ((r == 0 && lane == 0) || key[r] != prev);
     }
     return wave_sum(nh);
 }
@@ -171,17 +188,23 @@ __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ li
                                                   TermRange tr,
                                                   const int32_t *__restrict__ At_rowidx,
                                                   const int64_t *__restrict__ flop,
-                                                  int64_t *__restrict__ Ccount) {
+                                                  int64_t *__restrict__ Ccount,
+                                                  uint16_t *__restrict__ tiny_perm,
+                                                  int32_t *__restrict__ col_slot) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= count) return;  // whole wave leaves together
     const int32_t j = list ? list[w] : w;  // NULL list: every column is tiny
     const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1], f = flop[j];
+    uint16_t *perm = tiny_perm ? tiny_perm + (size_t)w * (EMAX * kWave) : nullptr;
     int c;
-    if (f <= kWave) c = sym_wave_count<1>(q0, q1, tr, At_rowidx);
-    else if (f <= 2 * kWave) c = sym_wave_count<2>(q0, q1, tr, At_rowidx);
-    else if (EMAX == 4 || f <= 4 * kWave) c = sym_wave_count<4>(q0, q1, tr, At_rowidx);
-    else c = sym_wave_count<EMAX>(q0, q1, tr, At_rowidx);
-    if (lane_id() == 0) Ccount[j] = c;
+    if (f <= kWave) c = sym_wave_count<1>(q0, q1, tr, At_rowidx, perm);
+    else if (f <= 2 * kWave) c = sym_wave_count<2>(q0, q1, tr, At_rowidx, perm);
+    else if (EMAX == 4 || f <= 4 * kWave) c = sym_wave_count<4>(q0, q1, tr, At_rowidx, perm);
+    else c = sym_wave_count<EMAX>(q0, q1, tr, At_rowidx, perm);
+    if (lane_id() == 0) {
+        Ccount[j] = c;
+        if (perm) col_slot[j] = w;
+    }
 }
 
 // --- hash bins: LDS open addressing (linear probing), count inserts -------
@@ -242,7 +265,7 @@ struct SymDenseLds {
 __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
     TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
-    uint32_t *__restrict__ keep_bits, int32_t *__restrict__ dense_slot) {
+    uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot) {
     extern __shared__ uint32_t s_bits[];
     __shared__ SymDenseLds L;
     const int w = blockIdx.x;
@@ -264,7 +287,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     if (keep_bits) {  // the numeric phase reuses this bitmap
         uint32_t *dst = keep_bits + (size_t)w * nw;
         for (int i = gt; i < nw; i += kDenseThreads) dst[i] = s_bits[i];
-        if (gt == 0) dense_slot[j] = w;
+        if (gt == 0) col_slot[j] = w;
     }
 }
 
@@ -353,7 +376,7 @@ static int flop_bin_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
     const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
-                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.dense_slot,
+                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot,
                        p.flop,
                        p.sym_bin, p.sym_list,
                        p.C_colptr, p.st_colptr, p.n_col_tiles, p.ctr);
@@ -394,11 +417,11 @@ int launch_symbolic_bins(Plan &p) {
         if (p.th.tiny_max_flop <= 4 * kWave)
             hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream, list,
                                p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
-                               p.flop, p.C_colptr);
+                               p.flop, p.C_colptr, p.tiny_perm, p.col_slot);
         else
             hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream, list,
                                p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
-                               p.flop, p.C_colptr);
+                               p.flop, p.C_colptr, p.tiny_perm, p.col_slot);
         SPG_LAUNCHED("k_sym_tiny");
     }
     int rc;
@@ -415,7 +438,7 @@ int launch_symbolic_bins(Plan &p) {
                            dim3(kDenseThreads), lds, p.stream,
                            p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
                            p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr, p.dense_bits,
-                           p.dense_slot);
+                           p.col_slot);
         SPG_LAUNCHED("k_sym_dense");
     }
     return SPGEMM_OK;
