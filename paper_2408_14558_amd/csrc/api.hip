@@ -43,6 +43,20 @@ struct PoolBlock {
 
 static std::mutex g_pool_mtx;
 static std::vector<PoolBlock> g_pool;
+static std::vector<hipEvent_t> g_spare_events;  // recorded events come back here
+
+// An event for pool_put: a spare one if any, else a new one.
+static hipError_t take_event(hipEvent_t *ev) {
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mtx);
+        if (!g_spare_events.empty()) {
+            *ev = g_spare_events.back();
+            g_spare_events.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
 
 static size_t round_block(size_t bytes, bool pinned) {
     const size_t g = pinned ? 4096 : (1 << 20);
@@ -70,7 +84,7 @@ static int pool_get(size_t bytes, bool pinned, int device, hipStream_t stream, v
             } else if (b.stream != stream) {
                 SPG_HIP(hipStreamWaitEvent(stream, b.ev, 0));
             }
-            SPG_HIP(hipEventDestroy(b.ev));
+            g_spare_events.push_back(b.ev);
             *out = b.ptr;
             *got = b.bytes;
             return SPGEMM_OK;
@@ -91,9 +105,9 @@ static int pool_get(size_t bytes, bool pinned, int device, hipStream_t stream, v
 
 static void pool_put(void *ptr, size_t bytes, bool pinned, int device, hipStream_t stream) {
     if (!ptr) return;
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, stream) != hipSuccess) {
+    hipEvent_t ev = nullptr;
+    if (take_event(&ev) != hipSuccess || hipEventRecord(ev, stream) != hipSuccess) {
+        if (ev) (void)hipEventDestroy(ev);
         (void)hipStreamSynchronize(stream);
         if (pinned) (void)hipHostFree(ptr); else (void)hipFree(ptr);
         return;
@@ -104,10 +118,13 @@ static void pool_put(void *ptr, size_t bytes, bool pinned, int device, hipStream
 
 static int pool_trim() {
     std::vector<PoolBlock> blocks;
+    std::vector<hipEvent_t> spare;
     {
         std::lock_guard<std::mutex> lk(g_pool_mtx);
         blocks.swap(g_pool);
+        spare.swap(g_spare_events);
     }
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
     for (auto &b : blocks) {
         (void)hipEventSynchronize(b.ev);
         (void)hipEventDestroy(b.ev);
@@ -119,6 +136,22 @@ static int pool_trim() {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// LDS bytes one workgroup may use, per device (queried once).
+static int device_lds_max(int device, int *out) {
+    static std::mutex mtx;
+    static std::vector<int> cache;
+    std::lock_guard<std::mutex> lk(mtx);
+    if (device < 0) return 1;
+    if ((size_t)device >= cache.size()) cache.resize(device + 1, 0);
+    if (cache[device] == 0 &&
+        hipDeviceGetAttribute(&cache[device], hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+            hipSuccess) {
+        cache[device] = 0;
+        return 1;
+    }
+    *out = cache[device];
+    return 0;
+}
 struct Carver {
     size_t off = 0;
     template <typename T>
@@ -188,55 +221,44 @@ static int check_tuning(const spgemm_tuning &t) {
     return SPGEMM_OK;
 }
 
-// Room for the symbolic phase to keep the row bitmap of each of its dense
-// columns, so the numeric phase loads it instead of walking the products
-// again.  Optional: without it (too large, above workspace_limit, or the
-// allocation fails) the numeric phase rebuilds the bitmaps.
+// Room for what the symbolic phase keeps for the numeric phase, in one
+// pooled block: the row bitmap of each of its dense columns (the numeric
+// phase loads it instead of walking the products again) and the sorted
+// product order of each tiny column (the numeric phase does not sort again).
+// Optional: a part that is too large, above workspace_limit, or not
+// allocatable is left out and the numeric phase recomputes it.
 constexpr size_t kDenseBitsMax = size_t(8) << 30;
 
-static void reserve_dense_bits(Plan &p) {
+static void reserve_kept(Plan &p) {
     const size_t nw = (size_t)((p.m + 31) / 32);
-    const size_t need = (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
-    const bool fits = need > 0 && need <= kDenseBitsMax &&
-                      (p.tun.workspace_limit <= 0 ||
-                       p.ws_bytes + need <= (size_t)p.tun.workspace_limit);
-    if (fits && p.dense_bits_bytes >= need) return;
-    pool_put(p.dense_bits, p.dense_bits_bytes, false, p.device, p.stream);
+    size_t dense = (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
+    // tiny columns: the kernels' 64*EMAX product slots, 2 bytes each
+    const size_t slots = p.th.tiny_max_flop <= 256 ? 256 : 512;
+    size_t tiny = p.m < kPackedRowLimit ? (size_t)p.sym_count[kBinTiny] * slots * 2 : 0;
+    const size_t limit = p.tun.workspace_limit > 0 ? (size_t)p.tun.workspace_limit : SIZE_MAX;
+    if (dense > kDenseBitsMax || p.ws_bytes + dense > limit) dense = 0;
+    if (tiny > kDenseBitsMax || p.ws_bytes + dense + tiny > limit) tiny = 0;
+    const size_t dense_at = 0, tiny_at = (dense + 255) & ~(size_t)255;
+    const size_t need = tiny_at + tiny;
     p.dense_bits = nullptr;
-    p.dense_bits_bytes = 0;
-    if (!fits) return;
-    void *ptr = nullptr;
-    size_t got = 0;
-    if (pool_get(need, false, p.device, p.stream, &ptr, &got) == SPGEMM_OK) {
-        p.dense_bits = (uint32_t *)ptr;
-        p.dense_bits_bytes = got;
-    } else {
-        (void)hipGetLastError();
-    }
-}
-
-// Room for the symbolic phase to keep the sorted order of every tiny
-// column's products (64 or 128 bytes per column and 64 products), so the
-// numeric phase does not sort again.  Optional, like the dense bitmaps.
-static void reserve_tiny_perm(Plan &p) {
-    const int slots = p.th.tiny_max_flop <= 256 ? 256 : 512;  // the tiny kernels' 64*EMAX
-    const size_t need = (size_t)p.sym_count[kBinTiny] * slots * sizeof(uint16_t);
-    const bool fits = need > 0 && p.m < kPackedRowLimit && need <= kDenseBitsMax &&
-                      (p.tun.workspace_limit <= 0 ||
-                       p.ws_bytes + p.dense_bits_bytes + need <= (size_t)p.tun.workspace_limit);
-    if (fits && p.tiny_perm_bytes >= need) return;
-    pool_put(p.tiny_perm, p.tiny_perm_bytes, false, p.device, p.stream);
     p.tiny_perm = nullptr;
-    p.tiny_perm_bytes = 0;
-    if (!fits) return;
-    void *ptr = nullptr;
-    size_t got = 0;
-    if (pool_get(need, false, p.device, p.stream, &ptr, &got) == SPGEMM_OK) {
-        p.tiny_perm = (uint16_t *)ptr;
-        p.tiny_perm_bytes = got;
-    } else {
-        (void)hipGetLastError();
+    if (need == 0) return;
+    if (p.kept_bytes < need) {
+        pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
+        p.kept = nullptr;
+        p.kept_bytes = 0;
+        void *ptr = nullptr;
+        size_t got = 0;
+        if (pool_get(need, false, p.device, p.stream, &ptr, &got) != SPGEMM_OK) {
+            (void)hipGetLastError();
+            return;
+        }
+        p.kept = ptr;
+        p.kept_bytes = got;
     }
+    char *k = (char *)p.kept;
+    if (dense) p.dense_bits = (uint32_t *)(k + dense_at);
+    if (tiny) p.tiny_perm = (uint16_t *)(k + tiny_at);
 }
 
 static int sync_counters(Plan &p) {
@@ -328,9 +350,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     auto *p = new (std::nothrow) spgemm_plan_s();
     if (!p) return fail(SPGEMM_ENOMEM, "plan allocation failed");
     Plan &pl = *p;
-    if (hipGetDevice(&pl.device) != hipSuccess ||
-        hipDeviceGetAttribute(&pl.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                              pl.device) != hipSuccess) {
+    if (hipGetDevice(&pl.device) != hipSuccess || device_lds_max(pl.device, &pl.lds_max)) {
         delete p;
         return fail(SPGEMM_EHIP, "hipGetDevice / hipDeviceGetAttribute failed");
     }
@@ -583,8 +603,7 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
     SPG_HIP(hipStreamSynchronize(p.stream));
     for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
-    reserve_dense_bits(p);
-    reserve_tiny_perm(p);
+    reserve_kept(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
     if ((rc = launch_colptr_scan(p))) return rc;
     SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
@@ -636,8 +655,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     Plan &p = *plan;
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
     pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream);
-    pool_put(p.dense_bits, p.dense_bits_bytes, false, p.device, p.stream);
-    pool_put(p.tiny_perm, p.tiny_perm_bytes, false, p.device, p.stream);
+    pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;
 }

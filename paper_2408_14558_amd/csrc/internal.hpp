@@ -159,10 +159,10 @@ struct Plan {
     // What the symbolic phase keeps for the numeric phase, per column: its
     // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
     int32_t *col_slot = nullptr;    // n
-    uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns (pooled)
-    size_t dense_bits_bytes = 0;
-    uint16_t *tiny_perm = nullptr;  // sorted order of the terms of tiny columns (pooled)
-    size_t tiny_perm_bytes = 0;
+    void *kept = nullptr;           // pooled block holding the two parts below
+    size_t kept_bytes = 0;
+    uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns
+    uint16_t *tiny_perm = nullptr;  // sorted order of the terms of tiny columns
     int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
     int32_t *tlen = nullptr;      // nnzB
     TermRange term_range() const { return TermRange{tstart, tlen}; }
