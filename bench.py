@@ -319,12 +319,12 @@ def main():
     Bd = spg.DeviceCsc.from_host(w["Bi"], dtype=tdt, device=dev)
     stream = torch.cuda.current_stream()
 
-    ev = []  # (numeric start, numeric end) per timed step
+    ev = []  # (numeric start, numeric end) per instrumented step
 
     tun = spg.tuning(**{k: int(v) for k, v in (t.split("=", 1) for t in args.tune)}) \
         if args.tune else None
 
-    def step(record):
+    def step(record=False):
         p = spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun)
         p.symbolic()
         if record:
@@ -339,14 +339,18 @@ def main():
         return rows, vals
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # the numeric phase inside steps, timed in extra steps outside the timed region
+    for _ in range(min(args.steps, 10)):
+        step(record=True)
+    torch.cuda.synchronize()
     num_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
     # sizes of the workload (from the library's own statistics), and the

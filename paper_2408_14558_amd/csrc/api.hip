@@ -103,8 +103,17 @@ static int pool_get(size_t bytes, bool pinned, int device, hipStream_t stream, v
     return SPGEMM_OK;
 }
 
-static void pool_put(void *ptr, size_t bytes, bool pinned, int device, hipStream_t stream) {
+// Returns a block to the pool.  `last_use`, when given, is an event already
+// recorded after the block's last use (the pool takes it over); otherwise one
+// is recorded on `stream` now.
+static void pool_put(void *ptr, size_t bytes, bool pinned, int device, hipStream_t stream,
+                     hipEvent_t last_use = nullptr) {
     if (!ptr) return;
+    if (last_use) {
+        std::lock_guard<std::mutex> lk(g_pool_mtx);
+        g_pool.push_back(PoolBlock{ptr, bytes, device, pinned, last_use, stream});
+        return;
+    }
     hipEvent_t ev = nullptr;
     if (take_event(&ev) != hipSuccess || hipEventRecord(ev, stream) != hipSuccess) {
         if (ev) (void)hipEventDestroy(ev);
@@ -477,6 +486,17 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.tlen = (int32_t *)(w + o_tln);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);
+    {
+        void *dev = nullptr;
+        if (hipHostGetDevicePointer(&dev, pl.pinned, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            pool_put(pl.ws, pl.ws_bytes, false, pl.device, pl.stream);
+            pool_put(pl.pinned, pl.pinned_bytes, true, pl.device, pl.stream);
+            delete p;
+            return fail(SPGEMM_EHIP, "hipHostGetDevicePointer failed");
+        }
+        pl.hctr_dev = (DevCounters *)((char *)dev + h_ctr);
+    }
     std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
     if (!tiles.empty()) std::memcpy(h + h_tiles, tiles.data(), sizeof(RankTile) * tiles.size());
 
@@ -504,6 +524,16 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
                                                                    "(pointers or sorted unique rows)"));
     }
     if ((rc = launch_plan_kernels(pl))) return cleanup(rc);
+    if (pl.n > 0) {
+        // sparse flops, term ranges and symbolic bins depend on the patterns
+        // only: computed here, right after the gather, with their counts on
+        // their way to the host by the time spgemm_symbolic needs them
+        if ((rc = launch_flop_bin(pl))) return cleanup(rc);
+        e = take_event(&pl.counts_ready);
+        if (e == hipSuccess) e = hipEventRecord(pl.counts_ready, pl.stream);
+        if (e != hipSuccess)
+            return cleanup(fail(SPGEMM_EHIP, std::string("plan counters: ") + hipGetErrorString(e)));
+    }
     *out = p;
     return SPGEMM_OK;
 }
@@ -597,16 +627,17 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
         *nnzC = 0;
         return SPGEMM_OK;
     }
-    // the plan's init cleared the symbolic counters; a later run clears them itself
-    if (p.symbolic_runs++ > 0 && (rc = launch_symbolic_reset(p))) return rc;
-    if ((rc = launch_flop_bin(p))) return rc;
-    SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
-    SPG_HIP(hipStreamSynchronize(p.stream));
-    for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
+    // flops and symbolic bins came with the plan; a later run clears what the
+    // previous symbolic run accumulated
+    if (p.symbolic_runs++ == 0) {
+        SPG_HIP(hipEventSynchronize(p.counts_ready));
+        for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
+    } else if ((rc = launch_symbolic_reset(p))) {
+        return rc;
+    }
     reserve_kept(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
-    if ((rc = launch_colptr_scan(p))) return rc;
-    SPG_HIP(hipMemcpyAsync(p.hctr, p.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, p.stream));
+    if ((rc = launch_colptr_scan(p))) return rc;  // publishes the counters to hctr
     SPG_HIP(hipStreamSynchronize(p.stream));
     p.nnzC = p.hctr->nnzC;
     p.flops = p.hctr->flops.v;
@@ -654,7 +685,9 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     if (!plan) return SPGEMM_OK;
     Plan &p = *plan;
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
-    pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream);
+    // the pinned block's last device-side use is the counters copy that
+    // counts_ready follows (later copies were waited for on the host)
+    pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream, p.counts_ready);
     pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;

@@ -191,6 +191,29 @@ __device__ __forceinline__ long long chained_prefix(uint64_t *status, long long 
     return prefix;
 }
 
+// Called by every thread of every workgroup of a kernel, once, after the
+// workgroup's last update of the counters: the workgroup that finishes last
+// copies the counters to `out` (host memory the host reads once the kernel is
+// done), so no separate device-to-host copy is needed.  `done` counts the
+// finished workgroups.
+__device__ __forceinline__ void publish_when_last(unsigned long long *done,
+                                                  const DevCounters *ctr, DevCounters *out,
+                                                  int *lds_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's counter updates before its ticket
+        *lds_flag = atomicAdd(done, 1ull) == (unsigned long long)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (*lds_flag) {
+        __threadfence();  // every other workgroup's updates are visible
+        const int *src = reinterpret_cast<const int *>(ctr);
+        int *dst = reinterpret_cast<int *>(out);
+        for (int i = threadIdx.x; i < (int)(sizeof(DevCounters) / sizeof(int)); i += blockDim.x)
+            dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Takes the next tile ticket (thread 0) and broadcasts it to the workgroup.
 __device__ __forceinline__ long long take_ticket(unsigned long long *counter, long long *lds_slot) {
     if (threadIdx.x == 0) *lds_slot = (long long)atomicAdd(counter, 1ull);

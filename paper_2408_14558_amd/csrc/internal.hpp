@@ -76,7 +76,14 @@ struct DevCounters {
     LineInt num_count[kNumBins];
 };
 
-enum Ticket { kTkRank = 0, kTkSelect = 1, kTkColptr = 2, kTkExport = 3 };
+enum Ticket {
+    kTkRank = 0,
+    kTkSelect = 1,
+    kTkColptr = 2,
+    kTkExport = 3,
+    kTkFlopDone = 4,    // workgroups of the flops kernel that have finished
+    kTkColptrDone = 5,  // tiles of the colptr scan that have finished
+};
 
 // Where the products of entry q of B_i live in A~: positions [start[q],
 // start[q] + len[q]) of A~'s arrays, i.e. the column map[row of q] (len is 0
@@ -168,12 +175,15 @@ struct Plan {
     TermRange term_range() const { return TermRange{tstart, tlen}; }
     int lds_max = 65536;          // LDS bytes one workgroup may use on this device
 
-    // host view of the counters (inside the pinned block)
+    // host view of the counters (inside the pinned block) and its device
+    // address, where the flops kernel and the colptr scan publish them
     DevCounters *hctr = nullptr;
+    DevCounters *hctr_dev = nullptr;
 
     // symbolic results
     bool symbolic_done = false;
-    int symbolic_runs = 0;  // the plan's init clears the counters for the first run
+    int symbolic_runs = 0;
+    hipEvent_t counts_ready = nullptr;  // the plan's counters (flops, bins) reached hctr
     int64_t *C_colptr = nullptr;
     int64_t nnzC = -1;
     int64_t flops = -1;

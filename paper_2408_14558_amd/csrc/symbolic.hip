@@ -73,8 +73,8 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
     int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
-    int64_t *__restrict__ Ccount, uint64_t *__restrict__ status, int64_t nstatus,
-    DevCounters *__restrict__ ctr) {
+    uint64_t *__restrict__ status, int64_t nstatus, DevCounters *__restrict__ ctr,
+    DevCounters *__restrict__ hout) {
     constexpr int COLS = kFlopThreads / S;
     __shared__ int s_bin[COLS];
     __shared__ int s_lpos[COLS];
@@ -136,12 +136,13 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         sym_bin[j] = b;
         s_bin[tid] = b;
         s_lpos[tid] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
-        if (b == kBinEmpty) Ccount[j] = 0;
         if (f) atomic_add_i64(&s_flops, f);
     }
     __syncthreads();
     if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops.v, s_flops);
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
+    __shared__ int s_last;
+    publish_when_last(&ctr->tickets[kTkFlopDone], ctr, hout, &s_last);
 }
 
 // --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
@@ -296,7 +297,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
 __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
     int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
-    uint64_t *__restrict__ status, int64_t ntiles, DevCounters *__restrict__ ctr) {
+    uint64_t *__restrict__ status, int64_t ntiles, DevCounters *__restrict__ ctr,
+    DevCounters *__restrict__ hout) {
     __shared__ long long s_ticket;
     __shared__ long long s_tmp64[kScanThreads / kWave + 1];
     __shared__ long long s_prefix;
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
         cnt[i] = 0;
         if (lc < nloc) {
             const int64_t j = j0 + lc;
-            cnt[i] = Ccolptr[j];
+            cnt[i] = flop[j] == 0 ? 0 : Ccolptr[j];  // empty columns have no count
             const int b = num_bin_of(flop[j], cnt[i], th);
             num_bin[j] = b;
             s_bin[lc] = b;
@@ -345,28 +347,31 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
         ctr->nnzC = s_prefix + total;
     }
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->num_count, num_list, n);
+    __shared__ int s_last;
+    publish_when_last(&ctr->tickets[kTkColptrDone], ctr, hout, &s_last);
 }
 
-// Clears what one symbolic phase accumulates (the colptr scan ticket, nnzC,
-// flops and the bin counters), for a second symbolic run on one plan.
-__global__ void k_symbolic_reset(DevCounters *__restrict__ ctr) {
+// Clears what one symbolic phase accumulates (the colptr scan's ticket and
+// tile states, nnzC and the numeric bin counters), for a second symbolic
+// run on one plan.  The flops and symbolic bins come from the plan.
+__global__ void k_symbolic_reset(DevCounters *__restrict__ ctr, uint64_t *__restrict__ status,
+                                 int64_t nstatus) {
     const int t = threadIdx.x;
     if (t == 0) {
         ctr->tickets[kTkColptr] = 0;
+        ctr->tickets[kTkColptrDone] = 0;
         ctr->nnzC = 0;
-        ctr->flops.v = 0;
     }
-    if (t < kNumBins) {
-        ctr->sym_count[t].v = 0;
-        ctr->num_count[t].v = 0;
-    }
+    if (t < kNumBins) ctr->num_count[t].v = 0;
+    for (int64_t s = t; s < nstatus; s += blockDim.x) status[s] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 int launch_symbolic_reset(Plan &p) {
-    hipLaunchKernelGGL(k_symbolic_reset, dim3(1), dim3(64), 0, p.stream, p.ctr);
+    hipLaunchKernelGGL(k_symbolic_reset, dim3(1), dim3(256), 0, p.stream, p.ctr, p.st_colptr,
+                       p.n_col_tiles);
     SPG_LAUNCHED("k_symbolic_reset");
     return SPGEMM_OK;
 }
@@ -377,9 +382,8 @@ static int flop_bin_launch(Plan &p) {
     const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
                        p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot,
-                       p.flop,
-                       p.sym_bin, p.sym_list,
-                       p.C_colptr, p.st_colptr, p.n_col_tiles, p.ctr);
+                       p.flop, p.sym_bin, p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr,
+                       p.hctr_dev);
     SPG_LAUNCHED("k_flop_bin");
     return SPGEMM_OK;
 }
@@ -448,7 +452,7 @@ int launch_colptr_scan(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     hipLaunchKernelGGL(k_colptr_scan, dim3((unsigned)p.n_col_tiles), dim3(kScanThreads), 0,
                        p.stream, p.n, p.C_colptr, p.flop, p.th, p.num_bin, p.num_list,
-                       p.st_colptr, p.n_col_tiles, p.ctr);
+                       p.st_colptr, p.n_col_tiles, p.ctr, p.hctr_dev);
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
 }
