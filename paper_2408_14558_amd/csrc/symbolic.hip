@@ -276,7 +276,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int gt = threadIdx.x;
     for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
     __syncthreads();
-    for_each_term<kDenseThreads, float, kSymDenseUnroll>(
+    // short entries stay with their thread: a flat walk would give a wave
+    // consecutive rows of one column of A~, whose bits share words
+    for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
         Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
         [&](int64_t p) { return At_rowidx[p]; },
         [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });

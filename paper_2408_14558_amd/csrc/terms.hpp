@@ -25,8 +25,10 @@ struct TermStage {
     long long lstart[CH];  // long entries: first position in A~ still to visit
     long long lend[CH];    // one past the entry's last position
     V lbv[CH];             // b_kj
-    int lnext[CH];         // offset (from lstart) of the entry's next unclaimed piece
+    int lnext[CH];         // long entries: offset (from lstart) of the next unclaimed
+                           // piece; short ones: offset of the first term in the flat list
     int nlong;
+    int qnext;             // next long entry to start
     int tmp[kMaxGroupWaves + 2];  // scratch for a group scan of the caller
 };
 
@@ -38,26 +40,78 @@ struct TermStageCursor : TermStage<CH, V> {
     int lcut[CH];  // offset from lstart of the first term at or past the window
 };
 
-// Long entries of a chunk are dealt to the group's waves round-robin, each
-// walked in pieces of U*64 consecutive terms claimed from the entry's lnext
-// counter.  A wave that has finished its own entries claims pieces of the
-// others, so a few very long columns of A~ (hubs of a power-law matrix) do
-// not leave the other waves idle.  Stealing is tried when the chunk has at
-// most kStealFactor long entries per wave (more entries balance by
-// themselves).
-#ifndef SPG_STEAL_FACTOR
-#define SPG_STEAL_FACTOR 4
-#endif
-constexpr int kStealFactor = SPG_STEAL_FACTOR;
+constexpr int next_pow2_const(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
 
-// Claims the next piece of long entry li for the calling wave: the offset of
-// its first term from lstart (wave-uniform).
+// Long entries of a chunk (stage slots [0, nl)) are handed to the group's
+// waves one at a time from a shared counter (qnext), and each is walked in
+// pieces of U*64 consecutive terms claimed from its own counter (lnext).  A
+// wave that finds no entry left to start helps on the entries that still
+// have unclaimed pieces, so hub columns of A~ (power-law inputs) are spread
+// over the group instead of holding one wave while the others wait.
+
+// The next long entry to start for the calling wave (wave-uniform).
 template <int CH, typename V>
-__device__ __forceinline__ int claim_piece(TermStage<CH, V> *st, int li, int piece) {
+__device__ __forceinline__ int claim_entry(TermStage<CH, V> *st) {
+    int e = 0;
+    if (lane_id() == 0) e = atomicAdd(&st->qnext, 1);
+    return __shfl(e, 0);
+}
+
+// The offset (from lstart) of the next unclaimed piece of entry e.
+template <int CH, typename V>
+__device__ __forceinline__ int claim_piece(TermStage<CH, V> *st, int e, int piece) {
     int off = 0;
-    if (lane_id() == 0) off = atomicAdd(&st->lnext[li], piece);
+    if (lane_id() == 0) off = atomicAdd(&st->lnext[e], piece);
     return __shfl(off, 0);
 }
+
+// A long entry with unclaimed pieces before lim(e), or -1 (one LDS read per
+// 64 entries); the search starts at entry `from` (a different one for every
+// wave).
+template <typename LIM>
+__device__ __forceinline__ int entry_with_work(const int *lnext, int nl, int from, LIM &&lim) {
+    const int first = nl > 0 ? from % nl : 0;
+    for (int b = 0; b < nl; b += kWave) {
+        int e = first + b + lane_id();
+        if (e >= nl) e -= nl;  // b + lane < nl and first < nl, so e < 2 nl
+        const bool left = b + lane_id() < nl && lnext[e] < lim(e);
+        const uint64_t m = __ballot(left);
+        if (m) return __shfl(e, __ffsll((unsigned long long)m) - 1);
+    }
+    return -1;
+}
+
+// Short entries of a chunk are walked as one flat list of terms spread over
+// the whole group (G > 64): the entries sit in the stage's slots
+// [CH - ns, CH) in entry order, lnext[s] holding the offset of the slot's
+// first term in the list.  Returns the slot holding term t (0 <= t < the
+// list's length): a fixed-depth search, so the U searches of a thread
+// overlap.
+template <int CH, typename V>
+__device__ __forceinline__ int short_slot(const TermStage<CH, V> *st, int ns, int t) {
+    constexpr int kTop = next_pow2_const(CH) >> 1;  // evaluated at compile time
+    int lo = CH - ns;
+#pragma unroll
+    for (int step = kTop; step > 0; step >>= 1) {
+        const int c = min(lo + step, CH - 1);  // the read stays in bounds, no branch
+        lo = (lo + step < CH && st->lnext[c] <= t) ? lo + step : lo;
+    }
+    return lo;
+}
+
+// Terms of the flat short list taken per thread per round: a chunk holds at
+// most CH * kShortLen of them, spread over G threads, so few rounds suffice.
+template <int G>
+constexpr int short_unroll() { return G >= 512 ? 2 : 4; }
+
+// Scan value of one entry for the flat short list: (1 << 16) | its length
+// (a chunk holds at most 1024 entries of at most kShortLen terms, so the
+// length sum stays below 2^16 and the count below 2^11).
+__device__ __forceinline__ int short_code(int len) { return len > 0 ? ((1 << 16) | len) : 0; }
 
 // A term's row id and a_ik.
 template <typename V>
@@ -75,7 +129,8 @@ constexpr int kUnroll = 4;
 // bv) it calls ap(ld(p), bv); ld does the global loads, ap the LDS work, so
 // kUnroll loads per thread are in flight before the first use.  All G
 // threads must call it (it synchronises the group).
-template <int G, typename V, int U = kUnroll, int CH = G, typename LD, typename AP>
+template <int G, typename V, int U = kUnroll, int CH = G, bool kFlat = true, typename LD,
+          typename AP>
 __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange tr,
                                               const V *__restrict__ Bvals,
                                               TermStage<CH, V> *st, int gt, LD &&ld, AP &&ap) {
@@ -85,7 +140,10 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
     constexpr int NTEAM = G / TEAM;
     const int team = gt / TEAM, tl = gt % TEAM;
     for (int64_t qb = q0; qb < q1; qb += CH) {
-        if (gt == 0) st->nlong = 0;
+        if (gt == 0) {
+            st->nlong = 0;
+            st->qnext = 0;
+        }
         group_sync<G>();
         const int64_t q = qb + gt;
         long long start = 0;
@@ -101,44 +159,91 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
             st->lstart[slot] = start;
             st->lend[slot] = start + len;
             st->lbv[slot] = bv;
-        } else {
-            for (int e = 0; e < len; e += kUnroll) {
-                Item it[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (e + u < len) it[u] = ld((int64_t)(start + e + u));
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (e + u < len) ap(it[u], bv);
-            }
+            st->lnext[slot] = 0;
         }
-        group_sync<G>();
-        const int nl = st->nlong;
         if constexpr (G > kWave) {
-            constexpr int PS = U * kWave;
-            if (gt < nl) st->lnext[gt] = 0;
+            // short entries: one flat list of terms over the whole group, or
+            // (kFlat false) each walked by the thread that loaded it
+            int ns = 0, nt = 0;
+            if constexpr (kFlat) {
+                int tot;
+                const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0),
+                                                  st->tmp, &tot);
+                ns = tot >> 16;
+                nt = tot & 0xFFFF;
+                if (len > 0 && len <= kShortLen) {
+                    const int slot = CH - ns + (sp >> 16);
+                    st->lstart[slot] = start;
+                    st->lbv[slot] = bv;
+                    st->lnext[slot] = sp & 0xFFFF;
+                }
+            } else if (len <= kShortLen) {
+                for (int e = 0; e < len; e += kUnroll) {
+                    Item it[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (e + u < len) it[u] = ld((int64_t)(start + e + u));
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (e + u < len) ap(it[u], bv);
+                }
+            }
             group_sync<G>();
-            auto walk = [&](int li) {
-                const long long s0 = st->lstart[li];
-                const int len = (int)(st->lend[li] - s0);
-                const V b = st->lbv[li];
+            const int nl = st->nlong;
+            constexpr int SU = short_unroll<G>();
+            for (int t0 = 0; t0 < nt; t0 += SU * G) {
+                Item it[SU];
+                V b[SU];
+                // threads past the list's end load its last term again (in
+                // bounds, no divergent branch) and do not apply it
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int t = min(t0 + u * G + gt, nt - 1);
+                    const int sl = short_slot<CH, V>(st, ns, t);
+                    it[u] = ld((int64_t)(st->lstart[sl] + (t - st->lnext[sl])));
+                    b[u] = st->lbv[sl];
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u)
+                    if (t0 + u * G + gt < nt) ap(it[u], b[u]);
+            }
+            constexpr int PS = U * kWave;
+            auto walk = [&](int e) {
+                const long long s0 = st->lstart[e];
+                const int len = (int)(st->lend[e] - s0);
+                const V b = st->lbv[e];
                 while (true) {
-                    const int off = claim_piece<CH, V>(st, li, PS);
+                    const int off = claim_piece<CH, V>(st, e, PS);
                     if (off >= len) break;
-                    const long long s = s0 + off, t = s0 + min(len, off + PS);
                     Item it[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u)
-                        if (s + u * kWave + tl < t) it[u] = ld((int64_t)(s + u * kWave + tl));
+                        if (off + u * kWave + tl < len)
+                            it[u] = ld((int64_t)(s0 + off + u * kWave + tl));
 #pragma unroll
                     for (int u = 0; u < U; ++u)
-                        if (s + u * kWave + tl < t) ap(it[u], b);
+                        if (off + u * kWave + tl < len) ap(it[u], b);
                 }
             };
-            for (int li = team; li < nl; li += NTEAM) walk(li);
-            if (nl <= kStealFactor * NTEAM)
-                for (int k = 1; k < nl; ++k) walk((team + k) % nl);
+            for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
+            auto lim = [&](int e) { return (int)(st->lend[e] - st->lstart[e]); };
+            for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
+                 e = entry_with_work(st->lnext, nl, team, lim))
+                walk(e);
         } else {
+            if (len <= kShortLen) {
+                for (int e = 0; e < len; e += kUnroll) {
+                    Item it[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (e + u < len) it[u] = ld((int64_t)(start + e + u));
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (e + u < len) ap(it[u], bv);
+                }
+            }
+            group_sync<G>();
+            const int nl = st->nlong;
             for (int li = team; li < nl; li += NTEAM) {
                 const long long s = st->lstart[li], t = st->lend[li];
                 const V b = st->lbv[li];
@@ -177,65 +282,97 @@ __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int3
     const int team = gt / kWave, tl = lane_id();
     static_assert(CH <= G && G <= kMaxGroupWaves * kWave, "chunk and group sizes");
     for (int64_t qb = q0; qb < q1; qb += CH) {
-        if (gt == 0) st->nlong = 0;
+        if (gt == 0) {
+            st->nlong = 0;
+            st->qnext = 0;
+        }
         group_sync<G>();
         const int64_t q = qb + gt;
+        int len = 0, rel = 0;
+        long long c0 = 0;
+        V bv = V(0);
         if (gt < CH && q < q1) {
-            const int len = tr.len[q];
+            len = tr.len[q];
             if (len > 0) {
-                const long long c0 = tr.start[q];
-                const long long end = c0 + len;
-                const int rel = first ? 0 : cursor[q - q0];
-                const V bv = Bvals[q];
-                if (end - c0 > kShortLen) {
-                    const int slot = atomicAdd(&st->nlong, 1);
-                    st->lstart[slot] = c0 + rel;
-                    st->lend[slot] = end;
-                    st->lbv[slot] = bv;
-                    st->llen[slot] = (int)(end - c0);
-                    st->lq[slot] = (int)(q - q0);
-                } else {
-                    long long pos = c0 + rel;
-                    while (pos < end) {
-                        const int32_t r = At_rowidx[pos];
-                        if (r >= r_hi) break;
-                        ap(r, ldv((int64_t)pos), bv);
-                        ++pos;
-                    }
-                    cursor[q - q0] = (int32_t)(pos - c0);
-                }
+                c0 = tr.start[q];
+                rel = first ? 0 : cursor[q - q0];
+                bv = Bvals[q];
             }
+        }
+        if (len > kShortLen && rel < len) {
+            const int slot = atomicAdd(&st->nlong, 1);
+            st->lstart[slot] = c0 + rel;
+            st->lend[slot] = c0 + len;
+            st->lbv[slot] = bv;
+            st->llen[slot] = len;
+            st->lq[slot] = (int)(q - q0);
+            st->lcut[slot] = len - rel;
+            st->lnext[slot] = 0;
+        }
+        // short entries: the unvisited rest of each is one run of a flat term
+        // list over the whole group; lcut counts the run's terms below r_hi
+        // (a prefix of the run, rows ascending)
+        const int rest = len <= kShortLen ? len - rel : 0;
+        int tot;
+        const int sp = group_excl_scan<G>(short_code(rest), st->tmp, &tot);
+        const int ns = tot >> 16, nt = tot & 0xFFFF;
+        if (rest > 0) {
+            const int slot = CH - ns + (sp >> 16);
+            st->lstart[slot] = c0 + rel;
+            st->lbv[slot] = bv;
+            st->lnext[slot] = sp & 0xFFFF;
+            st->llen[slot] = rel;
+            st->lq[slot] = (int)(q - q0);
+            st->lcut[slot] = 0;
         }
         group_sync<G>();
         const int nl = st->nlong;
-        constexpr int PS = U * kWave;
-        if (gt < nl) {
-            st->lnext[gt] = 0;
-            st->lcut[gt] = (int)(st->lend[gt] - st->lstart[gt]);
+        constexpr int SU = short_unroll<G>();
+        for (int t0 = 0; t0 < nt; t0 += SU * G) {
+            int32_t r[SU];
+            long long pos[SU];
+            int sl[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int t = min(t0 + u * G + gt, nt - 1);
+                sl[u] = short_slot<CH, V>(st, ns, t);
+                pos[u] = st->lstart[sl[u]] + (t - st->lnext[sl[u]]);
+                r[u] = At_rowidx[pos[u]];
+                if (t0 + u * G + gt >= nt) r[u] = kNoRow;  // a repeat of the last term
+            }
+            V v[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                if (r[u] < r_hi) v[u] = ldv((int64_t)pos[u]);
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                if (r[u] < r_hi) {
+                    ap(r[u], v[u], st->lbv[sl[u]]);
+                    atomicAdd(&st->lcut[sl[u]], 1);
+                }
+            }
         }
-        group_sync<G>();
-        auto walk = [&](int li) {
-            const long long s0 = st->lstart[li];
-            const int len = (int)(st->lend[li] - s0);
-            const V b = st->lbv[li];
+        // long entries: a piece that meets r_hi sets the entry's cut (rows
+        // ascend inside an entry, so its later pieces hold nothing for this
+        // window)
+        constexpr int PS = U * kWave;
+        auto walk = [&](int e) {
+            const long long s0 = st->lstart[e];
+            const int len = (int)(st->lend[e] - s0);
+            const V b = st->lbv[e];
             while (true) {
-                const int off = claim_piece<CH, V>(st, li, PS);
-                // rows ascend inside an entry: once a piece has met r_hi, the
-                // entry's later pieces hold nothing for this window
-                if (off >= st->lcut[li]) break;
-                const long long s = s0 + off, t = s0 + min(len, off + PS);
+                const int off = claim_piece<CH, V>(st, e, PS);
+                if (off >= st->lcut[e]) break;
                 int32_t r[U];
                 V v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const long long e = s + u * kWave + tl;
-                    r[u] = e < t ? At_rowidx[e] : kNoRow;
+                    const int p = off + u * kWave + tl;
+                    r[u] = p < len ? At_rowidx[s0 + p] : kNoRow;
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const long long e = s + u * kWave + tl;
-                    if (r[u] < r_hi) v[u] = ldv((int64_t)e);
-                }
+                for (int u = 0; u < U; ++u)
+                    if (r[u] < r_hi) v[u] = ldv((int64_t)(s0 + off + u * kWave + tl));
                 int cnt = 0;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -243,16 +380,19 @@ __device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int3
                     // the positions below r_hi are a prefix of the piece
                     cnt += __popcll(__ballot(r[u] < r_hi));
                 }
-                if (s + cnt < t) {
-                    if (tl == 0) atomicMin(&st->lcut[li], off + cnt);
+                if (off + cnt < min(len, off + PS)) {
+                    if (tl == 0) atomicMin(&st->lcut[e], off + cnt);
                     break;
                 }
             }
         };
-        for (int li = team; li < nl; li += NTEAM) walk(li);
-        if (nl <= kStealFactor * NTEAM)
-            for (int k = 1; k < nl; ++k) walk((team + k) % nl);
+        for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
+        auto lim = [&](int e) { return st->lcut[e]; };
+        for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
+             e = entry_with_work(st->lnext, nl, team, lim))
+            walk(e);
         group_sync<G>();
+        if (gt >= CH - ns && gt < CH) cursor[st->lq[gt]] = st->llen[gt] + st->lcut[gt];
         if (gt < nl)
             cursor[st->lq[gt]] =
                 (int32_t)(st->lstart[gt] + st->lcut[gt] - (st->lend[gt] - st->llen[gt]));
