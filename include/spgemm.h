@@ -81,7 +81,10 @@ typedef struct {
                                    (0 = 4, at most 8) */
     int32_t batch_persistent;   /* must be 0: the single-launch persistent form of the
                                    batch is switched off (SPGEMM_EUNSUPPORTED) */
-    int32_t reserved[2];        /* must be 0 */
+    int32_t dense_first_flop;   /* dense output columns with at least this many products are
+                                   handed out first (numeric bin 7), so the longest ones do
+                                   not finish last; 0 = no such bin */
+    int32_t reserved;           /* must be 0 */
     int64_t workspace_limit;    /* bytes of device workspace a plan may take; 0 = no limit */
 } spgemm_tuning;
 
@@ -99,7 +102,8 @@ typedef struct {
     int64_t flops;          /* sparse flops of A*B_i (-1 before symbolic) */
     int64_t nnz_C;          /* stored entries of C_i (-1 before symbolic) */
     int64_t sym_bins[8];    /* columns per symbolic bin: 0 empty, 1 tiny, 2..5 hash, 6 bitmap, 7 unused */
-    int64_t num_bins[8];    /* columns per numeric bin: 0 empty, 1 tiny, 2..5 hash, 6 dense, 7 unused */
+    int64_t num_bins[8];    /* columns per numeric bin: 0 empty, 1 tiny, 2..5 hash, 6 dense,
+                               7 dense with at least dense_first_flop products */
 } spgemm_stats;
 
 typedef struct spgemm_plan_s *spgemm_plan_t;
@@ -114,7 +118,7 @@ const char *spgemm_version(void);
  * Fills *t with the default tuning.  Environment variables override single
  * fields (decimal integers; unparsable values are ignored, ranges are
  * checked when a plan uses the tuning): SPGEMM_TINY_MAX_FLOP,
- * SPGEMM_HASH_MAX_FLOP, SPGEMM_HASH_MAX_NNZ, SPGEMM_DENSE_WINDOW,
+ * SPGEMM_HASH_MAX_FLOP, SPGEMM_HASH_MAX_NNZ, SPGEMM_DENSE_WINDOW, SPGEMM_DENSE_FIRST_FLOP,
  * SPGEMM_MEDIUM_KERNEL, SPGEMM_BATCH_STREAMS, SPGEMM_VALIDATE,
  * SPGEMM_WORKSPACE_LIMIT.  Returns SPGEMM_EINVAL for NULL.
  */

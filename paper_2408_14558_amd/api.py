@@ -88,7 +88,7 @@ def tuning(**kw) -> _lib.Tuning:
     return t
 
 
-BIN_NAMES = ["empty", "tiny", "hash0", "hash1", "hash2", "hash3", "dense", "unused"]
+BIN_NAMES = ["empty", "tiny", "hash0", "hash1", "hash2", "hash3", "dense", "dense-first"]
 
 
 class Plan:

@@ -145,6 +145,31 @@ static int pool_trim() {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// Compute units of a device (queried once); 0 if the query fails.
+int device_cu_count(int device) {
+    static std::mutex mtx;
+    static std::vector<int> cache;
+    std::lock_guard<std::mutex> lk(mtx);
+    if (device < 0) return 0;
+    if ((size_t)device >= cache.size()) cache.resize(device + 1, 0);
+    if (cache[device] == 0 &&
+        hipDeviceGetAttribute(&cache[device], hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess)
+        cache[device] = 0;
+    return cache[device];
+}
+
+unsigned resident_groups(const void *kernel, int threads, size_t lds, int device,
+                         long long work) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
+        (void)hipGetLastError();
+    const long long cus = device_cu_count(device);
+    long long g = (long long)std::max(per_cu, 1) * (cus > 0 ? cus : 256);
+    g = std::min(g, work);
+    return (unsigned)std::max(g, 1LL);
+}
+
 // LDS bytes one workgroup may use, per device (queried once).
 static int device_lds_max(int device, int *out) {
     static std::mutex mtx;
@@ -209,6 +234,7 @@ static void thresholds_from(const spgemm_tuning &t, Thresholds &th) {
             prev = th.num_hash_max[h];
         }
     }
+    th.dense_first_flop = t.dense_first_flop;
 }
 
 static int check_tuning(const spgemm_tuning &t) {
@@ -225,8 +251,8 @@ static int check_tuning(const spgemm_tuning &t) {
         return fail(SPGEMM_EINVAL, "medium_kernel must be 0, 1 or 2");
     if (t.batch_streams < 0 || t.batch_streams > 8)
         return fail(SPGEMM_EINVAL, "batch_streams must lie in [0, 8]");
-    if (t.reserved[0] != 0 || t.reserved[1] != 0)
-        return fail(SPGEMM_EINVAL, "reserved tuning fields must be 0");
+    if (t.dense_first_flop < 0) return fail(SPGEMM_EINVAL, "dense_first_flop must be >= 0");
+    if (t.reserved != 0) return fail(SPGEMM_EINVAL, "reserved tuning fields must be 0");
     return SPGEMM_OK;
 }
 
@@ -307,7 +333,8 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->medium_kernel = 0;
     t->batch_streams = 0;
     t->batch_persistent = 0;
-    t->reserved[0] = t->reserved[1] = 0;
+    t->dense_first_flop = 1 << 18;
+    t->reserved = 0;
     t->validate = 0;
     t->own_partition = -1;
     t->own_partition_whole = 0;
@@ -316,6 +343,7 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     env_override("SPGEMM_HASH_MAX_FLOP", &t->hash_max_flop);
     env_override("SPGEMM_HASH_MAX_NNZ", &t->hash_max_nnz);
     env_override("SPGEMM_DENSE_WINDOW", &t->dense_window);
+    env_override("SPGEMM_DENSE_FIRST_FLOP", &t->dense_first_flop);
     env_override("SPGEMM_MEDIUM_KERNEL", &t->medium_kernel);
     env_override("SPGEMM_BATCH_STREAMS", &t->batch_streams);
     env_override("SPGEMM_VALIDATE", &t->validate);

@@ -44,7 +44,8 @@ static int64_t product_launches(const Plan &p, const spgemm_batch_io &io) {
     int64_t n = 0;
     if (io.A_vals && p.k > 0 && p.nnzA > 0) ++n;
     if (p.n == 0 || p.nnzC == 0) return n;
-    for (int bin = kBinTiny; bin <= kBinDense; ++bin) n += p.num_count[bin] > 0;
+    for (int bin = kBinTiny; bin < kBinDense; ++bin) n += p.num_count[bin] > 0;
+    n += p.num_count[kBinDense] + p.num_count[kBinDenseFirst] > 0;  // one launch serves both
     return n;
 }
 

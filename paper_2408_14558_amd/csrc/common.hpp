@@ -245,6 +245,30 @@ __device__ __forceinline__ void lds_atomic_add(V *p, V v) {
     atomicAdd(p, v);
 }
 
+// Work queue of a launch with fewer workgroups than items (q[0]: next item,
+// q[1]: workgroups finished): every workgroup takes items in turn until
+// they run out, so no compute unit idles while items are left and the long
+// items do not wait behind the dispatch order.  All threads of the group
+// call; s_item is LDS.
+__device__ __forceinline__ int queue_take(unsigned int *q, int *s_item) {
+    __syncthreads();  // every thread has read the previous item
+    if (threadIdx.x == 0) *s_item = (int)atomicAdd(&q[0], 1u);
+    __syncthreads();
+    return *s_item;
+}
+
+// Called once by every workgroup after its last queue_take: the last one to
+// leave puts the queue back to 0 for the next launch.
+__device__ __forceinline__ void queue_leave(unsigned int *q) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&q[1], 1u) == gridDim.x - 1) {
+            atomicExch(&q[0], 0u);
+            atomicExch(&q[1], 0u);
+        }
+    }
+}
+
 __device__ __forceinline__ int next_pow2(int x) {
     int p = 1;
     while (p < x) p <<= 1;

@@ -22,6 +22,7 @@ enum Bin : int {
     kBinH2 = 4,
     kBinH3 = 5,    // LDS hash, largest table
     kBinDense = 6, // LDS bitmap over all rows (symbolic) / rank windows (numeric)
+    kBinDenseFirst = 7,  // numeric: dense columns with the most products, handed out first
     kNumBins = 8
 };
 
@@ -74,6 +75,10 @@ struct DevCounters {
     LineI64 flops;
     LineInt sym_count[kNumBins];
     LineInt num_count[kNumBins];
+    // work queues of the dense kernels: next column, workgroups finished
+    // (the last workgroup of a launch puts both back to 0)
+    unsigned int num_dense_queue[2];
+    unsigned int sym_dense_queue[2];
 };
 
 enum Ticket {
@@ -106,6 +111,7 @@ struct Thresholds {
     int tiny_max_flop;
     int sym_hash_max[4];  // flop limit per symbolic hash bin (0 = bin unused)
     int num_hash_max[4];  // nnz limit per numeric hash bin
+    int dense_first_flop;  // dense columns with at least this many products: bin 7 (0 = none)
 };
 
 // ---------------------------------------------------------------------------
@@ -217,6 +223,12 @@ int fail(int code, const std::string &msg);
 // ---------------------------------------------------------------------------
 // launchers (each returns SPGEMM_OK or an error code with the message set)
 // ---------------------------------------------------------------------------
+// Compute units of a device (queried once; 0 if unknown).
+int device_cu_count(int device);
+// Workgroups of `kernel` (threads each, lds bytes of dynamic LDS) that fit
+// on the device at once, capped at `work` (at least 1).
+unsigned resident_groups(const void *kernel, int threads, size_t lds, int device, long long work);
+
 int launch_validate(Plan &p);
 int launch_plan_kernels(Plan &p);
 int launch_gather_values(Plan &p, const void *Avals);

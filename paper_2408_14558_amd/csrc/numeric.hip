@@ -44,17 +44,22 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_num_hash(const int32_t *_
 }
 
 template <typename V>
-__global__ __launch_bounds__(kDenseThreads) void k_num_dense(const int32_t *__restrict__ list,
-                                                             int count, NumArgs<V> a, int VC) {
+__global__ __launch_bounds__(kDenseThreads) void k_num_dense(
+    const int32_t *__restrict__ first, int nfirst, const int32_t *__restrict__ list, int count,
+    NumArgs<V> a, int VC, DevCounters *__restrict__ ctr) {
+    unsigned int *queue = ctr->num_dense_queue;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ NumDenseStatic<kDenseThreads, V> S;
-    const int w = blockIdx.x;
-    if (w >= count) return;
+    __shared__ int s_item;
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
     V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
-    num_dense_column<kDenseThreads, V>(a, list[w], bits, wpre, vals, VC, S);
+    // the columns with the most products (list `first`) go out first
+    for (int w = queue_take(queue, &s_item); w < nfirst + count; w = queue_take(queue, &s_item))
+        num_dense_column<kDenseThreads, V>(a, w < nfirst ? first[w] : list[w - nfirst], bits,
+                                           wpre, vals, VC, S);
+    queue_leave(queue);
 }
 
 template <int G, typename V>
@@ -136,7 +141,8 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
     if ((rc = num_hash_launch<kNumTable[1], kNumTable[1] / 8, V>(p, kBinH1, a))) return rc;
     if ((rc = num_hash_launch<kNumTable[2], kNumTable[2] / 8, V>(p, kBinH2, a))) return rc;
     if ((rc = num_hash_launch<kNumTable[3], kNumTable[3] / 8, V>(p, kBinH3, a))) return rc;
-    if (p.num_count[kBinDense] > 0) {
+    const int ndense = p.num_count[kBinDense] + p.num_count[kBinDenseFirst];
+    if (ndense > 0) {
         if (p.m > kMaxDenseRows)
             return fail(SPGEMM_EUNSUPPORTED,
                         "columns with more rows than the largest hash bin need m <= 262144");
@@ -146,9 +152,13 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
             lds -= (size_t)(VC - p.tun.dense_window) * sizeof(V);
             VC = p.tun.dense_window;
         }
-        hipLaunchKernelGGL(k_num_dense<V>, dim3(p.num_count[kBinDense]), dim3(kDenseThreads), lds,
-                           p.stream, list(kBinDense), p.num_count[kBinDense], a, VC);
-        SPG_LAUNCHED("k_num_dense (dynamic LDS " + std::to_string(lds) + " B)");
+        const unsigned grid = resident_groups((const void *)k_num_dense<V>, kDenseThreads, lds,
+                                              p.device, ndense);
+        hipLaunchKernelGGL(k_num_dense<V>, dim3(grid), dim3(kDenseThreads), lds, p.stream,
+                           list(kBinDenseFirst), p.num_count[kBinDenseFirst], list(kBinDense),
+                           p.num_count[kBinDense], a, VC, p.ctr);
+        SPG_LAUNCHED("k_num_dense (" + std::to_string(grid) + " workgroups, dynamic LDS " +
+                     std::to_string(lds) + " B)");
     }
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;

@@ -266,32 +266,36 @@ struct SymDenseLds {
 __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
     TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
-    uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot) {
+    uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot,
+    DevCounters *__restrict__ ctr) {
     extern __shared__ uint32_t s_bits[];
     __shared__ SymDenseLds L;
-    const int w = blockIdx.x;
-    if (w >= count) return;
-    const int32_t j = list[w];
+    __shared__ int s_item;
+    unsigned int *queue = ctr->sym_dense_queue;
     const int nw = (int)((m + 31) >> 5);
     const int gt = threadIdx.x;
-    for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
-    __syncthreads();
-    // short entries stay with their thread: a flat walk would give a wave
-    // consecutive rows of one column of A~, whose bits share words
-    for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
-        Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
-        [&](int64_t p) { return At_rowidx[p]; },
-        [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
-    int c = 0;
-    for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
-    int total;
-    (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
-    if (gt == 0) Ccount[j] = total;
-    if (keep_bits) {  // the numeric phase reuses this bitmap
-        uint32_t *dst = keep_bits + (size_t)w * nw;
-        for (int i = gt; i < nw; i += kDenseThreads) dst[i] = s_bits[i];
-        if (gt == 0) col_slot[j] = w;
+    for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item)) {
+        const int32_t j = list[w];
+        for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
+        __syncthreads();
+        // short entries stay with their thread: a flat walk would give a wave
+        // consecutive rows of one column of A~, whose bits share words
+        for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
+            Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
+            [&](int64_t p) { return At_rowidx[p]; },
+            [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
+        int c = 0;
+        for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
+        int total;
+        (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
+        if (gt == 0) Ccount[j] = total;
+        if (keep_bits) {  // the numeric phase reuses this bitmap
+            uint32_t *dst = keep_bits + (size_t)w * nw;
+            for (int i = gt; i < nw; i += kDenseThreads) dst[i] = s_bits[i];
+            if (gt == 0) col_slot[j] = w;
+        }
     }
+    queue_leave(queue);
 }
 
 // Exclusive scan of the per-column counts into C_i's column pointers (in
@@ -323,7 +327,9 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
         if (lc < nloc) {
             const int64_t j = j0 + lc;
             cnt[i] = flop[j] == 0 ? 0 : Ccolptr[j];  // empty columns have no count
-            const int b = num_bin_of(flop[j], cnt[i], th);
+            int b = num_bin_of(flop[j], cnt[i], th);
+            if (b == kBinDense && th.dense_first_flop > 0 && flop[j] >= th.dense_first_flop)
+                b = kBinDenseFirst;
             num_bin[j] = b;
             s_bin[lc] = b;
             s_lpos[lc] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
@@ -440,12 +446,13 @@ int launch_symbolic_bins(Plan &p) {
             return fail(SPGEMM_EUNSUPPORTED,
                         "columns with more flops than the largest hash bin need m <= 262144");
         const size_t lds = (size_t)((p.m + 31) / 32) * 4;
-        hipLaunchKernelGGL(k_sym_dense, dim3((unsigned)p.sym_count[kBinDense]),
-                           dim3(kDenseThreads), lds, p.stream,
+        const unsigned grid = resident_groups((const void *)k_sym_dense, kDenseThreads, lds,
+                                              p.device, p.sym_count[kBinDense]);
+        hipLaunchKernelGGL(k_sym_dense, dim3(grid), dim3(kDenseThreads), lds, p.stream,
                            p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
                            p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr, p.dense_bits,
-                           p.col_slot);
-        SPG_LAUNCHED("k_sym_dense");
+                           p.col_slot, p.ctr);
+        SPG_LAUNCHED("k_sym_dense (" + std::to_string(grid) + " workgroups)");
     }
     return SPGEMM_OK;
 }

@@ -46,7 +46,7 @@ def test_default_tuning_and_version(lib):
     t = _lib.Tuning()
     assert lib.spgemm_default_tuning(ctypes.byref(t)) == 0
     assert t.tiny_max_flop == 256 and t.hash_max_flop == 4096 and t.hash_max_nnz == 2048
-    assert t.batch_streams == 0 and t.batch_persistent == 0 and list(t.reserved) == [0, 0]
+    assert t.batch_streams == 0 and t.batch_persistent == 0 and t.reserved == 0
     assert ctypes.sizeof(_lib.Tuning) == 56
     assert lib.spgemm_default_tuning(None) == _lib.EINVAL
     assert b"gfx950" in lib.spgemm_version()
@@ -122,7 +122,7 @@ def test_host_side_rejections(lib, case):
         elif case == "hash_tuning":
             tun.hash_max_nnz = 4096
         elif case == "reserved_tuning":
-            tun.reserved[1] = 1
+            tun.reserved = 1
         else:
             tun.batch_streams = 9
     rc, h = _plan(lib, A, B, offs, P, b, tun, dtype)

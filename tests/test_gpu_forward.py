@@ -143,7 +143,7 @@ def test_every_bin_gives_the_same_product(name):
     st, sbin, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 1), 64, tun=tun)
     print(name, "sym bins", st["sym_bins"], "num bins", st["num_bins"], flush=True)
     if name in ("all_dense", "all_dense_windows"):
-        assert set(np.unique(nbin)) <= {0, 6}
+        assert set(np.unique(nbin)) <= {0, 6, 7}
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
@@ -163,6 +163,31 @@ def test_dense_windows_on_big_columns():
     st, _, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 2), 256,
                               tun=spg.tuning(dense_window=64, hash_max_nnz=128))
     assert (nbin == 6).sum() > 0
+
+
+@pytest.mark.parametrize("first", [1, 3000])
+def test_dense_first_bin_and_self_resetting_queues(first):
+    """Dense columns with at least dense_first_flop products go to numeric
+    bin 7 and are handed out before the others by the same work-queue
+    kernel; running symbolic and numeric twice on one plan checks that the
+    dense kernels' queues put themselves back to 0 after every launch."""
+    A = synth.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, seed=5)
+    ref = oracle.spgemm(A, A)
+    tun = spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0, dense_window=64,
+                     dense_first_flop=first)
+    st, _, nbin = check_local(A, A, synth.partition_offsets(A.ncols, 1), 256, tun=tun)
+    print("num bins", st["num_bins"], flush=True)
+    assert (nbin == 7).sum() > 0
+    if first > 1:
+        assert (nbin == 6).sum() > 0
+    Ad = _dev(A, torch.float64)
+    with spg.Plan(Ad, Ad, None, 256, tuning=tun) as p:
+        for _ in range(2):
+            c = p.symbolic().cpu().numpy()
+            r, v = p.numeric()
+            assert np.array_equal(c, ref.colptr)
+            assert np.array_equal(r.cpu().numpy(), ref.rowidx)
+            assert_values(v.cpu().numpy(), ref.vals, ref.absvals, True)
 
 
 def test_export_of_partial_group_before_empty_tail():
