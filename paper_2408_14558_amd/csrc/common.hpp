@@ -269,6 +269,44 @@ __device__ __forceinline__ void queue_leave(unsigned int *q) {
     }
 }
 
+// Copies n 32-bit words with all G threads of the workgroup (between LDS
+// and global memory): 16-byte accesses when both pointers allow them, with
+// up to two loads in flight per thread before their stores.
+template <int G>
+__device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, int n) {
+    int head = 0;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        const int n4 = n >> 2;
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+        for (int i0 = threadIdx.x; i0 < n4; i0 += 2 * G) {
+            uint4 t[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (i0 + u * G < n4) t[u] = s4[i0 + u * G];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (i0 + u * G < n4) d4[i0 + u * G] = t[u];
+        }
+        head = n4 << 2;
+    }
+    for (int i = head + threadIdx.x; i < n; i += G) dst[i] = src[i];
+}
+
+// Sets n 32-bit words of LDS to 0 with all G threads (16-byte stores when
+// aligned).
+template <int G>
+__device__ __forceinline__ void zero_words(uint32_t *dst, int n) {
+    int head = 0;
+    if ((((uintptr_t)dst) & 15) == 0) {
+        const int n4 = n >> 2;
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+        for (int i = threadIdx.x; i < n4; i += G) d4[i] = make_uint4(0u, 0u, 0u, 0u);
+        head = n4 << 2;
+    }
+    for (int i = head + threadIdx.x; i < n; i += G) dst[i] = 0u;
+}
+
 __device__ __forceinline__ int next_pow2(int x) {
     int p = 1;
     while (p < x) p <<= 1;

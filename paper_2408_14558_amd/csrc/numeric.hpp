@@ -349,7 +349,7 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    for (int i = gt; i < nw; i += G) bits[i] = 0u;
+    zero_words<G>(bits, nw);
     __syncthreads();
     for_each_term<G, V>(q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
                         [&](int64_t p) { return a.At_rowidx[p]; },
@@ -432,10 +432,10 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     const int slot = a.col_slot[j];
     if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
         const uint32_t *src = a.dense_bits + (size_t)slot * nw;
-        for (int i = gt; i < nw; i += G) bits[i] = src[i];
+        copy_words<G>(bits, src, nw);
         __syncthreads();
     } else {
-        for (int i = gt; i < nw; i += G) bits[i] = 0u;
+        zero_words<G>(bits, nw);
         __syncthreads();
         for_each_term<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
             q0, q1, a.tr, (const V *)nullptr, &S.st, gt,

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
     uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot,
     DevCounters *__restrict__ ctr) {
-    extern __shared__ uint32_t s_bits[];
+    extern __shared__ __align__(16) uint32_t s_bits[];
     __shared__ SymDenseLds L;
     __shared__ int s_item;
     unsigned int *queue = ctr->sym_dense_queue;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int gt = threadIdx.x;
     for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item)) {
         const int32_t j = list[w];
-        for (int i = gt; i < nw; i += kDenseThreads) s_bits[i] = 0u;
+        zero_words<kDenseThreads>(s_bits, nw);
         __syncthreads();
         // short entries stay with their thread: a flat walk would give a wave
         // consecutive rows of one column of A~, whose bits share words
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
         if (gt == 0) Ccount[j] = total;
         if (keep_bits) {  // the numeric phase reuses this bitmap
             uint32_t *dst = keep_bits + (size_t)w * nw;
-            for (int i = gt; i < nw; i += kDenseThreads) dst[i] = s_bits[i];
+            copy_words<kDenseThreads>(dst, s_bits, nw);
             if (gt == 0) col_slot[j] = w;
         }
     }
