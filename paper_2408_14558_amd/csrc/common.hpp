@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace spg {
@@ -36,9 +38,25 @@ __device__ __forceinline__ void group_sync() {
     }
 }
 
+// Inclusive scan of an int over all 64 lanes with DPP moves (no LDS round
+// trips): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then lane 15
+// of rows 0 and 2 added to rows 1 and 3, then lane 31 to rows 2 and 3.
+// Lanes whose source lies outside the row read 0.  Every lane must be
+// active.
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Inclusive scan over the lanes of a wave (width W, power of two <= 64).
 template <int W = kWave, typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
+    if constexpr (W == kWave && std::is_same<T, int>::value) return wave_incl_scan_dpp(v);
     const int l = lane_id() & (W - 1);
 #pragma unroll
     for (int d = 1; d < W; d <<= 1) {
