@@ -16,6 +16,7 @@ Prints ONE JSON line.  value = 2 * sparse flops / step time (GFLOP/s).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,34 @@ if ROOT not in sys.path:
 
 METRIC = "SpGEMM GFLOP/s + achieved HBM GB/s (% peak); batched/backward vs plain speedup"
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the numeric phase, from two rocprofv3 counter
+# passes (FETCH_SIZE, then WRITE_SIZE, summed over the phase's kernels and
+# divided by the launches), scaled by what the same counters read for a
+# plain 1 GiB device copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  A value only
+# holds for the kernel sources it was taken on; when their digest differs,
+# traffic is reported as null.
+TRAFFIC_SOURCES = ("numeric.hip", "numeric.hpp", "terms.hpp", "common.hpp", "internal.hpp")
+MEASURED_TRAFFIC = {
+    "er65536_d16_p16_block0_b256": {"bytes": 32017088, "sources": "1fe0397767ec946b"},
+    "rmat18_ef16_AxA_f64": {"bytes": 48924375759, "sources": "1fe0397767ec946b"},
+}
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2408_14558_amd", "csrc")
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_desc):
+    m = MEASURED_TRAFFIC.get(workload_desc)
+    if m is None or m["sources"] != kernel_sources_digest():
+        return None
+    return m["bytes"]
 
 
 def workload(name):
@@ -387,7 +416,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(w["desc"]),
             "algorithmic_bytes": int(num_bytes),
             "avg_ms": round(loop_ms, 5),
             "avg_ms_in_step": round(num_ms, 5),
