@@ -294,6 +294,57 @@ def study_gather_volume(spg, blocks=(1, 16, 64, 256, 1024, 4096), P=16, reps=3):
     return rows
 
 
+def study_bfs(spg, levels_max=32):
+    """Forward search of batched betweenness centrality: 4096 sources on an
+    unweighted R-MAT scale-16 graph; every level is one product N = A * F
+    (plan + symbolic + numeric, timed with events on the launch stream), the
+    next frontier keeps the vertices a source has not reached (a selection
+    done here with torch on the device; it is not part of the timed work)."""
+    import torch
+
+    import synth
+
+    w = synth.workload("bfs_rmat16_4096")
+    A, F = w["A"], w["B"]
+    n, ns = A.nrows, F.ncols
+    dev = "cuda"
+    Ad = spg.DeviceCsc.from_host(A, device=dev)
+    Fd = spg.DeviceCsc.from_host(F, device=dev)
+    visited = torch.zeros(n * ns, dtype=torch.bool, device=dev)
+    cols0 = torch.repeat_interleave(torch.arange(ns, device=dev), Fd.colptr.diff())
+    visited[cols0 * n + Fd.rowidx.long()] = True
+    stream = torch.cuda.current_stream()
+    rows_out, total_ms, total_flops = [], 0.0, 0
+    for level in range(levels_max):
+        if Fd.nnz == 0:
+            break
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        with spg.Plan(Ad, Fd, None, w["b"]) as p:
+            N = p.run()
+            st = p.stats()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        total_ms += ms
+        total_flops += st["flops"]
+        rows_out.append({"level": level, "nnz_F": Fd.nnz, "flops": st["flops"],
+                         "nnz_N": st["nnz_C"], "ms": round(ms, 4),
+                         "GFLOPs": round(2 * st["flops"] / (ms * 1e-3) / 1e9, 2),
+                         "num_bins": st["num_bins"]})
+        cols = torch.repeat_interleave(torch.arange(ns, device=dev), N.colptr.diff())
+        key = cols * n + N.rowidx.long()
+        keep = ~visited[key]
+        visited[key[keep]] = True
+        colptr = torch.zeros(ns + 1, dtype=torch.int64, device=dev)
+        colptr[1:] = torch.cumsum(torch.bincount(cols[keep], minlength=ns), 0)
+        Fd = spg.DeviceCsc(n, ns, colptr, N.rowidx[keep].contiguous(), N.vals[keep].contiguous())
+    return {"workload": "bfs_rmat16_4096 (R-MAT scale 16, ef 16, unit values, seed 3; "
+                        "4096 sources, seed 7)",
+            "levels": rows_out, "total_ms": round(total_ms, 3),
+            "total_GFLOPs": round(2 * total_flops / (total_ms * 1e-3) / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,7 +354,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and backward measurements")
-    ap.add_argument("--study", choices=["gather-volume"],
+    ap.add_argument("--study", choices=["gather-volume", "bfs"],
                     help="instead of the benchmark, run a study and print its table as JSON")
     ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
                     help="override a spgemm_tuning field for the main workload (repeatable)")
@@ -338,6 +389,10 @@ def main():
     if args.study == "gather-volume":
         print(json.dumps({"study": "gather_volume_vs_block_size_and_order",
                           "rows": study_gather_volume(spg)}), flush=True)
+        return
+    if args.study == "bfs":
+        print(json.dumps({"study": "multi_source_bfs_forward_search", **study_bfs(spg)}),
+              flush=True)
         return
 
     w = workload(args.workload)

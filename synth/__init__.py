@@ -279,6 +279,33 @@ def er_batch(count: int, seed: int):
 # named workloads
 # --------------------------------------------------------------------------
 
+def unit_values(M: CSC) -> CSC:
+    """The pattern of M with every stored value 1 (an unweighted graph)."""
+    return CSC(M.nrows, M.ncols, M.colptr, M.rowidx, np.ones(M.nnz))
+
+
+def bfs_sources(n: int, count: int, seed: int) -> CSC:
+    """Frontier of a multi-source search at its start: column s holds a 1 at
+    the s-th of `count` distinct vertices drawn uniformly from [0, n)."""
+    rng = np.random.default_rng(seed)
+    src = np.sort(rng.choice(n, size=count, replace=False)) if count else np.zeros(0, np.int64)
+    return from_triplets(n, count, src, np.arange(count), np.ones(count))
+
+
+def next_frontier(N: CSC, visited: np.ndarray):
+    """One level of a multi-source breadth-first search: N = A * F holds, in
+    column s, the vertices one hop from source s's frontier with their
+    shortest-path counts; the next frontier keeps the entries of vertices
+    that search s has not reached yet.  visited (n x count, bool) is updated
+    in place.  Pure selection, no arithmetic."""
+    cols = np.repeat(np.arange(N.ncols), np.diff(N.colptr))
+    keep = ~visited[N.rowidx, cols]
+    visited[N.rowidx[keep], cols[keep]] = True
+    colptr = np.zeros(N.ncols + 1, dtype=np.int64)
+    np.cumsum(np.bincount(cols[keep], minlength=N.ncols), out=colptr[1:])
+    return CSC(N.nrows, N.ncols, colptr, N.rowidx[keep].copy(), np.asarray(N.vals)[keep].copy())
+
+
 def workload(name: str):
     """Named inputs used by tests and the benchmark.
 
@@ -298,6 +325,12 @@ def workload(name: str):
         A = erdos_renyi(131072, 131072, 8, seed=5)
         B = sign_sketch(131072, 4096, 4, seed=6)
         return {"A": A, "B": B, "P": 1, "offsets": partition_offsets(A.ncols, 1), "b": 256}
+    if name == "bfs_rmat16_4096":
+        # multi-source search of a batched betweenness-centrality forward
+        # pass: 4096 sources on an unweighted R-MAT graph
+        A = unit_values(rmat(16, 16, 0.57, 0.19, 0.19, 0.05, seed=3))
+        F = bfs_sources(A.ncols, 4096, seed=7)
+        return {"A": A, "B": F, "P": 1, "offsets": partition_offsets(A.ncols, 1), "b": 256}
     if name == "sketch_er512":
         A = erdos_renyi(512, 512, 8, seed=5)
         B = sign_sketch(512, 16, 4, seed=6)

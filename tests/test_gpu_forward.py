@@ -190,6 +190,25 @@ def test_dense_first_bin_and_self_resetting_queues(first):
             assert_values(v.cpu().numpy(), ref.vals, ref.absvals, True)
 
 
+def test_medium_bitmap_queue_over_two_bins_and_reruns():
+    """Both medium bins on the bitmap kernel: two launches share one work
+    queue, which each launch puts back to 0; numeric twice on one plan."""
+    A = synth.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, seed=6)
+    ref = oracle.spgemm(A, A)
+    tun = spg.tuning(medium_kernel=2, hash_max_nnz=2048)
+    Ad = _dev(A, torch.float64)
+    with spg.Plan(Ad, Ad, None, 256, tuning=tun) as p:
+        c = p.symbolic().cpu().numpy()
+        st = p.stats()
+        print("num bins", st["num_bins"], flush=True)
+        assert sum(1 for b in (2, 3, 4, 5) if st["num_bins"][b] > 0) >= 2
+        for _ in range(2):
+            r, v = p.numeric()
+            assert np.array_equal(c, ref.colptr)
+            assert np.array_equal(r.cpu().numpy(), ref.rowidx)
+            assert_values(v.cpu().numpy(), ref.vals, ref.absvals, True)
+
+
 def test_export_of_partial_group_before_empty_tail():
     """A partition whose last tile holds no nonzero column: its final, short
     group must still report its last column."""
