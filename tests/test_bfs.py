@@ -1,9 +1,9 @@
 """Multi-source breadth-first search (the forward search of batched
-betweenness centrality, Sec. II-C and Sec. IV-C): every level is one product N = A * F of
-the graph with the frontier, and the next frontier keeps the vertices a
-source has not reached.  On the CPU the levels from the oracle's product are
-pinned against shortest-path distances and a brute-force count of shortest
-paths."""
+betweenness centrality, Sec. II-C and Sec. IV-C): every level is one product
+N = A * F of the graph with the frontier, and the next frontier keeps the
+vertices a source has not reached.  On the CPU the levels from the oracle's
+product are pinned against shortest-path distances and a brute-force count
+of shortest paths."""
 
 import numpy as np
 from scipy.sparse import csc_matrix
