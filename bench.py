@@ -345,6 +345,63 @@ def study_bfs(spg, levels_max=32):
             "total_GFLOPs": round(2 * total_flops / (total_ms * 1e-3) / 1e9, 2)}
 
 
+def study_outer(spg, parts=(4, 8, 16), reps=3):
+    """The right product of a Galerkin step, X * P (P the 2x2x2 aggregation
+    prolongator of the 64^3 7-point Laplacian A), by the two 1D forms on one
+    GPU, over the same number of blocks p: column-wise (Alg. 1: C_i = X * P_i
+    for P's column blocks, uploaded beforehand) and outer-product (Alg. 3:
+    row blocks P(K_r, :), partial products X(:, K_r) * P(K_r, :), their sum).
+    X = A is this project's order, X = P^T A the paper's.  Times are the
+    whole local work of each form (plans included), averaged over reps."""
+    import torch
+    import synth
+
+    A = spg.DeviceCsc.from_host(synth.laplacian3d(64))
+    Ph = synth.aggregation3d(64)
+    P = spg.DeviceCsc.from_host(Ph)
+    Pt = spg.DeviceCsc.from_host(synth.aggregation3d_t(64))
+    X_paper = spg.spgemm(Pt, A, None, 64)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    rows = []
+    for name, X in (("A*P", A), ("(P^T A)*P", X_paper)):
+        for p in parts:
+            offs = synth.partition_offsets(X.ncols, p)
+            coffs = synth.partition_offsets(Ph.ncols, p)
+            blocks = [spg.DeviceCsc.from_host(synth.column_slice(Ph, int(coffs[i]), int(coffs[i + 1])))
+                      for i in range(p)]
+            cw_ms, cw = timed(lambda: [spg.spgemm(X, Bi, offs, 64) for Bi in blocks])
+            op_ms, C = timed(lambda: spg.outer_product(X, P, offs, 64))
+            # volumes (untimed): entries of X each form's products take into
+            # A~, and the partial results the outer-product form's merge moves
+            cw_At = 0
+            for Bi in blocks:
+                with spg.Plan(X, Bi, offs, 64) as q:
+                    cw_At += q.stats()["nnz_At"]
+            op_At, partial = 0, 0
+            for r in range(p):
+                with spg.Plan(X, spg.row_block(P, int(offs[r]), int(offs[r + 1])), offs, 64) as q:
+                    op_At += q.stats()["nnz_At"]
+                    partial += q.run().nnz
+            rows.append({"product": name, "p": p, "nnz_X": X.nnz, "nnz_C": C.nnz,
+                         "column_wise_At_entries": cw_At, "outer_At_entries": op_At,
+                         "partial_nnz": partial,
+                         "column_wise_ms": round(cw_ms, 4), "outer_product_ms": round(op_ms, 4),
+                         "outer_over_column_wise": round(op_ms / cw_ms, 3)})
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +411,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and backward measurements")
-    ap.add_argument("--study", choices=["gather-volume", "bfs"],
+    ap.add_argument("--study", choices=["gather-volume", "bfs", "outer"],
                     help="instead of the benchmark, run a study and print its table as JSON")
     ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
                     help="override a spgemm_tuning field for the main workload (repeatable)")
@@ -389,6 +446,10 @@ def main():
     if args.study == "gather-volume":
         print(json.dumps({"study": "gather_volume_vs_block_size_and_order",
                           "rows": study_gather_volume(spg)}), flush=True)
+        return
+    if args.study == "outer":
+        print(json.dumps({"study": "galerkin_right_product_column_wise_vs_outer_product",
+                          "rows": study_outer(spg)}), flush=True)
         return
     if args.study == "bfs":
         print(json.dumps({"study": "multi_source_bfs_forward_search", **study_bfs(spg)}),

@@ -291,6 +291,38 @@ int spgemm_batch_check(spgemm_batch_t batch);
 
 int spgemm_batch_destroy(spgemm_batch_t batch);
 
+/* ---------------------------------------------------------------------------
+ * Outer-product form (Alg. 3): with the inner dimension split into row
+ * blocks K_r of B, C = sum_r A(:, K_r) * B(K_r, :).  The two steps that move
+ * data in Alg. 3 (row blocks of B to their owners; the partial results to
+ * the owners of C for merging) are the two calls below; the partial
+ * products and their sum run through spgemm_plan/symbolic/numeric.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Row block B(r0:r1, :) of B (device CSC) with its global row ids, so that a
+ * plan of A times it selects only columns r0..r1-1 of A.  Outputs (device,
+ * caller-allocated): colptr_out int64[ncols+1]; rowidx_out int32 and vals_out
+ * dtype with room for nnz(B) entries (the block's count ends up in
+ * colptr_out[ncols]).  Asynchronous on `stream`.  Errors: EINVAL (NULL
+ * arrays, 0 <= r0 <= r1 <= nrows violated), EHIP.
+ */
+int spgemm_row_block(const spgemm_csc *B, spgemm_dtype dtype, int64_t r0, int64_t r1,
+                     int64_t *colptr_out, int32_t *rowidx_out, void *vals_out, void *stream);
+
+/*
+ * Stacks P partial results of one shape (m x n, host array of device CSCs)
+ * side by side, stack = [C_0 ... C_{P-1}] (m x P*n: colptr int64[P*n+1],
+ * row ids int32 and values dtype[sum of nnz]), and writes the selector
+ * S = [I_n; ...; I_n] (P*n x n: colptr int64[n+1], row ids int32[P*n],
+ * values dtype[P*n], all 1), so that stack * S = sum_r C_r.  All outputs are
+ * device arrays the caller allocates.  Asynchronous on `stream`.  Errors:
+ * EINVAL (P < 1, parts of different shapes, P*n >= 2^31, NULL arrays), EHIP.
+ */
+int spgemm_stack_parts(int32_t P, const spgemm_csc *parts, spgemm_dtype dtype,
+                       int64_t *stack_colptr, int32_t *stack_rowidx, void *stack_vals,
+                       int64_t *sel_colptr, int32_t *sel_rowidx, void *sel_vals, void *stream);
+
 /* Releases every pooled device/host buffer not held by a live plan. */
 int spgemm_pool_trim(void);
 

@@ -90,6 +90,10 @@ SIGNATURES = {
     "spgemm_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "spgemm_batch_check": (ctypes.c_int, [_vp]),
     "spgemm_batch_destroy": (ctypes.c_int, [_vp]),
+    "spgemm_row_block": (ctypes.c_int, [ctypes.POINTER(Csc), ctypes.c_int, _i64, _i64, _vp, _vp,
+                                        _vp, _vp]),
+    "spgemm_stack_parts": (ctypes.c_int, [_i32, ctypes.POINTER(Csc), ctypes.c_int, _vp, _vp, _vp,
+                                          _vp, _vp, _vp, _vp]),
     "spgemm_pool_trim": (ctypes.c_int, []),
 }
 

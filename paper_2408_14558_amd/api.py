@@ -342,3 +342,64 @@ def galerkin_chain(A0: DeviceCsc, levels, block_size: int = 64,
         outs.append(Ac)
         A = Ac
     return plans, io, outs
+
+
+def _dtype_of(t: torch.Tensor) -> int:
+    return _lib.F64 if t.dtype == torch.float64 else _lib.F32
+
+
+def row_block(B: DeviceCsc, r0: int, r1: int, stream=None) -> DeviceCsc:
+    """B(r0:r1, :) with B's global row ids (spgemm_row_block); reads the
+    block's entry count back (one synchronisation)."""
+    lib = _lib.load()
+    dev = B.colptr.device
+    cap = max(B.nnz, 1)
+    colptr = torch.empty(B.ncols + 1, dtype=torch.int64, device=dev)
+    rows = torch.empty(cap, dtype=torch.int32, device=dev)
+    vals = torch.empty(cap, dtype=B.vals.dtype, device=dev)
+    c = B.c_struct()
+    check(lib.spgemm_row_block(ctypes.byref(c), _dtype_of(B.vals), int(r0), int(r1),
+                               _ptr(colptr), _ptr(rows), _ptr(vals), _stream(stream)),
+          "spgemm_row_block")
+    nnz = int(colptr[-1])
+    return DeviceCsc(B.nrows, B.ncols, colptr, rows[:nnz], vals[:nnz])
+
+
+def sum_parts(parts, block_size: int = 256, tuning: Optional[_lib.Tuning] = None,
+              stream=None) -> DeviceCsc:
+    """Sum of partial results of one shape: the stack [C_0 ... C_{P-1}] times
+    the selector [I; ...; I] (spgemm_stack_parts), through the plain path."""
+    lib = _lib.load()
+    P = len(parts)
+    m, n = parts[0].nrows, parts[0].ncols
+    dev = parts[0].colptr.device
+    vdt = parts[0].vals.dtype
+    total = sum(p.nnz for p in parts)
+    st_colptr = torch.empty(P * n + 1, dtype=torch.int64, device=dev)
+    st_rows = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+    st_vals = torch.empty(max(total, 1), dtype=vdt, device=dev)
+    se_colptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    se_rows = torch.empty(max(P * n, 1), dtype=torch.int32, device=dev)
+    se_vals = torch.empty(max(P * n, 1), dtype=vdt, device=dev)
+    arr = (_lib.Csc * P)(*[p.c_struct() for p in parts])
+    check(lib.spgemm_stack_parts(P, arr, _dtype_of(parts[0].vals), _ptr(st_colptr), _ptr(st_rows),
+                                 _ptr(st_vals), _ptr(se_colptr), _ptr(se_rows), _ptr(se_vals),
+                                 _stream(stream)), "spgemm_stack_parts")
+    stack = DeviceCsc(m, P * n, st_colptr, st_rows[:total], st_vals[:total])
+    sel = DeviceCsc(P * n, n, se_colptr, se_rows[:P * n], se_vals[:P * n])
+    return spgemm(stack, sel, None, block_size, tuning)
+
+
+def outer_product(A: DeviceCsc, B: DeviceCsc, offsets, block_size: int = 256,
+                  tuning: Optional[_lib.Tuning] = None) -> DeviceCsc:
+    """C = A * B by the outer-product 1D algorithm (Alg. 3) on one GPU: the
+    inner dimension split at `offsets` (A's column partitions = B's row
+    blocks), one partial product A * B(K_r, :) per block (its plan selects
+    A's columns K_r by Alg. 1 and 2), then the partial results summed."""
+    offs = np.asarray(offsets, dtype=np.int64)
+    parts = []
+    for r in range(len(offs) - 1):
+        Br = row_block(B, int(offs[r]), int(offs[r + 1]))
+        parts.append(spgemm(A, Br, offs, block_size, tuning))
+    return sum_parts(parts, block_size, tuning)
+
