@@ -193,10 +193,15 @@ int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
  *   C_colptr  int64[n_i+1], caller-allocated; receives C_i's column pointers.
  *   nnzC      HOST int64*; receives nnz(C_i).
  *
- * Computes the sparse flops of every column (Sec. III-B), bins columns by
- * them, counts the distinct rows of every output column (a row is stored
- * whenever a product reaches it, even if values later cancel) and scans the
- * counts.  Synchronises the plan's stream twice (bin sizes, then nnzC).
+ * Uses the sparse flops and bins of every column (Sec. III-B) that the
+ * plan computed, counts the distinct rows of every output column (a row is
+ * stored whenever a product reaches it, even if values later cancel) and
+ * scans the counts.  Waits on the host twice: for the bin sizes (first call
+ * on a plan only) and for nnzC.  Both are written to pinned host memory by
+ * the last workgroup of the kernel that computes them, followed by a flag
+ * the host polls for a short while before it falls back to a blocking
+ * synchronisation of the plan's stream; C_colptr is complete when the call
+ * returns, and later work on the plan's stream is ordered after it.
  */
 int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
 

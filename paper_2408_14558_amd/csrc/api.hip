@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <climits>
 #include <cstring>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -145,6 +146,25 @@ static int pool_trim() {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// Waits until a publishing kernel has set pinned flag f (its counters are in
+// hctr by then): spins on the flag for up to kSpinMicros, because a blocking
+// wait adds the host's wake-up latency to every small product, then falls
+// back to block(), which also reports launch errors.
+constexpr int kSpinMicros = 500;
+
+template <typename F>
+static hipError_t wait_flag(Plan &p, int f, F &&block) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned i = 0;; ++i) {
+        if (__atomic_load_n(p.hflags + f, __ATOMIC_ACQUIRE)) return hipSuccess;
+        if ((i & 255u) == 255u &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros))
+            break;
+        __builtin_ia32_pause();
+    }
+    return block();
+}
+
 // Compute units of a device (queried once); 0 if the query fails.
 int device_cu_count(int device) {
     static std::mutex mtx;
@@ -472,6 +492,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     }
     Carver ch;
     const size_t h_ctr = ch.take<DevCounters>(1);
+    const size_t h_flags = ch.take<uint32_t>(32);
     const size_t h_gbase = ch.take<int64_t>(P + 1);
     const size_t h_tiles = h_gbase + up_gap;
     const size_t pinned_bytes = h_tiles + sizeof(RankTile) * (size_t)pl.n_rank_tiles;
@@ -524,6 +545,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
             return fail(SPGEMM_EHIP, "hipHostGetDevicePointer failed");
         }
         pl.hctr_dev = (DevCounters *)((char *)dev + h_ctr);
+        pl.hflags = (uint32_t *)(h + h_flags);
+        pl.hflags_dev = (uint32_t *)((char *)dev + h_flags);
     }
     std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
     if (!tiles.empty()) std::memcpy(h + h_tiles, tiles.data(), sizeof(RankTile) * tiles.size());
@@ -556,6 +579,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
         // sparse flops, term ranges and symbolic bins depend on the patterns
         // only: computed here, right after the gather, with their counts on
         // their way to the host by the time spgemm_symbolic needs them
+        __atomic_store_n(pl.hflags + kFlagCounts, 0u, __ATOMIC_RELEASE);
         if ((rc = launch_flop_bin(pl))) return cleanup(rc);
         e = take_event(&pl.counts_ready);
         if (e == hipSuccess) e = hipEventRecord(pl.counts_ready, pl.stream);
@@ -658,15 +682,16 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     // flops and symbolic bins came with the plan; a later run clears what the
     // previous symbolic run accumulated
     if (p.symbolic_runs++ == 0) {
-        SPG_HIP(hipEventSynchronize(p.counts_ready));
+        SPG_HIP(wait_flag(p, kFlagCounts, [&] { return hipEventSynchronize(p.counts_ready); }));
         for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;
     }
     reserve_kept(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
+    __atomic_store_n(p.hflags + kFlagColptr, 0u, __ATOMIC_RELEASE);
     if ((rc = launch_colptr_scan(p))) return rc;  // publishes the counters to hctr
-    SPG_HIP(hipStreamSynchronize(p.stream));
+    SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
     p.nnzC = p.hctr->nnzC;
     p.flops = p.hctr->flops.v;
     for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hctr->num_count[b].v;

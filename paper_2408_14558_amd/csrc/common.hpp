@@ -211,12 +211,13 @@ __device__ __forceinline__ long long chained_prefix(uint64_t *status, long long 
 
 // Called by every thread of every workgroup of a kernel, once, after the
 // workgroup's last update of the counters: the workgroup that finishes last
-// copies the counters to `out` (host memory the host reads once the kernel is
-// done), so no separate device-to-host copy is needed.  `done` counts the
+// copies the counters to `out` (host memory), so no separate device-to-host
+// copy is needed, then sets *ready to 1 with a system-scope release store:
+// the host may read `out` as soon as it sees the flag.  `done` counts the
 // finished workgroups.
 __device__ __forceinline__ void publish_when_last(unsigned long long *done,
                                                   const DevCounters *ctr, DevCounters *out,
-                                                  int *lds_flag) {
+                                                  unsigned int *ready, int *lds_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();  // this workgroup's counter updates before its ticket
@@ -229,6 +230,11 @@ __device__ __forceinline__ void publish_when_last(unsigned long long *done,
         int *dst = reinterpret_cast<int *>(out);
         for (int i = threadIdx.x; i < (int)(sizeof(DevCounters) / sizeof(int)); i += blockDim.x)
             dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence_system();
+            __hip_atomic_store(ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 

@@ -82,6 +82,8 @@ struct DevCounters {
     unsigned int num_bitmap_queue[2];  // both medium bins: their launches follow each other
 };
 
+enum PinnedFlag { kFlagCounts = 0, kFlagColptr = 1 };
+
 enum Ticket {
     kTkRank = 0,
     kTkSelect = 1,
@@ -186,6 +188,10 @@ struct Plan {
     // address, where the flops kernel and the colptr scan publish them
     DevCounters *hctr = nullptr;
     DevCounters *hctr_dev = nullptr;
+    // pinned flags the publishing kernels set once hctr holds their counters
+    // (host and device addresses): kFlagCounts (flops pass), kFlagColptr (scan)
+    uint32_t *hflags = nullptr;
+    uint32_t *hflags_dev = nullptr;
 
     // symbolic results
     bool symbolic_done = false;

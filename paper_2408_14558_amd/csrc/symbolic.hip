@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     uint64_t *__restrict__ status, int64_t nstatus, DevCounters *__restrict__ ctr,
-    DevCounters *__restrict__ hout) {
+    DevCounters *__restrict__ hout, unsigned int *__restrict__ hready) {
     constexpr int COLS = kFlopThreads / S;
     __shared__ int s_bin[COLS];
     __shared__ int s_lpos[COLS];
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops.v, s_flops);
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
     __shared__ int s_last;
-    publish_when_last(&ctr->tickets[kTkFlopDone], ctr, hout, &s_last);
+    publish_when_last(&ctr->tickets[kTkFlopDone], ctr, hout, hready, &s_last);
 }
 
 // --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
     int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
     uint64_t *__restrict__ status, int64_t ntiles, DevCounters *__restrict__ ctr,
-    DevCounters *__restrict__ hout) {
+    DevCounters *__restrict__ hout, unsigned int *__restrict__ hready) {
     __shared__ long long s_ticket;
     __shared__ long long s_tmp64[kScanThreads / kWave + 1];
     __shared__ long long s_prefix;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     }
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->num_count, num_list, n);
     __shared__ int s_last;
-    publish_when_last(&ctr->tickets[kTkColptrDone], ctr, hout, &s_last);
+    publish_when_last(&ctr->tickets[kTkColptrDone], ctr, hout, hready, &s_last);
 }
 
 // Clears what one symbolic phase accumulates (the colptr scan's ticket and
@@ -391,7 +391,7 @@ static int flop_bin_launch(Plan &p) {
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
                        p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot,
                        p.flop, p.sym_bin, p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr,
-                       p.hctr_dev);
+                       p.hctr_dev, p.hflags_dev + kFlagCounts);
     SPG_LAUNCHED("k_flop_bin");
     return SPGEMM_OK;
 }
@@ -461,7 +461,8 @@ int launch_colptr_scan(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     hipLaunchKernelGGL(k_colptr_scan, dim3((unsigned)p.n_col_tiles), dim3(kScanThreads), 0,
                        p.stream, p.n, p.C_colptr, p.flop, p.th, p.num_bin, p.num_list,
-                       p.st_colptr, p.n_col_tiles, p.ctr, p.hctr_dev);
+                       p.st_colptr, p.n_col_tiles, p.ctr, p.hctr_dev,
+                       p.hflags_dev + kFlagColptr);
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
 }
