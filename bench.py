@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # traffic is reported as null.
 TRAFFIC_SOURCES = ("numeric.hip", "numeric.hpp", "terms.hpp", "common.hpp", "internal.hpp")
 MEASURED_TRAFFIC = {
-    "er65536_d16_p16_block0_b256": {"bytes": 32017088, "sources": "1fe0397767ec946b"},
-    "rmat18_ef16_AxA_f64": {"bytes": 48924375759, "sources": "1fe0397767ec946b"},
+    "er65536_d16_p16_block0_b256": {"bytes": 32011965, "sources": "fbee52b2acd31c7c"},
+    "rmat18_ef16_AxA_f64": {"bytes": 48911855910, "sources": "fbee52b2acd31c7c"},
 }
 
 
