@@ -420,8 +420,8 @@ def main():
                          "(reference for HBM byte counters), and print its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ extern "C" {
 #define SPGEMM_EINVAL (-1)       /* bad argument or malformed matrix */
 #define SPGEMM_ENOMEM (-2)       /* device or host allocation failed / over limit */
 #define SPGEMM_EHIP (-3)         /* a HIP runtime call failed (message has text) */
-#define SPGEMM_EUNSUPPORTED (-4) /* valid request this build cannot serve */
+#define SPGEMM_EUNSUPPORTED (-4) /* valid request the library does not serve */
 #define SPGEMM_ESTATE (-5)       /* call out of order (e.g. numeric before symbolic) */
 
 typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
