@@ -6,8 +6,10 @@
 #include <climits>
 #include <cstring>
 #include <chrono>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -181,9 +183,26 @@ int device_cu_count(int device) {
 
 unsigned resident_groups(const void *kernel, int threads, size_t lds, int device,
                          long long work) {
+    // the occupancy query costs tens of microseconds of host time: asked once
+    // per kernel, block size, LDS size and device
+    static std::mutex mtx;
+    static std::map<std::tuple<const void *, int, size_t, int>, int> cache;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
-        (void)hipGetLastError();
+    {
+        std::lock_guard<std::mutex> lk(mtx);
+        const auto key = std::make_tuple(kernel, threads, lds, device);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            per_cu = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                per_cu = 0;
+            }
+            cache[key] = per_cu;
+        }
+    }
     const long long cus = device_cu_count(device);
     long long g = (long long)std::max(per_cu, 1) * (cus > 0 ? cus : 256);
     g = std::min(g, work);

@@ -79,7 +79,6 @@ struct DevCounters {
     // (the last workgroup of a launch puts both back to 0)
     unsigned int num_dense_queue[2];
     unsigned int sym_dense_queue[2];
-    unsigned int num_bitmap_queue[2];  // both medium bins: their launches follow each other
 };
 
 enum PinnedFlag { kFlagCounts = 0, kFlagColptr = 1 };

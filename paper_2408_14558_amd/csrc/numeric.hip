@@ -64,19 +64,15 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
 
 template <int G, typename V>
 __global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ list, int count,
-                                                  NumArgs<V> a, int vcap,
-                                                  DevCounters *__restrict__ ctr) {
+                                                  NumArgs<V> a, int vcap) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ NumBitmapStatic<G, V> S;
-    __shared__ int s_item;
-    unsigned int *queue = ctr->num_bitmap_queue;
+    if ((int)blockIdx.x >= count) return;
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
     V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
-    for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item))
-        num_bitmap_column<G, V>(a, list[w], bits, wpre, vals, vcap, S);
-    queue_leave(queue);
+    num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, vcap, S);
 }
 
 // Bitmap instead of hash for a medium bin when the bitmap is not much
@@ -111,10 +107,8 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     const int mk = p.tun.medium_kernel;
     if ((mk == 0 && fits) || (mk == 2 && lds <= 96 * 1024)) {
         constexpr int GB = T <= 512 ? 128 : 256;
-        const unsigned grid =
-            resident_groups((const void *)k_num_bitmap<GB, V>, GB, lds, p.device, cnt);
-        hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(grid), dim3(GB), lds, p.stream,
-                           p.num_list + (int64_t)bin * p.n, cnt, a, T / 2, p.ctr);
+        hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(cnt), dim3(GB), lds, p.stream,
+                           p.num_list + (int64_t)bin * p.n, cnt, a, T / 2);
         SPG_LAUNCHED("k_num_bitmap<" + std::to_string(GB) + ">");
         return SPGEMM_OK;
     }
