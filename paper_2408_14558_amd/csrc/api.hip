@@ -512,6 +512,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     Carver ch;
     const size_t h_ctr = ch.take<DevCounters>(1);
     const size_t h_flags = ch.take<uint32_t>(32);
+    const size_t h_pub = ch.take<PublishedCounts>(1);
     const size_t h_gbase = ch.take<int64_t>(P + 1);
     const size_t h_tiles = h_gbase + up_gap;
     const size_t pinned_bytes = h_tiles + sizeof(RankTile) * (size_t)pl.n_rank_tiles;
@@ -563,7 +564,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
             delete p;
             return fail(SPGEMM_EHIP, "hipHostGetDevicePointer failed");
         }
-        pl.hctr_dev = (DevCounters *)((char *)dev + h_ctr);
+        pl.hpub = (PublishedCounts *)(h + h_pub);
+        pl.hpub_dev = (PublishedCounts *)((char *)dev + h_pub);
         pl.hflags = (uint32_t *)(h + h_flags);
         pl.hflags_dev = (uint32_t *)((char *)dev + h_flags);
     }
@@ -702,18 +704,18 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     // previous symbolic run accumulated
     if (p.symbolic_runs++ == 0) {
         SPG_HIP(wait_flag(p, kFlagCounts, [&] { return hipEventSynchronize(p.counts_ready); }));
-        for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hctr->sym_count[b].v;
+        for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hpub->sym_count[b];
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;
     }
     reserve_kept(p);
     if ((rc = launch_symbolic_bins(p))) return rc;
     __atomic_store_n(p.hflags + kFlagColptr, 0u, __ATOMIC_RELEASE);
-    if ((rc = launch_colptr_scan(p))) return rc;  // publishes the counters to hctr
+    if ((rc = launch_colptr_scan(p))) return rc;  // publishes its counters to hpub
     SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
-    p.nnzC = p.hctr->nnzC;
-    p.flops = p.hctr->flops.v;
-    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hctr->num_count[b].v;
+    p.nnzC = p.hpub->nnzC;
+    p.flops = p.hpub->flops;
+    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
     p.symbolic_done = true;
     *nnzC = p.nnzC;
     return SPGEMM_OK;

@@ -83,6 +83,15 @@ struct DevCounters {
 
 enum PinnedFlag { kFlagCounts = 0, kFlagColptr = 1 };
 
+// What the symbolic phase needs from the device counters, copied by the
+// kernel that completes them to pinned host memory (one wave's writes).
+struct PublishedCounts {
+    long long flops;
+    long long nnzC;
+    int sym_count[kNumBins];
+    int num_count[kNumBins];
+};
+
 enum Ticket {
     kTkRank = 0,
     kTkSelect = 1,
@@ -186,7 +195,8 @@ struct Plan {
     // host view of the counters (inside the pinned block) and its device
     // address, where the flops kernel and the colptr scan publish them
     DevCounters *hctr = nullptr;
-    DevCounters *hctr_dev = nullptr;
+    PublishedCounts *hpub = nullptr;      // pinned; written by the publishing kernels
+    PublishedCounts *hpub_dev = nullptr;  // its device address
     // pinned flags the publishing kernels set once hctr holds their counters
     // (host and device addresses): kFlagCounts (flops pass), kFlagColptr (scan)
     uint32_t *hflags = nullptr;

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
     int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
     uint64_t *__restrict__ status, int64_t nstatus, DevCounters *__restrict__ ctr,
-    DevCounters *__restrict__ hout, unsigned int *__restrict__ hready) {
+    PublishedCounts *__restrict__ hout, unsigned int *__restrict__ hready) {
     constexpr int COLS = kFlopThreads / S;
     __shared__ int s_bin[COLS];
     __shared__ int s_lpos[COLS];
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
     int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
     uint64_t *__restrict__ status, int64_t ntiles, DevCounters *__restrict__ ctr,
-    DevCounters *__restrict__ hout, unsigned int *__restrict__ hready) {
+    PublishedCounts *__restrict__ hout, unsigned int *__restrict__ hready) {
     __shared__ long long s_ticket;
     __shared__ long long s_tmp64[kScanThreads / kWave + 1];
     __shared__ long long s_prefix;
@@ -391,7 +391,7 @@ static int flop_bin_launch(Plan &p) {
     hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
                        p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot,
                        p.flop, p.sym_bin, p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr,
-                       p.hctr_dev, p.hflags_dev + kFlagCounts);
+                       p.hpub_dev, p.hflags_dev + kFlagCounts);
     SPG_LAUNCHED("k_flop_bin");
     return SPGEMM_OK;
 }
@@ -461,7 +461,7 @@ int launch_colptr_scan(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
     hipLaunchKernelGGL(k_colptr_scan, dim3((unsigned)p.n_col_tiles), dim3(kScanThreads), 0,
                        p.stream, p.n, p.C_colptr, p.flop, p.th, p.num_bin, p.num_list,
-                       p.st_colptr, p.n_col_tiles, p.ctr, p.hctr_dev,
+                       p.st_colptr, p.n_col_tiles, p.ctr, p.hpub_dev,
                        p.hflags_dev + kFlagColptr);
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
