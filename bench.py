@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # traffic is reported as null.
 TRAFFIC_SOURCES = ("numeric.hip", "numeric.hpp", "terms.hpp", "common.hpp", "internal.hpp")
 MEASURED_TRAFFIC = {
-    "er65536_d16_p16_block0_b256": {"bytes": 32017089, "sources": "9d01beedd4b8e8e5"},
-    "rmat18_ef16_AxA_f64": {"bytes": 48960169865, "sources": "9d01beedd4b8e8e5"},
+    "er65536_d16_p16_block0_b256": {"bytes": 32017088, "sources": "495728eb2d80d279"},
+    "rmat18_ef16_AxA_f64": {"bytes": 49101198529, "sources": "495728eb2d80d279"},
 }
 
 
