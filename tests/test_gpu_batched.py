@@ -148,3 +148,44 @@ def test_batched_errors(workload):
     with pytest.raises(spg.SpgemmError) as e:
         spg.Batch([p], [{"C_rowidx": A.rowidx, "C_vals": A.vals}])
     assert e.value.code == -5  # symbolic has not run
+
+
+def test_graph_replays_of_dense_queue_kernels():
+    """A batch whose products run the dense kernels (all dense bins, small
+    windows; one product with dense-first columns): the work-queue counters
+    live in each plan's device counters and put themselves back to 0 at the
+    end of every launch, so every replay of the captured graph computes the
+    same product."""
+    tun_all = spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0, dense_window=64,
+                         dense_first_flop=2000)
+    mats = [synth.rmat(11, 16, 0.57, 0.19, 0.19, 0.05, seed=s) for s in (31, 32)]
+    plans, io, refs = [], [], []
+    for M in mats:
+        Md = spg.DeviceCsc.from_host(M)
+        p = spg.Plan(Md, Md, None, 64, tuning=tun_all)
+        C = p.run()
+        st = p.stats()
+        assert st["num_bins"][6] + st["num_bins"][7] > 0
+        plans.append(p)
+        io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+        refs.append(oracle.spgemm(M, M))
+    s = torch.cuda.Stream()
+    for p in plans:
+        p.set_stream(s)
+    b = spg.Batch(plans, io)
+    try:
+        b.run(1, stream=s)
+        for rep in range(3):
+            with torch.cuda.stream(s):  # cleared in stream order before the replay
+                for d in io:
+                    d["C_vals"].zero_()
+            b.run(2, stream=s)
+            s.synchronize()
+            for d, ref in zip(io, refs):
+                assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
+                assert_values(d["C_vals"].cpu().numpy(), ref.vals, ref.absvals, True)
+        b.check()
+    finally:
+        b.close()
+        for p in plans:
+            p.close()

@@ -93,3 +93,18 @@ def test_galerkin_right_product_both_forms(left):
         cols.append(spg.spgemm(Xd, spg.DeviceCsc.from_host(Bi), offs, 64).to_host())
     rows = np.concatenate([c.rowidx for c in cols])
     assert np.array_equal(rows, ref.rowidx)
+
+
+def test_outer_product_fp32():
+    """The FP32 instances of the row-block and stacking kernels."""
+    A = synth.as_fp32(synth.erdos_renyi(600, 400, 5, seed=41))
+    B = synth.as_fp32(synth.erdos_renyi(400, 150, 4, seed=42))
+    offs = synth.partition_offsets(400, 5)
+    Ad = spg.DeviceCsc.from_host(A, dtype=torch.float32)
+    Bd = spg.DeviceCsc.from_host(B, dtype=torch.float32)
+    C = spg.outer_product(Ad, Bd, offs, 16)
+    ref = oracle.spgemm(A, B)
+    assert C.vals.dtype == torch.float32
+    assert np.array_equal(C.colptr.cpu().numpy(), ref.colptr)
+    assert np.array_equal(C.rowidx.cpu().numpy(), ref.rowidx)
+    assert_values(C.vals.cpu().numpy(), ref.vals, ref.absvals, False)
