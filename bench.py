@@ -510,6 +510,14 @@ def main():
     value = 2.0 * flops / (ms_per_step * 1e-3) / 1e9
     num_bytes = (4 + vsize) * (st["nnz_B"] + st["nnz_At"] + st["nnz_C"]) + 8 * (st["n"] + 1)
     achieved = num_bytes / (loop_ms * 1e-3) / 1e9
+    # what a plain device copy moving the same bytes (half read, half
+    # written) reaches at this size: the practical ceiling of a single
+    # launch of this volume, launch ramp included
+    half = max(1, num_bytes // 16)
+    csrc = torch.ones(half, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    copy_ms = _time_on(stream, lambda: cdst.copy_(csrc), 50)
+    del csrc, cdst
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -536,6 +544,9 @@ def main():
             "algorithmic_bytes": int(num_bytes),
             "avg_ms": round(loop_ms, 5),
             "avg_ms_in_step": round(num_ms, 5),
+            "plain_copy_same_bytes": {
+                "ms": round(copy_ms, 5),
+                "GBps": round(16 * half / (copy_ms * 1e-3) / 1e9, 1)},
         },
         "sizes": {"flops": flops, "nnz_C": st["nnz_C"], "nnz_At": st["nnz_At"], "kt": st["kt"],
                   "M": st["M"], "K": st["K"], "cv_memA": round(st["cv_memA"], 4),

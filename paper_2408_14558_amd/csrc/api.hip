@@ -568,6 +568,10 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
         pl.hpub_dev = (PublishedCounts *)((char *)dev + h_pub);
         pl.hflags = (uint32_t *)(h + h_flags);
         pl.hflags_dev = (uint32_t *)((char *)dev + h_flags);
+        // group bases and rank tiles sit at the same offsets in both blocks:
+        // k_plan_init copies them as one block of 8-byte words
+        pl.up_src = (const uint64_t *)((char *)dev + h_gbase);
+        pl.up_words = (int64_t)(((h_tiles - h_gbase) + sizeof(RankTile) * tiles.size()) / 8);
     }
     std::memcpy(h + h_gbase, gbase.data(), sizeof(int64_t) * (P + 1));
     if (!tiles.empty()) std::memcpy(h + h_tiles, tiles.data(), sizeof(RankTile) * tiles.size());
@@ -579,12 +583,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
         delete p;
         return code;
     };
-    // group bases and rank tiles sit at the same offsets in both blocks: one copy
-    const size_t up_bytes = (h_tiles - h_gbase) + sizeof(RankTile) * tiles.size();
-    hipError_t e = hipMemcpyAsync(pl.group_base, h + h_gbase, up_bytes, hipMemcpyHostToDevice,
-                                  pl.stream);
-    if (e != hipSuccess) return cleanup(fail(SPGEMM_EHIP, std::string("hipMemcpyAsync: ") +
-                                                              hipGetErrorString(e)));
+    static_assert(sizeof(RankTile) % 8 == 0 && sizeof(int64_t) == 8, "upload in 8-byte words");
+    hipError_t e = hipSuccess;
     if (tun.validate) {
         e = hipMemsetAsync(pl.ctr, 0, sizeof(DevCounters), pl.stream);
         if (e != hipSuccess) return cleanup(fail(SPGEMM_EHIP, hipGetErrorString(e)));
@@ -596,12 +596,12 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
                                                                    "(pointers or sorted unique rows)"));
     }
     if ((rc = launch_plan_kernels(pl))) return cleanup(rc);
+    // sparse flops, term ranges and symbolic bins depend on the patterns
+    // only: computed here, in one launch with the gather of A~, with their
+    // counts on their way to the host by the time spgemm_symbolic needs them
+    if (pl.n > 0) __atomic_store_n(pl.hflags + kFlagCounts, 0u, __ATOMIC_RELEASE);
+    if ((rc = launch_flop_bin_gather(pl))) return cleanup(rc);
     if (pl.n > 0) {
-        // sparse flops, term ranges and symbolic bins depend on the patterns
-        // only: computed here, right after the gather, with their counts on
-        // their way to the host by the time spgemm_symbolic needs them
-        __atomic_store_n(pl.hflags + kFlagCounts, 0u, __ATOMIC_RELEASE);
-        if ((rc = launch_flop_bin(pl))) return cleanup(rc);
         e = take_event(&pl.counts_ready);
         if (e == hipSuccess) e = hipEventRecord(pl.counts_ready, pl.stream);
         if (e != hipSuccess)

@@ -209,19 +209,21 @@ __device__ __forceinline__ long long chained_prefix(uint64_t *status, long long 
     return prefix;
 }
 
-// Called by every thread of every workgroup of a kernel, once, after the
-// workgroup's last update of the counters: the workgroup that finishes last
-// copies the counters the host needs to `out` (pinned host memory), so no
-// separate device-to-host copy is needed, then sets *ready to 1 with a
+// Called by every thread of each of `groups` workgroups of a kernel, once,
+// after the workgroup's last update of the counters: the workgroup that
+// finishes last
+// copies the counters the host needs to `out` (pinned host memory), so
+// no separate device-to-host copy is needed, then sets *ready to 1 with a
 // system-scope release store: the host may read `out` as soon as it sees the
 // flag.  `done` counts the finished workgroups.
 __device__ __forceinline__ void publish_when_last(unsigned long long *done,
+                                                  unsigned long long groups,
                                                   const DevCounters *ctr, PublishedCounts *out,
                                                   unsigned int *ready, int *lds_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();  // this workgroup's counter updates before its ticket
-        *lds_flag = atomicAdd(done, 1ull) == (unsigned long long)(gridDim.x - 1);
+        *lds_flag = atomicAdd(done, 1ull) == groups - 1;
     }
     __syncthreads();
     if (*lds_flag) {

@@ -10,7 +10,8 @@ namespace spg {
 
 constexpr int kGatherCols = 64;
 constexpr int kGatherThreads = 256;
-constexpr int kUnrollCopy = 4;
+constexpr int kUnrollCopy = 8;  // a tile of hub columns (10^5 entries) in few rounds
+constexpr int kUnrollTail = 4;
 
 struct GatherStage {
     int pref[kGatherCols];
@@ -19,17 +20,45 @@ struct GatherStage {
     int total;
 };
 
-// Largest o in [0, n) with pref[o] <= s (pref non-decreasing, pref[0] = 0).
-__device__ __forceinline__ int find_owner(const int *pref, int n, int s) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pref[mid] <= s)
-            lo = mid;
-        else
-            hi = mid - 1;
+// Largest o in [0, N) with pref[o] <= s (pref non-decreasing, pref[0] = 0;
+// N a power of two).  A fixed number of branch-free steps, so that the
+// searches of a thread's several elements overlap their LDS reads.
+template <int N>
+__device__ __forceinline__ int find_owner(const int *pref, int s) {
+    static_assert((N & (N - 1)) == 0, "N must be a power of two");
+    int o = 0;
+#pragma unroll
+    for (int step = N / 2; step > 0; step >>= 1) o += pref[o + step] <= s ? step : 0;
+    return o;
+}
+
+// One round of a thread's copy: elements e0 + u * kGatherThreads, u < U.
+template <int U, typename V, bool kRows>
+__device__ __forceinline__ void copy_round(int e0, int total, const GatherStage &st,
+                                           const int32_t *__restrict__ Arowidx,
+                                           const V *__restrict__ Avals,
+                                           int32_t *__restrict__ At_rowidx,
+                                           V *__restrict__ At_vals) {
+    long long dp[U];
+    int32_t r[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = min(e0 + u * kGatherThreads, total - 1);
+        const int o = find_owner<kGatherCols>(st.pref, e);
+        const int64_t off = e - st.pref[o];
+        const long long sp = st.src[o] + off;
+        dp[u] = st.dst[o] + off;
+        if (kRows) r[u] = Arowidx[sp];
+        v[u] = Avals[sp];
     }
-    return lo;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (e0 + u * kGatherThreads < total) {
+            if (kRows) At_rowidx[dp[u]] = r[u];
+            At_vals[dp[u]] = v[u];
+        }
+    }
 }
 
 // Copies the selected columns among A's columns [tile*kGatherCols,
@@ -67,31 +96,14 @@ __device__ __forceinline__ void gather_tile(int64_t tile, const int64_t *__restr
     }
     __syncthreads();
     const int total = st.total;
-    for (int e0 = tid; e0 < total; e0 += kUnrollCopy * kGatherThreads) {
-        long long dp[kUnrollCopy];
-        int32_t r[kUnrollCopy];
-        V v[kUnrollCopy];
-#pragma unroll
-        for (int u = 0; u < kUnrollCopy; ++u) {
-            const int e = e0 + u * kGatherThreads;
-            if (e < total) {
-                const int o = find_owner(st.pref, kGatherCols, e);
-                const int64_t off = e - st.pref[o];
-                const long long sp = st.src[o] + off;
-                dp[u] = st.dst[o] + off;
-                if (kRows) r[u] = Arowidx[sp];
-                v[u] = Avals[sp];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnrollCopy; ++u) {
-            const int e = e0 + u * kGatherThreads;
-            if (e < total) {
-                if (kRows) At_rowidx[dp[u]] = r[u];
-                At_vals[dp[u]] = v[u];
-            }
-        }
-    }
+    int e0 = tid;
+    // rounds whose kUnrollCopy slots all hold an element, then rounds of
+    // kUnrollTail; every slot loads (past the end: the tile's last element
+    // again), so the loads carry no branches and are in flight together
+    for (; e0 + (kUnrollCopy - 1) * kGatherThreads < total; e0 += kUnrollCopy * kGatherThreads)
+        copy_round<kUnrollCopy, V, kRows>(e0, total, st, Arowidx, Avals, At_rowidx, At_vals);
+    for (; e0 < total; e0 += kUnrollTail * kGatherThreads)
+        copy_round<kUnrollTail, V, kRows>(e0, total, st, Arowidx, Avals, At_rowidx, At_vals);
     __syncthreads();
 }
 

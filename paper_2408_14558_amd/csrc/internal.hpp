@@ -162,6 +162,10 @@ struct Plan {
     int64_t *group_base = nullptr;  // device [P+1]
     RankTile *rank_tiles = nullptr;  // device
     int64_t n_rank_tiles = 0;
+    // the host-written block [group_base .. rank_tiles] in pinned memory (a
+    // device address) and its size in 8-byte words: k_plan_init copies it
+    const uint64_t *up_src = nullptr;
+    int64_t up_words = 0;
     int32_t *map = nullptr;
     int32_t *colid = nullptr;
     int64_t *At_colptr = nullptr;
@@ -249,7 +253,7 @@ int launch_validate(Plan &p);
 int launch_plan_kernels(Plan &p);
 int launch_gather_values(Plan &p, const void *Avals);
 int launch_export_blocks(Plan &p, int64_t *blocks);
-int launch_flop_bin(Plan &p);
+int launch_flop_bin_gather(Plan &p);
 int launch_symbolic_bins(Plan &p);
 int launch_colptr_scan(Plan &p);
 int launch_symbolic_reset(Plan &p);

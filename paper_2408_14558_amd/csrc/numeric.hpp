@@ -37,22 +37,28 @@ struct NumArgs {
 // 32-bit word per term instead of a key and a value; after the sort every
 // lane fetches its values from LDS by slot.
 
+// q0, q1: the column's entries of B_i; o: its first output position; perm:
+// its kept sort order or NULL (all loaded by the caller up front, so that
+// they travel together instead of as a chain of round trips).
 template <int E, typename V, bool kPacked>
-__device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, int *s_rows,
-                                                V *s_vals, const uint16_t *perm) {
+__device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0, int64_t q1,
+                                                int64_t o, int *s_rows, V *s_vals,
+                                                const uint16_t *perm) {
     static_assert(E * kWave <= (1 << kSlotBits), "slot ids need kSlotBits bits");
+    const int lane = lane_id();
+    uint16_t sl[E];
+    if (perm) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) sl[r] = perm[lane * E + r];  // in flight with the terms
+    }
     int64_t p[E];
     V bv[E];
-    wave_terms<E, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.tr, a.Bvals, p, bv);
-    const int lane = lane_id();
+    wave_terms<E, V>(q0, q1, a.tr, a.Bvals, p, bv);
     int key[E];
     V val[E];
     if (perm) {
         // the symbolic phase kept the sorted order of the slots: rows and
         // values wait in LDS by slot and are read back in that order
-        uint16_t sl[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) sl[r] = perm[lane * E + r];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             if (p[r] >= 0) {
@@ -126,7 +132,6 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int32_t j, 
         }
     }
     wave_sync();
-    const int64_t o = a.Ccolptr[j];
     for (int e = lane; e < total; e += kWave) {
         a.Crow[o + e] = s_rows[e];
         a.Cval[o + e] = s_vals[e];
@@ -140,14 +145,16 @@ template <typename V, int EMAX, bool kPacked>
 __device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j, int *s_rows,
                                                   V *s_vals) {
     static_assert(EMAX == 4 || EMAX == 8, "EMAX is 4 or 8");
+    // every per-column load at once
     const int64_t f = a.flop[j];
     const int slot = a.tiny_perm ? a.col_slot[j] : -1;
+    const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1], o = a.Ccolptr[j];
     const uint16_t *perm = slot >= 0 ? a.tiny_perm + (size_t)slot * (EMAX * kWave) : nullptr;
-    if (f <= kWave) num_wave_column<1, V, kPacked>(a, j, s_rows, s_vals, perm);
-    else if (f <= 2 * kWave) num_wave_column<2, V, kPacked>(a, j, s_rows, s_vals, perm);
+    if (f <= kWave) num_wave_column<1, V, kPacked>(a, q0, q1, o, s_rows, s_vals, perm);
+    else if (f <= 2 * kWave) num_wave_column<2, V, kPacked>(a, q0, q1, o, s_rows, s_vals, perm);
     else if (EMAX == 4 || f <= 4 * kWave)
-        num_wave_column<4, V, kPacked>(a, j, s_rows, s_vals, perm);
-    else num_wave_column<EMAX, V, kPacked>(a, j, s_rows, s_vals, perm);
+        num_wave_column<4, V, kPacked>(a, q0, q1, o, s_rows, s_vals, perm);
+    else num_wave_column<EMAX, V, kPacked>(a, q0, q1, o, s_rows, s_vals, perm);
 }
 
 // --- hash: LDS table, compaction, bitonic sort -----------------------------

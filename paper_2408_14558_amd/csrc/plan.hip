@@ -7,13 +7,18 @@
 
 namespace spg {
 
-// Clears H, the group tables, the scan states and the counters.
+// Clears H, the group tables, the scan states and the counters, and copies
+// the host-written group bases and rank tiles from pinned host memory
+// (up_src) to the device (up_dst), in place of a separate copy.
 __global__ void k_plan_init(uint8_t *__restrict__ H, int64_t k, uint8_t *__restrict__ hit,
                             int32_t *__restrict__ gfirst, int32_t *__restrict__ glast, int64_t G,
                             uint64_t *__restrict__ status, int64_t nstatus,
-                            DevCounters *__restrict__ ctr, int64_t *__restrict__ At_colptr) {
+                            DevCounters *__restrict__ ctr, int64_t *__restrict__ At_colptr,
+                            const uint64_t *__restrict__ up_src, uint64_t *__restrict__ up_dst,
+                            int64_t up_words) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < up_words; i += stride) up_dst[i] = up_src[i];
     for (int64_t i = t0; i < k; i += stride) H[i] = 0;
     for (int64_t g = t0; g < G; g += stride) {
         hit[g] = 0;
@@ -279,10 +284,11 @@ int launch_validate(Plan &p) {
 
 int launch_plan_kernels(Plan &p) {
     const int64_t nstatus = p.n_rank_tiles + 2 * p.n_sel_tiles;
-    const int64_t clear_work = std::max<int64_t>(std::max<int64_t>(p.k, p.G), nstatus);
+    const int64_t clear_work =
+        std::max<int64_t>(std::max<int64_t>(p.k, p.G), std::max<int64_t>(nstatus, p.up_words));
     hipLaunchKernelGGL(k_plan_init, dim3(grid_for(clear_work, 256, 2048)), dim3(256), 0, p.stream,
                        p.H, p.k, p.hit, p.gfirst, p.glast, p.G, p.st_rank, nstatus, p.ctr,
-                       p.At_colptr);
+                       p.At_colptr, p.up_src, (uint64_t *)p.group_base, p.up_words);
     if (p.nnzB > 0)
         hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(p.nnzB, 256, 8192)), dim3(256), 0, p.stream,
                            p.Browidx, p.nnzB, p.H);
@@ -295,17 +301,8 @@ int launch_plan_kernels(Plan &p) {
         hipLaunchKernelGGL(k_select, dim3((unsigned)p.n_sel_tiles), dim3(kScanThreads), 0,
                            p.stream, p.Acolptr, p.k, p.gid, p.hit, p.gfirst, p.map, p.colid,
                            p.At_colptr, p.st_sel_cnt, p.st_sel_nnz, p.n_sel_tiles, p.ctr);
-    if (p.k > 0 && p.nnzA > 0) {
-        const unsigned g = (unsigned)((p.k + kGatherCols - 1) / kGatherCols);
-        if (p.dtype == SPGEMM_F64)
-            hipLaunchKernelGGL((k_gather<double, true>), dim3(g), dim3(kGatherThreads), 0, p.stream,
-                               p.Acolptr, p.Arowidx, (const double *)p.Avals, p.map, p.At_colptr,
-                               p.k, p.At_rowidx, (double *)p.At_vals);
-        else
-            hipLaunchKernelGGL((k_gather<float, true>), dim3(g), dim3(kGatherThreads), 0, p.stream,
-                               p.Acolptr, p.Arowidx, (const float *)p.Avals, p.map, p.At_colptr,
-                               p.k, p.At_rowidx, (float *)p.At_vals);
-    }
+    // the gather of A~ runs in one launch with the flops and bins
+    // (launch_flop_bin_gather)
     SPG_HIP(hipGetLastError());
     return SPGEMM_OK;
 }

@@ -3,6 +3,7 @@
 // each output column (Sec. III-A, column-by-column formula; a row counts as
 // soon as one product reaches it), and the exclusive scan giving C_i's
 // column pointers.  The scan also bins the columns for the numeric phase.
+#include "gather.hpp"
 #include "terms.hpp"
 
 namespace spg {
@@ -63,12 +64,13 @@ __device__ __forceinline__ int term_range(int64_t q, const int32_t *__restrict__
 }
 
 // Sparse flops of every column of B_i and its symbolic bin, and the term
-// range of every entry of B_i.  S lanes walk
+// range of every entry of B_i; tile `blk` of `ngroups`.  S lanes walk
 // one column (S picked from the average column length); columns with more
-// than 16*S entries are summed by a whole wave afterwards.
+// than 16*S entries are walked by the whole workgroup afterwards.
 constexpr int kFlopThreads = 256;
 template <int S>
-__global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
+__device__ __forceinline__ void flop_bin_tile(
+    int64_t blk, int64_t ngroups,
     int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
     int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
@@ -84,11 +86,11 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     __shared__ int s_base[kNumBins];
     __shared__ int s_nlong;
     __shared__ long long s_flops;
+    __shared__ long long s_red[kFlopThreads / kWave + 1];
     const int tid = threadIdx.x;
     {
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t s = (int64_t)blockIdx.x * blockDim.x + tid; s < nstatus; s += stride)
-            status[s] = 0;
+        const int64_t stride = ngroups * kFlopThreads;
+        for (int64_t s = blk * kFlopThreads + tid; s < nstatus; s += stride) status[s] = 0;
     }
     if (tid < kNumBins) s_cnt[tid] = 0;
     if (tid == 0) {
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         s_nlong = 0;
     }
     __syncthreads();
-    const int64_t j0 = (int64_t)blockIdx.x * COLS;
+    const int64_t j0 = blk * COLS;
     const int nloc = (int)min<int64_t>(COLS, n - j0);
     const int lc = tid / S, sub = tid % S;
     long long acc = 0;
@@ -116,15 +118,55 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
         else s_f[lc] = acc;
     }
     __syncthreads();
-    const int wv = tid / kWave, lane = lane_id();
-    for (int li = wv; li < s_nlong; li += kFlopThreads / kWave) {
+    // long columns one after the other, each by the whole workgroup with
+    // kLongUnroll entries in flight per thread: the loads of one entry
+    // (row, map, A~'s pointers) depend on each other, those of different
+    // entries do not
+    constexpr int kLongUnroll = 8;
+    const int nlong = s_nlong;
+    for (int li = 0; li < nlong; ++li) {
         const int t = s_long[li];
-        const int64_t q1 = Bcolptr[j0 + t + 1];
+        const int64_t q0 = Bcolptr[j0 + t], q1 = Bcolptr[j0 + t + 1];
         long long a2 = 0;
-        for (int64_t q = Bcolptr[j0 + t] + lane; q < q1; q += kWave)
-            a2 += term_range(q, Browidx, map, At_colptr, tstart, tlen);
-        a2 = wave_sum(a2);
-        if (lane == 0) s_f[t] = a2;
+        for (int64_t qb = q0 + tid; qb < q1; qb += kLongUnroll * kFlopThreads) {
+            // loads without branches (an index out of the range reads a
+            // valid element and is discarded), so all of a round's loads of
+            // one kind are in flight together
+            int32_t jt[kLongUnroll];
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const int64_t q = qb + (int64_t)u * kFlopThreads;
+                const int32_t r = Browidx[q < q1 ? q : q1 - 1];
+                jt[u] = q < q1 ? r : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const int32_t c = map[jt[u] >= 0 ? jt[u] : 0];
+                jt[u] = jt[u] >= 0 ? c : -1;
+            }
+            long long st[kLongUnroll];
+            int len[kLongUnroll];
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const bool ok = jt[u] >= 0;
+                const long long a0 = At_colptr[ok ? jt[u] : 0];
+                const long long a1 = At_colptr[ok ? jt[u] + 1 : 0];
+                st[u] = ok ? a0 : 0;
+                len[u] = ok ? (int)(a1 - a0) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const int64_t q = qb + (int64_t)u * kFlopThreads;
+                if (q < q1) {
+                    tstart[q] = st[u];
+                    tlen[q] = len[u];
+                    a2 += len[u];
+                }
+            }
+        }
+        long long tot;
+        group_excl_scan64<kFlopThreads>(a2, s_red, &tot);
+        if (tid == 0) s_f[t] = tot;
     }
     __syncthreads();
     if (tid < nloc) {
@@ -142,7 +184,35 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin(
     if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops.v, s_flops);
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
     __shared__ int s_last;
-    publish_when_last(&ctr->tickets[kTkFlopDone], ctr, hout, hready, &s_last);
+    publish_when_last(&ctr->tickets[kTkFlopDone], (unsigned long long)ngroups, ctr, hout, hready,
+                      &s_last);
+}
+
+// One launch for two independent steps that both follow the selection: the
+// flop and binning tiles (first, since the host waits for their counts) and
+// the gather tiles of A~.  Neither reads what the other writes, so their
+// chains of dependent loads overlap instead of running one after the other.
+static_assert(kFlopThreads == kGatherThreads, "both tiles use the whole workgroup");
+template <int S, typename V>
+__global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
+    int64_t nflop, int64_t n, const int64_t *__restrict__ Bcolptr,
+    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
+    const int64_t *__restrict__ At_colptr, Thresholds th, int64_t *__restrict__ tstart,
+    int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot, int64_t *__restrict__ flop,
+    int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list, uint64_t *__restrict__ status,
+    int64_t nstatus, DevCounters *__restrict__ ctr, PublishedCounts *__restrict__ hout,
+    unsigned int *__restrict__ hready, int64_t k, const int64_t *__restrict__ Acolptr,
+    const int32_t *__restrict__ Arowidx, const V *__restrict__ Avals,
+    int32_t *__restrict__ At_rowidx, V *__restrict__ At_vals) {
+    const int64_t blk = blockIdx.x;
+    if (blk < nflop) {
+        flop_bin_tile<S>(blk, nflop, n, Bcolptr, Browidx, map, At_colptr, th, tstart, tlen,
+                         col_slot, flop, sym_bin, sym_list, status, nstatus, ctr, hout, hready);
+    } else {
+        __shared__ GatherStage st;
+        gather_tile<V, true>(blk - nflop, Acolptr, Arowidx, Avals, map, At_colptr, k, At_rowidx,
+                             At_vals, st);
+    }
 }
 
 // --- tiny bin: one wave per column, <= 64*8 terms in registers -------------
@@ -356,7 +426,7 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     }
     append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->num_count, num_list, n);
     __shared__ int s_last;
-    publish_when_last(&ctr->tickets[kTkColptrDone], ctr, hout, hready, &s_last);
+    publish_when_last(&ctr->tickets[kTkColptrDone], gridDim.x, ctr, hout, hready, &s_last);
 }
 
 // Clears what one symbolic phase accumulates (the colptr scan's ticket and
@@ -384,24 +454,34 @@ int launch_symbolic_reset(Plan &p) {
     return SPGEMM_OK;
 }
 
-template <int S>
-static int flop_bin_launch(Plan &p) {
+template <int S, typename V>
+static int flop_bin_gather_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
-    const unsigned g = (unsigned)((p.n + COLS - 1) / COLS);
-    hipLaunchKernelGGL((k_flop_bin<S>), dim3(g), dim3(kFlopThreads), 0, p.stream, p.n, p.Bcolptr,
-                       p.Browidx, p.map, p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot,
-                       p.flop, p.sym_bin, p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr,
-                       p.hpub_dev, p.hflags_dev + kFlagCounts);
-    SPG_LAUNCHED("k_flop_bin");
+    const int64_t nflop = (p.n + COLS - 1) / COLS;
+    const int64_t ngather = p.nnzA > 0 ? (p.k + kGatherCols - 1) / kGatherCols : 0;
+    if (nflop + ngather == 0) return SPGEMM_OK;
+    hipLaunchKernelGGL((k_flop_bin_gather<S, V>), dim3((unsigned)(nflop + ngather)),
+                       dim3(kFlopThreads), 0, p.stream, nflop, p.n, p.Bcolptr, p.Browidx, p.map,
+                       p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot, p.flop, p.sym_bin,
+                       p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr, p.hpub_dev,
+                       p.hflags_dev + kFlagCounts, p.k, p.Acolptr, p.Arowidx,
+                       (const V *)p.Avals, p.At_rowidx, (V *)p.At_vals);
+    SPG_LAUNCHED("k_flop_bin_gather (" + std::to_string(nflop) + " flop tiles, " +
+                 std::to_string(ngather) + " gather tiles)");
     return SPGEMM_OK;
 }
 
-int launch_flop_bin(Plan &p) {
-    if (p.n == 0) return SPGEMM_OK;
-    const double avg = (double)p.nnzB / (double)p.n;
-    if (avg <= 4.0) return flop_bin_launch<1>(p);
-    if (avg <= 32.0) return flop_bin_launch<4>(p);
-    return flop_bin_launch<16>(p);
+template <int S>
+static int flop_bin_gather_dtype(Plan &p) {
+    return p.dtype == SPGEMM_F64 ? flop_bin_gather_launch<S, double>(p)
+                                 : flop_bin_gather_launch<S, float>(p);
+}
+
+int launch_flop_bin_gather(Plan &p) {
+    const double avg = p.n > 0 ? (double)p.nnzB / (double)p.n : 0.0;
+    if (avg <= 4.0) return flop_bin_gather_dtype<1>(p);
+    if (avg <= 32.0) return flop_bin_gather_dtype<4>(p);
+    return flop_bin_gather_dtype<16>(p);
 }
 
 template <int T, int G>
