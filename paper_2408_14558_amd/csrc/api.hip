@@ -488,6 +488,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t up_gap = o_tiles - o_gbase;
     const size_t o_map = cv.take<int32_t>(pl.k);
     const size_t o_colid = cv.take<int32_t>(pl.k);
+    const size_t o_cst = cv.take<int64_t>(pl.k);
+    const size_t o_cln = cv.take<int32_t>(pl.k);
     const size_t o_Atc = cv.take<int64_t>(pl.k + 1);
     const size_t o_Atr = cv.take<int32_t>(pl.nnzA);
     const size_t o_Atv = cv.take<uint8_t>(pl.nnzA * (int64_t)pl.vsize);
@@ -502,6 +504,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_cur = cv.take<int32_t>(pl.nnzB);
     const size_t o_tst = cv.take<int64_t>(pl.nnzB);
     const size_t o_dsl = cv.take<int32_t>(pl.n);
+    const size_t o_arr = cv.take<int32_t>(pl.n);
     const size_t o_tln = cv.take<int32_t>(pl.nnzB);
     const size_t ws_bytes = cv.off;
     if (tun.workspace_limit > 0 && (int64_t)ws_bytes > tun.workspace_limit) {
@@ -536,6 +539,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.rank_tiles = (RankTile *)(w + o_tiles);
     pl.map = (int32_t *)(w + o_map);
     pl.colid = (int32_t *)(w + o_colid);
+    pl.col_start = (int64_t *)(w + o_cst);
+    pl.col_len = (int32_t *)(w + o_cln);
     pl.At_colptr = (int64_t *)(w + o_Atc);
     pl.At_rowidx = (int32_t *)(w + o_Atr);
     pl.At_vals = (void *)(w + o_Atv);
@@ -552,6 +557,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.cursor = (int32_t *)(w + o_cur);
     pl.tstart = (int64_t *)(w + o_tst);
     pl.col_slot = (int32_t *)(w + o_dsl);
+    pl.arrive = (int32_t *)(w + o_arr);
     pl.tlen = (int32_t *)(w + o_tln);
     char *h = (char *)pl.pinned;
     pl.hctr = (DevCounters *)(h + h_ctr);

@@ -168,6 +168,10 @@ struct Plan {
     int64_t up_words = 0;
     int32_t *map = nullptr;
     int32_t *colid = nullptr;
+    // k: where column c of A sits in A~ (first entry, length; 0, 0 when not
+    // chosen), so a row of B_i finds its products with one load
+    int64_t *col_start = nullptr;
+    int32_t *col_len = nullptr;
     int64_t *At_colptr = nullptr;
     int32_t *At_rowidx = nullptr;
     void *At_vals = nullptr;
@@ -186,7 +190,8 @@ struct Plan {
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
     // What the symbolic phase keeps for the numeric phase, per column: its
     // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
-    int32_t *col_slot = nullptr;    // n
+    int32_t *col_slot = nullptr;
+    int32_t *arrive = nullptr;    // n: chunks of the flops pass done per long column    // n
     void *kept = nullptr;           // pooled block holding the two parts below
     size_t kept_bytes = 0;
     uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns

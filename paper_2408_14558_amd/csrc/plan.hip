@@ -7,7 +7,8 @@
 
 namespace spg {
 
-// Clears H, the group tables, the scan states and the counters, and copies
+// Clears H, the group tables, the scan states, the counters, the flops and
+// arrival counts of the flops pass, and copies
 // the host-written group bases and rank tiles from pinned host memory
 // (up_src) to the device (up_dst), in place of a separate copy.
 __global__ void k_plan_init(uint8_t *__restrict__ H, int64_t k, uint8_t *__restrict__ hit,
@@ -15,10 +16,15 @@ __global__ void k_plan_init(uint8_t *__restrict__ H, int64_t k, uint8_t *__restr
                             uint64_t *__restrict__ status, int64_t nstatus,
                             DevCounters *__restrict__ ctr, int64_t *__restrict__ At_colptr,
                             const uint64_t *__restrict__ up_src, uint64_t *__restrict__ up_dst,
-                            int64_t up_words) {
+                            int64_t up_words, int64_t *__restrict__ flop,
+                            int32_t *__restrict__ arrive, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t0; i < up_words; i += stride) up_dst[i] = up_src[i];
+    for (int64_t j = t0; j < n; j += stride) {
+        flop[j] = 0;
+        arrive[j] = 0;
+    }
     for (int64_t i = t0; i < k; i += stride) H[i] = 0;
     for (int64_t g = t0; g < G; g += stride) {
         hit[g] = 0;
@@ -113,13 +119,13 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
 
 // Selection (column lies in a chosen group) and the map into A~: an
 // exclusive scan of the selection, with a second scan of the selected
-// columns' lengths giving A~'s column pointers.  Counts kt, nnz(A~) and the
-// chosen groups M.
+// columns' lengths giving A~'s column pointers (also kept per column of A in
+// col_start, col_len).  Counts kt, nnz(A~) and the chosen groups M.
 __global__ __launch_bounds__(kScanThreads) void k_select(
     const int64_t *__restrict__ Acolptr, int64_t k, const int32_t *__restrict__ gid,
     const uint8_t *__restrict__ hit, const int32_t *__restrict__ gfirst,
     int32_t *__restrict__ map, int32_t *__restrict__ colid, int64_t *__restrict__ At_colptr,
-    uint64_t *__restrict__ st_cnt, uint64_t *__restrict__ st_nnz, int64_t ntiles,
+    int64_t *__restrict__ col_start, int32_t *__restrict__ col_len, uint64_t *__restrict__ st_cnt, uint64_t *__restrict__ st_nnz, int64_t ntiles,
     DevCounters *__restrict__ ctr) {
     __shared__ long long s_ticket;
     __shared__ int s_tmp[kScanThreads / kWave + 1];
@@ -170,10 +176,14 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
             map[c] = (int32_t)j;
             colid[j] = (int32_t)c;
             At_colptr[j] = pos;
+            col_start[c] = pos;
+            col_len[c] = (int32_t)len[i];
             ++j;
             pos += len[i];
         } else {
             map[c] = -1;
+            col_start[c] = 0;
+            col_len[c] = 0;
         }
     }
     int msum = wave_sum(mcnt);
@@ -284,11 +294,13 @@ int launch_validate(Plan &p) {
 
 int launch_plan_kernels(Plan &p) {
     const int64_t nstatus = p.n_rank_tiles + 2 * p.n_sel_tiles;
-    const int64_t clear_work =
-        std::max<int64_t>(std::max<int64_t>(p.k, p.G), std::max<int64_t>(nstatus, p.up_words));
+    const int64_t clear_work = std::max<int64_t>(
+        std::max<int64_t>(std::max<int64_t>(p.k, p.G), std::max<int64_t>(nstatus, p.up_words)),
+        p.n);
     hipLaunchKernelGGL(k_plan_init, dim3(grid_for(clear_work, 256, 2048)), dim3(256), 0, p.stream,
                        p.H, p.k, p.hit, p.gfirst, p.glast, p.G, p.st_rank, nstatus, p.ctr,
-                       p.At_colptr, p.up_src, (uint64_t *)p.group_base, p.up_words);
+                       p.At_colptr, p.up_src, (uint64_t *)p.group_base, p.up_words, p.flop,
+                       p.arrive, p.n);
     if (p.nnzB > 0)
         hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(p.nnzB, 256, 8192)), dim3(256), 0, p.stream,
                            p.Browidx, p.nnzB, p.H);
@@ -300,7 +312,8 @@ int launch_plan_kernels(Plan &p) {
     if (p.n_sel_tiles > 0)
         hipLaunchKernelGGL(k_select, dim3((unsigned)p.n_sel_tiles), dim3(kScanThreads), 0,
                            p.stream, p.Acolptr, p.k, p.gid, p.hit, p.gfirst, p.map, p.colid,
-                           p.At_colptr, p.st_sel_cnt, p.st_sel_nnz, p.n_sel_tiles, p.ctr);
+                           p.At_colptr, p.col_start, p.col_len, p.st_sel_cnt, p.st_sel_nnz,
+                           p.n_sel_tiles, p.ctr);
     // the gather of A~ runs in one launch with the flops and bins
     // (launch_flop_bin_gather)
     SPG_HIP(hipGetLastError());

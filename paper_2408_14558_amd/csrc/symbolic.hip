@@ -45,169 +45,258 @@ __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const
 }
 
 // Records where entry q of B_i finds its products in A~ (the column of A~
-// that map assigns to q's row) and returns their number.
+// that map assigns to q's row, kept per row in col_start, col_len) and
+// returns their number.
 __device__ __forceinline__ int term_range(int64_t q, const int32_t *__restrict__ Browidx,
-                                          const int32_t *__restrict__ map,
-                                          const int64_t *__restrict__ At_colptr,
+                                          const int64_t *__restrict__ col_start,
+                                          const int32_t *__restrict__ col_len,
                                           int64_t *__restrict__ tstart,
                                           int32_t *__restrict__ tlen) {
-    const int32_t jt = map[Browidx[q]];
-    long long start = 0;
-    int len = 0;
-    if (jt >= 0) {
-        start = At_colptr[jt];
-        len = (int)(At_colptr[jt + 1] - start);
-    }
+    const int32_t r = Browidx[q];
+    const long long start = col_start[r];
+    const int len = col_len[r];
     tstart[q] = start;
     tlen[q] = len;
     return len;
 }
 
 // Sparse flops of every column of B_i and its symbolic bin, and the term
-// range of every entry of B_i; tile `blk` of `ngroups`.  S lanes walk
-// one column (S picked from the average column length); columns with more
-// than 16*S entries are walked by the whole workgroup afterwards.
+// range of every entry of B_i.  Column tiles: S lanes walk one column (S
+// picked from the average column length).  A column with more than 16*S
+// entries (long) is left to the chunk workgroups instead: they split B_i's
+// entries into chunks of kLongChunk and walk the long columns' entries in
+// their chunk, so a hub column of 10^4 entries is walked by several
+// workgroups at once; the chunk that completes a long column bins it.
 constexpr int kFlopThreads = 256;
+constexpr int64_t kLongChunk = 8192;
+
+struct FlopArgs {
+    int64_t n, nnzB;
+    const int64_t *Bcolptr;
+    const int32_t *Browidx;
+    const int64_t *col_start;  // place in A~ of every column of A (row of B_i)
+    const int32_t *col_len;
+    Thresholds th;
+    int64_t *tstart;
+    int32_t *tlen;
+    int32_t *col_slot;
+    int64_t *flop;     // zero on entry (long columns add into it)
+    int32_t *arrive;   // zero on entry: chunks done per long column
+    int32_t *sym_bin;
+    int32_t *sym_list;
+    uint64_t *status;  // the colptr scan's tile states, cleared here
+    int64_t nstatus;
+    DevCounters *ctr;
+};
+
 template <int S>
-__device__ __forceinline__ void flop_bin_tile(
-    int64_t blk, int64_t ngroups,
-    int64_t n, const int64_t *__restrict__ Bcolptr, const int32_t *__restrict__ Browidx,
-    const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr, Thresholds th,
-    int64_t *__restrict__ tstart, int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot,
-    int64_t *__restrict__ flop, int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list,
-    uint64_t *__restrict__ status, int64_t nstatus, DevCounters *__restrict__ ctr,
-    PublishedCounts *__restrict__ hout, unsigned int *__restrict__ hready) {
+__device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups,
+                                                 const FlopArgs &a) {
     constexpr int COLS = kFlopThreads / S;
     __shared__ int s_bin[COLS];
     __shared__ int s_lpos[COLS];
-    __shared__ int s_long[COLS];
     __shared__ long long s_f[COLS];
     __shared__ int s_cnt[kNumBins];
     __shared__ int s_base[kNumBins];
-    __shared__ int s_nlong;
     __shared__ long long s_flops;
-    __shared__ long long s_red[kFlopThreads / kWave + 1];
     const int tid = threadIdx.x;
     {
         const int64_t stride = ngroups * kFlopThreads;
-        for (int64_t s = blk * kFlopThreads + tid; s < nstatus; s += stride) status[s] = 0;
+        for (int64_t s = blk * kFlopThreads + tid; s < a.nstatus; s += stride) a.status[s] = 0;
     }
     if (tid < kNumBins) s_cnt[tid] = 0;
-    if (tid == 0) {
-        s_flops = 0;
-        s_nlong = 0;
-    }
+    if (tid == 0) s_flops = 0;
     __syncthreads();
     const int64_t j0 = blk * COLS;
-    const int nloc = (int)min<int64_t>(COLS, n - j0);
+    const int nloc = (int)min<int64_t>(COLS, a.n - j0);
     const int lc = tid / S, sub = tid % S;
     long long acc = 0;
-    bool deferred = false;
+    bool is_long = false;
     if (lc < nloc) {
-        const int64_t q0 = Bcolptr[j0 + lc], q1 = Bcolptr[j0 + lc + 1];
-        if (q1 - q0 <= 16 * S) {
+        const int64_t q0 = a.Bcolptr[j0 + lc], q1 = a.Bcolptr[j0 + lc + 1];
+        is_long = q1 - q0 > 16 * S;
+        if (!is_long) {
 #pragma unroll 4
-            for (int64_t q = q0 + sub; q < q1; q += S) acc += term_range(q, Browidx, map, At_colptr, tstart, tlen);
-        } else {
-            deferred = true;
+            for (int64_t q = q0 + sub; q < q1; q += S)
+                acc += term_range(q, a.Browidx, a.col_start, a.col_len, a.tstart, a.tlen);
         }
     }
     acc = wave_sum<S>(acc);
-    if (lc < nloc && sub == 0) {
-        if (deferred) s_long[atomicAdd(&s_nlong, 1)] = lc;
-        else s_f[lc] = acc;
-    }
-    __syncthreads();
-    // long columns one after the other, each by the whole workgroup with
-    // kLongUnroll entries in flight per thread: the loads of one entry
-    // (row, map, A~'s pointers) depend on each other, those of different
-    // entries do not
-    constexpr int kLongUnroll = 8;
-    const int nlong = s_nlong;
-    for (int li = 0; li < nlong; ++li) {
-        const int t = s_long[li];
-        const int64_t q0 = Bcolptr[j0 + t], q1 = Bcolptr[j0 + t + 1];
-        long long a2 = 0;
-        for (int64_t qb = q0 + tid; qb < q1; qb += kLongUnroll * kFlopThreads) {
-            // loads without branches (an index out of the range reads a
-            // valid element and is discarded), so all of a round's loads of
-            // one kind are in flight together
-            int32_t jt[kLongUnroll];
-#pragma unroll
-            for (int u = 0; u < kLongUnroll; ++u) {
-                const int64_t q = qb + (int64_t)u * kFlopThreads;
-                const int32_t r = Browidx[q < q1 ? q : q1 - 1];
-                jt[u] = q < q1 ? r : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < kLongUnroll; ++u) {
-                const int32_t c = map[jt[u] >= 0 ? jt[u] : 0];
-                jt[u] = jt[u] >= 0 ? c : -1;
-            }
-            long long st[kLongUnroll];
-            int len[kLongUnroll];
-#pragma unroll
-            for (int u = 0; u < kLongUnroll; ++u) {
-                const bool ok = jt[u] >= 0;
-                const long long a0 = At_colptr[ok ? jt[u] : 0];
-                const long long a1 = At_colptr[ok ? jt[u] + 1 : 0];
-                st[u] = ok ? a0 : 0;
-                len[u] = ok ? (int)(a1 - a0) : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kLongUnroll; ++u) {
-                const int64_t q = qb + (int64_t)u * kFlopThreads;
-                if (q < q1) {
-                    tstart[q] = st[u];
-                    tlen[q] = len[u];
-                    a2 += len[u];
-                }
-            }
-        }
-        long long tot;
-        group_excl_scan64<kFlopThreads>(a2, s_red, &tot);
-        if (tid == 0) s_f[t] = tot;
-    }
+    if (lc < nloc && sub == 0) s_f[lc] = is_long ? -1 : acc;
     __syncthreads();
     if (tid < nloc) {
         const int64_t j = j0 + tid;
         const long long f = s_f[tid];
-        flop[j] = f;
-        col_slot[j] = -1;
-        const int b = sym_bin_of(f, th);
-        sym_bin[j] = b;
+        a.col_slot[j] = -1;
+        int b = kBinEmpty;
+        if (f >= 0) {  // a long column is binned by the chunk that completes it
+            a.flop[j] = f;
+            b = sym_bin_of(f, a.th);
+            a.sym_bin[j] = b;
+            if (f) atomic_add_i64(&s_flops, f);
+        }
         s_bin[tid] = b;
         s_lpos[tid] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
-        if (f) atomic_add_i64(&s_flops, f);
     }
     __syncthreads();
-    if (tid == 0 && s_flops) atomic_add_i64(&ctr->flops.v, s_flops);
-    append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, ctr->sym_count, sym_list, n);
-    __shared__ int s_last;
-    publish_when_last(&ctr->tickets[kTkFlopDone], (unsigned long long)ngroups, ctr, hout, hready,
-                      &s_last);
+    if (tid == 0 && s_flops) atomic_add_i64(&a.ctr->flops.v, s_flops);
+    append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, a.ctr->sym_count, a.sym_list, a.n);
+}
+
+// Chunk c of B_i's entries, [c*kLongChunk, min((c+1)*kLongChunk, nnzB)):
+// the term ranges of the long columns' entries in it and their flops.  The
+// long columns met in the chunk (at most kLongList: each has more than 16
+// entries, save the two cut by the chunk's ends) are listed with their part
+// of the chunk, and the whole workgroup walks those parts as one flat range.
+constexpr int kLongList = 512;
+static_assert(kLongChunk / 17 + 2 <= kLongList, "the list holds every long column of a chunk");
+template <int S>
+__device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
+    constexpr int kColsPer = 4;   // columns per thread and batch
+    constexpr int kLongUnroll = 8;
+    __shared__ int64_t s_j;
+    __shared__ int s_nl, s_more;
+    __shared__ int32_t s_col[kLongList];
+    __shared__ int64_t s_lo[kLongList];
+    __shared__ int s_pre[kLongList + 1];  // prefix of the parts' lengths
+    __shared__ long long s_part[kLongList];
+    __shared__ int s_tmp[kFlopThreads / kWave + 1];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int64_t e0 = c * kLongChunk, e1 = min(e0 + kLongChunk, a.nnzB);
+    // the column holding entry e0 (the last j with Bcolptr[j] <= e0): a
+    // 64-way search by one wave, Bcolptr[lo] <= e0 < Bcolptr[hi] throughout
+    if (tid < kWave) {
+        int64_t lo = 0, hi = a.n;
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + kWave - 1) / kWave;
+            const int64_t idx = lo + (int64_t)(lane + 1) * step;
+            const bool le = idx < hi && a.Bcolptr[idx] <= e0;
+            const int64_t nlo = lo + (int64_t)__popcll(__ballot(le)) * step;
+            hi = min(hi, nlo + step);
+            lo = nlo;
+        }
+        if (lane == 0) {
+            s_j = lo;
+            s_nl = 0;
+        }
+    }
+    __syncthreads();
+    // the long columns from there on, kColsPer * kFlopThreads at a time,
+    // until one ends at or past e1 (every column before it starts below e1
+    // and ends above e0, so it has entries in the chunk)
+    constexpr int kBatch = kColsPer * kFlopThreads;
+    for (int64_t jb = s_j;; jb += kBatch) {
+        if (tid == 0) s_more = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kColsPer; ++i) {
+            const int64_t j = jb + (int64_t)i * kFlopThreads + tid;
+            if (j < a.n) {
+                const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
+                if (q0 < e1 && q1 - q0 > 16 * S) {
+                    const int at = atomicAdd(&s_nl, 1);
+                    s_col[at] = (int32_t)j;
+                    s_lo[at] = max(q0, e0);
+                    s_pre[at] = (int)(min(q1, e1) - max(q0, e0));
+                }
+                if (i == kColsPer - 1 && tid == kFlopThreads - 1 && q1 < e1) s_more = 1;
+            }
+        }
+        __syncthreads();
+        const bool more = s_more != 0;
+        __syncthreads();
+        if (!more || jb + kBatch >= a.n) break;
+    }
+    const int nl = s_nl;
+    if (nl == 0) return;  // uniform
+    // lengths -> exclusive prefix (two per thread), partial sums cleared
+    int v0 = 0, v1 = 0;
+    if (2 * tid < nl) v0 = s_pre[2 * tid];
+    if (2 * tid + 1 < nl) v1 = s_pre[2 * tid + 1];
+    int total;
+    const int ex = group_excl_scan<kFlopThreads>(v0 + v1, s_tmp, &total);
+    if (2 * tid < nl) {
+        s_pre[2 * tid] = ex;
+        s_part[2 * tid] = 0;
+    }
+    if (2 * tid + 1 < nl) {
+        s_pre[2 * tid + 1] = ex + v0;
+        s_part[2 * tid + 1] = 0;
+    }
+    for (int i = nl + tid; i < kLongList + 1; i += kFlopThreads) s_pre[i] = total;
+    __syncthreads();
+    // the flat walk: element e of the parts lies in part li, the last with
+    // s_pre[li] <= e; loads without branches (past the end: the last element
+    // again, discarded), so a round's loads of one kind are in flight together
+    for (int eb = tid; eb < total; eb += kLongUnroll * kFlopThreads) {
+        int li[kLongUnroll];
+        int64_t q[kLongUnroll];
+        int32_t r[kLongUnroll];
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; ++u) {
+            const int e = min(eb + u * kFlopThreads, total - 1);
+            int o = 0;
+#pragma unroll
+            for (int step = kLongList / 2; step > 0; step >>= 1)
+                o += s_pre[o + step] <= e ? step : 0;
+            li[u] = o;
+            q[u] = s_lo[o] + (e - s_pre[o]);
+            r[u] = a.Browidx[q[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kLongUnroll; ++u) {
+            const long long st = a.col_start[r[u]];
+            const int len = a.col_len[r[u]];
+            if (eb + u * kFlopThreads < total) {
+                a.tstart[q[u]] = st;
+                a.tlen[q[u]] = len;
+                if (len) atomic_add_i64(&s_part[li[u]], (long long)len);
+            }
+        }
+    }
+    __syncthreads();
+    // one thread per listed column: its flops so far, then the arrival; the
+    // chunk that completes the column bins it
+    for (int i = tid; i < nl; i += kFlopThreads) {
+        const int64_t jc = s_col[i];
+        const int64_t q0 = a.Bcolptr[jc], q1 = a.Bcolptr[jc + 1];
+        if (s_part[i]) atomic_add_i64(reinterpret_cast<long long *>(a.flop + jc), s_part[i]);
+        __threadfence();  // the flops before the arrival
+        const int ncover = (int)((q1 - 1) / kLongChunk - q0 / kLongChunk + 1);
+        if (atomicAdd(&a.arrive[jc], 1) == ncover - 1) {
+            __threadfence();  // every chunk's flops are visible
+            const long long f =
+                __hip_atomic_load(a.flop + jc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int b = sym_bin_of(f, a.th);
+            a.sym_bin[jc] = b;
+            if (b != kBinEmpty)
+                a.sym_list[(int64_t)b * a.n + atomicAdd(&a.ctr->sym_count[b].v, 1)] = (int32_t)jc;
+            if (f) atomic_add_i64(&a.ctr->flops.v, f);
+        }
+    }
 }
 
 // One launch for two independent steps that both follow the selection: the
-// flop and binning tiles (first, since the host waits for their counts) and
-// the gather tiles of A~.  Neither reads what the other writes, so their
-// chains of dependent loads overlap instead of running one after the other.
-static_assert(kFlopThreads == kGatherThreads, "both tiles use the whole workgroup");
+// flops and bins (column tiles, then chunk workgroups; first, since the host
+// waits for their counts) and the gather tiles of A~.  Neither reads what
+// the other writes, so their chains of dependent loads overlap instead of
+// running one after the other.  The last of the flop workgroups publishes
+// the counters.
+static_assert(kFlopThreads == kGatherThreads, "all tiles use the whole workgroup");
 template <int S, typename V>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
-    int64_t nflop, int64_t n, const int64_t *__restrict__ Bcolptr,
-    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ map,
-    const int64_t *__restrict__ At_colptr, Thresholds th, int64_t *__restrict__ tstart,
-    int32_t *__restrict__ tlen, int32_t *__restrict__ col_slot, int64_t *__restrict__ flop,
-    int32_t *__restrict__ sym_bin, int32_t *__restrict__ sym_list, uint64_t *__restrict__ status,
-    int64_t nstatus, DevCounters *__restrict__ ctr, PublishedCounts *__restrict__ hout,
+    FlopArgs a, int64_t ncols_tiles, int64_t nchunks, PublishedCounts *__restrict__ hout,
     unsigned int *__restrict__ hready, int64_t k, const int64_t *__restrict__ Acolptr,
     const int32_t *__restrict__ Arowidx, const V *__restrict__ Avals,
+    const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr,
     int32_t *__restrict__ At_rowidx, V *__restrict__ At_vals) {
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = blockIdx.x, nflop = ncols_tiles + nchunks;
     if (blk < nflop) {
-        flop_bin_tile<S>(blk, nflop, n, Bcolptr, Browidx, map, At_colptr, th, tstart, tlen,
-                         col_slot, flop, sym_bin, sym_list, status, nstatus, ctr, hout, hready);
+        if (blk < ncols_tiles) flop_column_tile<S>(blk, ncols_tiles, a);
+        else flop_long_chunk<S>(blk - ncols_tiles, a);
+        __shared__ int s_last;
+        publish_when_last(&a.ctr->tickets[kTkFlopDone], (unsigned long long)nflop, a.ctr, hout,
+                          hready, &s_last);
     } else {
         __shared__ GatherStage st;
         gather_tile<V, true>(blk - nflop, Acolptr, Arowidx, Avals, map, At_colptr, k, At_rowidx,
@@ -429,6 +518,87 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     publish_when_last(&ctr->tickets[kTkColptrDone], gridDim.x, ctr, hout, hready, &s_last);
 }
 
+// The same scan and binning by one workgroup, for B_i with at most
+// kSmallScanCols columns: no tile tickets, no look-back and no global atomics
+// on the bin counters.  Chunks of kSmallScanThreads * kSmallScanItems
+// columns follow one another, the running total and each bin's list length
+// carried over; the counters the host needs are then published as by the
+// tiled scan's last workgroup.
+constexpr int kSmallScanThreads = 1024;
+constexpr int kSmallScanItems = 4;
+constexpr int64_t kSmallScanCols = 2 * kSmallScanThreads * kSmallScanItems;
+__global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
+    int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
+    int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
+    DevCounters *__restrict__ ctr, PublishedCounts *__restrict__ hout,
+    unsigned int *__restrict__ hready) {
+    constexpr int CH = kSmallScanThreads * kSmallScanItems;
+    __shared__ long long s_tmp64[kSmallScanThreads / kWave + 1];
+    __shared__ int s_cnt[kNumBins];   // this chunk's columns per bin
+    __shared__ int s_base[kNumBins];  // list entries of the earlier chunks per bin
+    const int tid = threadIdx.x;
+    if (tid < kNumBins) s_base[tid] = 0;
+    long long carry = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += CH) {
+        if (tid < kNumBins) s_cnt[tid] = 0;
+        __syncthreads();
+        long long cnt[kSmallScanItems];
+        int bin[kSmallScanItems], lpos[kSmallScanItems];
+        long long sum = 0;
+#pragma unroll
+        for (int i = 0; i < kSmallScanItems; ++i) {
+            const int64_t j = j0 + (int64_t)tid * kSmallScanItems + i;
+            cnt[i] = 0;
+            bin[i] = kBinEmpty;
+            lpos[i] = 0;
+            if (j < n) {
+                const long long f = flop[j];
+                cnt[i] = f == 0 ? 0 : Ccolptr[j];  // empty columns have no count
+                int b = num_bin_of(f, cnt[i], th);
+                if (b == kBinDense && th.dense_first_flop > 0 && f >= th.dense_first_flop)
+                    b = kBinDenseFirst;
+                num_bin[j] = b;
+                bin[i] = b;
+                if (b != kBinEmpty) lpos[i] = atomicAdd(&s_cnt[b], 1);
+            }
+            sum += cnt[i];
+        }
+        long long total;
+        // ends with a barrier: s_cnt is complete
+        long long run = carry + group_excl_scan64<kSmallScanThreads>(sum, s_tmp64, &total);
+#pragma unroll
+        for (int i = 0; i < kSmallScanItems; ++i) {
+            const int64_t j = j0 + (int64_t)tid * kSmallScanItems + i;
+            if (j < n) {
+                Ccolptr[j] = run;
+                if (bin[i] != kBinEmpty)
+                    num_list[(int64_t)bin[i] * n + s_base[bin[i]] + lpos[i]] = (int32_t)j;
+            }
+            run += cnt[i];
+        }
+        carry += total;
+        __syncthreads();  // every thread has read s_base
+        if (tid < kNumBins) s_base[tid] += s_cnt[tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Ccolptr[n] = carry;
+        ctr->nnzC = carry;
+        hout->flops = ctr->flops.v;
+        hout->nnzC = carry;
+    }
+    if (tid < kNumBins) {
+        ctr->num_count[tid].v = s_base[tid];
+        hout->num_count[tid] = s_base[tid];
+        hout->sym_count[tid] = ctr->sym_count[tid].v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence_system();
+        __hip_atomic_store(hready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // Clears what one symbolic phase accumulates (the colptr scan's ticket and
 // tile states, nnzC and the numeric bin counters), for a second symbolic
 // run on one plan.  The flops and symbolic bins come from the plan.
@@ -457,17 +627,20 @@ int launch_symbolic_reset(Plan &p) {
 template <int S, typename V>
 static int flop_bin_gather_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
-    const int64_t nflop = (p.n + COLS - 1) / COLS;
+    const int64_t ntiles = (p.n + COLS - 1) / COLS;
+    const int64_t nchunks = p.n > 0 ? (p.nnzB + kLongChunk - 1) / kLongChunk : 0;
     const int64_t ngather = p.nnzA > 0 ? (p.k + kGatherCols - 1) / kGatherCols : 0;
-    if (nflop + ngather == 0) return SPGEMM_OK;
-    hipLaunchKernelGGL((k_flop_bin_gather<S, V>), dim3((unsigned)(nflop + ngather)),
-                       dim3(kFlopThreads), 0, p.stream, nflop, p.n, p.Bcolptr, p.Browidx, p.map,
-                       p.At_colptr, p.th, p.tstart, p.tlen, p.col_slot, p.flop, p.sym_bin,
-                       p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr, p.hpub_dev,
+    if (ntiles + nchunks + ngather == 0) return SPGEMM_OK;
+    const FlopArgs a{p.n,         p.nnzB,   p.Bcolptr, p.Browidx,  p.col_start, p.col_len,
+                     p.th,        p.tstart, p.tlen,    p.col_slot, p.flop,      p.arrive,
+                     p.sym_bin,   p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr};
+    hipLaunchKernelGGL((k_flop_bin_gather<S, V>), dim3((unsigned)(ntiles + nchunks + ngather)),
+                       dim3(kFlopThreads), 0, p.stream, a, ntiles, nchunks, p.hpub_dev,
                        p.hflags_dev + kFlagCounts, p.k, p.Acolptr, p.Arowidx,
-                       (const V *)p.Avals, p.At_rowidx, (V *)p.At_vals);
-    SPG_LAUNCHED("k_flop_bin_gather (" + std::to_string(nflop) + " flop tiles, " +
-                 std::to_string(ngather) + " gather tiles)");
+                       (const V *)p.Avals, p.map, p.At_colptr, p.At_rowidx, (V *)p.At_vals);
+    SPG_LAUNCHED("k_flop_bin_gather (" + std::to_string(ntiles) + " column tiles, " +
+                 std::to_string(nchunks) + " chunks, " + std::to_string(ngather) +
+                 " gather tiles)");
     return SPGEMM_OK;
 }
 
@@ -539,6 +712,13 @@ int launch_symbolic_bins(Plan &p) {
 
 int launch_colptr_scan(Plan &p) {
     if (p.n == 0) return SPGEMM_OK;
+    if (p.n <= kSmallScanCols) {
+        hipLaunchKernelGGL(k_colptr_scan_small, dim3(1), dim3(kSmallScanThreads), 0, p.stream, p.n,
+                           p.C_colptr, p.flop, p.th, p.num_bin, p.num_list, p.ctr, p.hpub_dev,
+                           p.hflags_dev + kFlagColptr);
+        SPG_HIP(hipGetLastError());
+        return SPGEMM_OK;
+    }
     hipLaunchKernelGGL(k_colptr_scan, dim3((unsigned)p.n_col_tiles), dim3(kScanThreads), 0,
                        p.stream, p.n, p.C_colptr, p.flop, p.th, p.num_bin, p.num_list,
                        p.st_colptr, p.n_col_tiles, p.ctr, p.hpub_dev,

@@ -94,6 +94,48 @@ def test_random_small_shapes(seed):
     check_local(A, Bi, offs, b)
 
 
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 20011])
+def test_colptr_scan_one_workgroup_and_tiled(n):
+    # up to 8192 columns of B_i one workgroup scans and bins them all; above,
+    # tiles of 1024 columns with a look-back (20011: 20 tiles and a ragged one)
+    rng = np.random.default_rng(n)
+    A = rand_csc(rng, 3000, 500, 0.01)
+    Bi = rand_csc(rng, 500, n, 0.01, empty_cols=(0, n - 1))
+    st, _, nbin = check_local(A, Bi, synth.partition_offsets(500, 4), 16)
+    assert int((nbin == 0).sum()) >= 2  # empty columns stay out of every list
+    for b in range(1, 8):
+        assert st["num_bins"][b] == int((nbin == b).sum())
+
+
+def _with_long_columns(rng, k, n, base, longs):
+    """B_i (k x n): `base` random entries per column, and columns j of
+    `longs` = {j: length} with that many distinct random rows."""
+    rows, cols = [], []
+    for j in range(n):
+        cnt = longs.get(j, base)
+        r = rng.choice(k, size=min(cnt, k), replace=False)
+        rows.append(r)
+        cols.append(np.full(r.size, j))
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    return synth.from_triplets(k, n, r, c, rng.uniform(-1.0, 1.0, r.size))
+
+
+@pytest.mark.parametrize("case", ["wide_lanes", "one_lane"])
+def test_long_columns_split_over_chunks(case):
+    # columns longer than 16 entries per lane are walked in chunks of 8192
+    # entries of B_i by several workgroups; the chunk that completes a
+    # column bins it (30000 entries: five chunks; 8192: a chunk boundary
+    # inside; 17 entries with one lane per column: just over the limit)
+    rng = np.random.default_rng(31 if case == "wide_lanes" else 32)
+    k = 40000
+    A = rand_csc(rng, 300, k, 2.0 / 300)
+    if case == "wide_lanes":
+        Bi = _with_long_columns(rng, k, 50, 3, {7: 30000, 8: 8192, 49: 300})
+    else:
+        Bi = _with_long_columns(rng, k, 20000, 1, {0: 17, 5: 5000, 19999: 4000})
+    check_local(A, Bi, synth.partition_offsets(k, 8), 64)
+
+
 @pytest.mark.parametrize("case", ["emptyB", "one_row", "one_col", "P_equals_k", "all_empty_A"])
 def test_edge_cases(case):
     rng = np.random.default_rng(7)
