@@ -44,22 +44,6 @@ __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const
     }
 }
 
-// Records where entry q of B_i finds its products in A~ (the column of A~
-// that map assigns to q's row, kept per row in col_start, col_len) and
-// returns their number.
-__device__ __forceinline__ int term_range(int64_t q, const int32_t *__restrict__ Browidx,
-                                          const int64_t *__restrict__ col_start,
-                                          const int32_t *__restrict__ col_len,
-                                          int64_t *__restrict__ tstart,
-                                          int32_t *__restrict__ tlen) {
-    const int32_t r = Browidx[q];
-    const long long start = col_start[r];
-    const int len = col_len[r];
-    tstart[q] = start;
-    tlen[q] = len;
-    return len;
-}
-
 // Sparse flops of every column of B_i and its symbolic bin, and the term
 // range of every entry of B_i.  Column tiles: S lanes walk one column (S
 // picked from the average column length).  A column with more than 16*S
@@ -89,12 +73,19 @@ struct FlopArgs {
     DevCounters *ctr;
 };
 
+// A column tile: `rounds` groups of kFlopThreads / S columns, one after
+// the other, then one reservation per bin in the global lists for all of
+// them.  Atomics on one address from every workgroup of a large launch
+// serialise across the chip, so a launch over many columns gives each tile
+// several rounds rather than running more tiles.
+constexpr int kFlopTileCols = 1024;  // most columns one tile takes
 template <int S>
-__device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups,
+__device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups, int rounds,
                                                  const FlopArgs &a) {
     constexpr int COLS = kFlopThreads / S;
-    __shared__ int s_bin[COLS];
-    __shared__ int s_lpos[COLS];
+    static_assert(kFlopTileCols % COLS == 0, "whole rounds");
+    static_assert(kNumBins <= 16 && kFlopTileCols < (1 << 24), "bin and position share an int");
+    __shared__ int s_bl[kFlopTileCols];  // bin << 24 | place among the tile's columns of that bin
     __shared__ long long s_f[COLS];
     __shared__ int s_cnt[kNumBins];
     __shared__ int s_base[kNumBins];
@@ -106,41 +97,76 @@ __device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups,
     }
     if (tid < kNumBins) s_cnt[tid] = 0;
     if (tid == 0) s_flops = 0;
-    __syncthreads();
-    const int64_t j0 = blk * COLS;
-    const int nloc = (int)min<int64_t>(COLS, a.n - j0);
+    const int64_t jt = blk * (int64_t)rounds * COLS;
+    const int ntile = (int)min<int64_t>((int64_t)rounds * COLS, a.n - jt);
     const int lc = tid / S, sub = tid % S;
-    long long acc = 0;
-    bool is_long = false;
-    if (lc < nloc) {
-        const int64_t q0 = a.Bcolptr[j0 + lc], q1 = a.Bcolptr[j0 + lc + 1];
-        is_long = q1 - q0 > 16 * S;
-        if (!is_long) {
-#pragma unroll 4
-            for (int64_t q = q0 + sub; q < q1; q += S)
-                acc += term_range(q, a.Browidx, a.col_start, a.col_len, a.tstart, a.tlen);
+    for (int rd = 0; rd * COLS < ntile; ++rd) {
+        __syncthreads();  // s_f of the previous round is consumed
+        const int64_t j0 = jt + (int64_t)rd * COLS;
+        const int nloc = min(COLS, ntile - rd * COLS);
+        long long acc = 0;
+        bool is_long = false;
+        if (lc < nloc) {
+            const int64_t q0 = a.Bcolptr[j0 + lc], q1 = a.Bcolptr[j0 + lc + 1];
+            is_long = q1 - q0 > 16 * S;
+            if (!is_long) {
+                // rounds of four entries per lane, loaded without branches
+                // (past the end: the column's last entry again, discarded),
+                // so a round's loads of one kind are in flight together
+                constexpr int U = 4;
+                for (int64_t qb = q0 + sub; qb < q1; qb += U * S) {
+                    int32_t r[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) r[u] = a.Browidx[min(qb + u * S, q1 - 1)];
+                    long long st[U];
+                    int len[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        st[u] = a.col_start[r[u]];
+                        len[u] = a.col_len[r[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int64_t q = qb + u * S;
+                        if (q < q1) {
+                            a.tstart[q] = st[u];
+                            a.tlen[q] = len[u];
+                            acc += len[u];
+                        }
+                    }
+                }
+            }
         }
-    }
-    acc = wave_sum<S>(acc);
-    if (lc < nloc && sub == 0) s_f[lc] = is_long ? -1 : acc;
-    __syncthreads();
-    if (tid < nloc) {
-        const int64_t j = j0 + tid;
-        const long long f = s_f[tid];
-        a.col_slot[j] = -1;
-        int b = kBinEmpty;
-        if (f >= 0) {  // a long column is binned by the chunk that completes it
-            a.flop[j] = f;
-            b = sym_bin_of(f, a.th);
-            a.sym_bin[j] = b;
-            if (f) atomic_add_i64(&s_flops, f);
+        acc = wave_sum<S>(acc);
+        if (lc < nloc && sub == 0) s_f[lc] = is_long ? -1 : acc;
+        __syncthreads();
+        if (tid < nloc) {
+            const int64_t j = j0 + tid;
+            const long long f = s_f[tid];
+            a.col_slot[j] = -1;
+            int code = kBinEmpty << 24;
+            if (f >= 0) {  // a long column is binned by the chunk that completes it
+                a.flop[j] = f;
+                const int b = sym_bin_of(f, a.th);
+                a.sym_bin[j] = b;
+                if (f) atomic_add_i64(&s_flops, f);
+                if (b != kBinEmpty) code = (b << 24) | atomicAdd(&s_cnt[b], 1);
+            }
+            s_bl[rd * COLS + tid] = code;
         }
-        s_bin[tid] = b;
-        s_lpos[tid] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
     }
     __syncthreads();
     if (tid == 0 && s_flops) atomic_add_i64(&a.ctr->flops.v, s_flops);
-    append_to_bins(nloc, s_bin, s_lpos, s_cnt, s_base, j0, a.ctr->sym_count, a.sym_list, a.n);
+    if (tid < kNumBins) {
+        const int c = s_cnt[tid];
+        s_base[tid] = c ? atomicAdd(&a.ctr->sym_count[tid].v, c) : 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < ntile; i += kFlopThreads) {
+        const int b = s_bl[i] >> 24;
+        if (b != kBinEmpty)
+            a.sym_list[(int64_t)b * a.n + s_base[b] + (s_bl[i] & 0xFFFFFF)] = (int32_t)(jt + i);
+    }
 }
 
 // Chunk c of B_i's entries, [c*kLongChunk, min((c+1)*kLongChunk, nnzB)):
@@ -256,8 +282,22 @@ __device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
     }
     __syncthreads();
     // one thread per listed column: its flops so far, then the arrival; the
-    // chunk that completes the column bins it
-    for (int i = tid; i < nl; i += kFlopThreads) {
+    // chunk that completes a column bins it, the chunk's completed columns
+    // taking one reservation per bin in the global lists
+    __shared__ int s_cnt[kNumBins];
+    __shared__ int s_base[kNumBins];
+    __shared__ long long s_flops;
+    if (tid < kNumBins) s_cnt[tid] = 0;
+    if (tid == 0) s_flops = 0;
+    __syncthreads();
+    constexpr int kPer = kLongList / kFlopThreads;
+    int mybin[kPer], mypos[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int i = tid + t * kFlopThreads;
+        mybin[t] = kBinEmpty;
+        mypos[t] = 0;
+        if (i >= nl) continue;
         const int64_t jc = s_col[i];
         const int64_t q0 = a.Bcolptr[jc], q1 = a.Bcolptr[jc + 1];
         if (s_part[i]) atomic_add_i64(reinterpret_cast<long long *>(a.flop + jc), s_part[i]);
@@ -269,11 +309,25 @@ __device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
                 __hip_atomic_load(a.flop + jc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int b = sym_bin_of(f, a.th);
             a.sym_bin[jc] = b;
-            if (b != kBinEmpty)
-                a.sym_list[(int64_t)b * a.n + atomicAdd(&a.ctr->sym_count[b].v, 1)] = (int32_t)jc;
-            if (f) atomic_add_i64(&a.ctr->flops.v, f);
+            if (f) atomic_add_i64(&s_flops, f);
+            if (b != kBinEmpty) {
+                mybin[t] = b;
+                mypos[t] = atomicAdd(&s_cnt[b], 1);
+            }
         }
     }
+    __syncthreads();
+    if (tid == 0 && s_flops) atomic_add_i64(&a.ctr->flops.v, s_flops);
+    if (tid < kNumBins) {
+        const int c = s_cnt[tid];
+        s_base[tid] = c ? atomicAdd(&a.ctr->sym_count[tid].v, c) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPer; ++t)
+        if (mybin[t] != kBinEmpty)
+            a.sym_list[(int64_t)mybin[t] * a.n + s_base[mybin[t]] + mypos[t]] =
+                s_col[tid + t * kFlopThreads];
 }
 
 // One launch for two independent steps that both follow the selection: the
@@ -285,14 +339,15 @@ __device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
 static_assert(kFlopThreads == kGatherThreads, "all tiles use the whole workgroup");
 template <int S, typename V>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
-    FlopArgs a, int64_t ncols_tiles, int64_t nchunks, PublishedCounts *__restrict__ hout,
+    FlopArgs a, int64_t ncols_tiles, int rounds, int64_t nchunks,
+    PublishedCounts *__restrict__ hout,
     unsigned int *__restrict__ hready, int64_t k, const int64_t *__restrict__ Acolptr,
     const int32_t *__restrict__ Arowidx, const V *__restrict__ Avals,
     const int32_t *__restrict__ map, const int64_t *__restrict__ At_colptr,
     int32_t *__restrict__ At_rowidx, V *__restrict__ At_vals) {
     const int64_t blk = blockIdx.x, nflop = ncols_tiles + nchunks;
     if (blk < nflop) {
-        if (blk < ncols_tiles) flop_column_tile<S>(blk, ncols_tiles, a);
+        if (blk < ncols_tiles) flop_column_tile<S>(blk, ncols_tiles, rounds, a);
         else flop_long_chunk<S>(blk - ncols_tiles, a);
         __shared__ int s_last;
         publish_when_last(&a.ctr->tickets[kTkFlopDone], (unsigned long long)nflop, a.ctr, hout,
@@ -627,7 +682,12 @@ int launch_symbolic_reset(Plan &p) {
 template <int S, typename V>
 static int flop_bin_gather_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
-    const int64_t ntiles = (p.n + COLS - 1) / COLS;
+    // about kFlopTiles tiles at most: several rounds per tile beyond that
+    constexpr int64_t kFlopTiles = 512;
+    const int64_t base = (p.n + COLS - 1) / COLS;
+    const int64_t want = std::max<int64_t>(1, (base + kFlopTiles - 1) / kFlopTiles);
+    const int rounds = (int)std::min<int64_t>(kFlopTileCols / COLS, want);
+    const int64_t ntiles = (base + rounds - 1) / rounds;
     const int64_t nchunks = p.n > 0 ? (p.nnzB + kLongChunk - 1) / kLongChunk : 0;
     const int64_t ngather = p.nnzA > 0 ? (p.k + kGatherCols - 1) / kGatherCols : 0;
     if (ntiles + nchunks + ngather == 0) return SPGEMM_OK;
@@ -635,7 +695,7 @@ static int flop_bin_gather_launch(Plan &p) {
                      p.th,        p.tstart, p.tlen,    p.col_slot, p.flop,      p.arrive,
                      p.sym_bin,   p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr};
     hipLaunchKernelGGL((k_flop_bin_gather<S, V>), dim3((unsigned)(ntiles + nchunks + ngather)),
-                       dim3(kFlopThreads), 0, p.stream, a, ntiles, nchunks, p.hpub_dev,
+                       dim3(kFlopThreads), 0, p.stream, a, ntiles, rounds, nchunks, p.hpub_dev,
                        p.hflags_dev + kFlagCounts, p.k, p.Acolptr, p.Arowidx,
                        (const V *)p.Avals, p.map, p.At_colptr, p.At_rowidx, (V *)p.At_vals);
     SPG_LAUNCHED("k_flop_bin_gather (" + std::to_string(ntiles) + " column tiles, " +
