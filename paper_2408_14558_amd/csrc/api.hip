@@ -295,44 +295,55 @@ static int check_tuning(const spgemm_tuning &t) {
     return SPGEMM_OK;
 }
 
-// Room for what the symbolic phase keeps for the numeric phase, in one
-// pooled block: the row bitmap of each of its dense columns (the numeric
-// phase loads it instead of walking the products again) and the sorted
-// product order of each tiny column (the numeric phase does not sort again).
-// Optional: a part that is too large, above workspace_limit, or not
-// allocatable is left out and the numeric phase recomputes it.
+// Room for what the symbolic phase keeps for the numeric phase, in two
+// pooled blocks: the sorted product order of each tiny column (the numeric
+// phase does not sort again) and the row bitmap of each dense column (the
+// numeric phase loads it instead of walking the products again).  Optional:
+// a part that is too large, above workspace_limit, or not allocatable is left
+// out and the numeric phase recomputes it.
 constexpr size_t kDenseBitsMax = size_t(8) << 30;
 
-static void reserve_kept(Plan &p) {
+// Makes *block hold at least `need` bytes (keeping it when it does); false
+// when it cannot.
+static bool reserve_block(Plan &p, void **block, size_t *bytes, size_t need) {
+    if (*bytes >= need) return true;
+    pool_put(*block, *bytes, false, p.device, p.stream);
+    *block = nullptr;
+    *bytes = 0;
+    void *ptr = nullptr;
+    size_t got = 0;
+    if (pool_get(need, false, p.device, p.stream, &ptr, &got) != SPGEMM_OK) {
+        (void)hipGetLastError();
+        return false;
+    }
+    *block = ptr;
+    *bytes = got;
+    return true;
+}
+
+static size_t kept_limit(const Plan &p) {
+    return p.tun.workspace_limit > 0 ? (size_t)p.tun.workspace_limit : SIZE_MAX;
+}
+
+// Tiny part for `cols` tiny columns: the kernels' 64*EMAX product slots, 2
+// bytes each.
+static void reserve_tiny(Plan &p, int64_t cols) {
+    const size_t slots = p.th.tiny_max_flop <= 256 ? 256 : 512;
+    size_t tiny = p.m < kPackedRowLimit ? (size_t)cols * slots * 2 : 0;
+    if (tiny > kDenseBitsMax || p.ws_bytes + tiny > kept_limit(p)) tiny = 0;
+    p.tiny_perm = nullptr;
+    if (tiny && reserve_block(p, &p.kept_tiny, &p.kept_tiny_bytes, tiny))
+        p.tiny_perm = (uint16_t *)p.kept_tiny;
+}
+
+static void reserve_dense(Plan &p) {
     const size_t nw = (size_t)((p.m + 31) / 32);
     size_t dense = (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
-    // tiny columns: the kernels' 64*EMAX product slots, 2 bytes each
-    const size_t slots = p.th.tiny_max_flop <= 256 ? 256 : 512;
-    size_t tiny = p.m < kPackedRowLimit ? (size_t)p.sym_count[kBinTiny] * slots * 2 : 0;
-    const size_t limit = p.tun.workspace_limit > 0 ? (size_t)p.tun.workspace_limit : SIZE_MAX;
-    if (dense > kDenseBitsMax || p.ws_bytes + dense > limit) dense = 0;
-    if (tiny > kDenseBitsMax || p.ws_bytes + dense + tiny > limit) tiny = 0;
-    const size_t dense_at = 0, tiny_at = (dense + 255) & ~(size_t)255;
-    const size_t need = tiny_at + tiny;
+    const size_t tiny = p.tiny_perm ? p.kept_tiny_bytes : 0;
+    if (dense > kDenseBitsMax || p.ws_bytes + tiny + dense > kept_limit(p)) dense = 0;
     p.dense_bits = nullptr;
-    p.tiny_perm = nullptr;
-    if (need == 0) return;
-    if (p.kept_bytes < need) {
-        pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
-        p.kept = nullptr;
-        p.kept_bytes = 0;
-        void *ptr = nullptr;
-        size_t got = 0;
-        if (pool_get(need, false, p.device, p.stream, &ptr, &got) != SPGEMM_OK) {
-            (void)hipGetLastError();
-            return;
-        }
-        p.kept = ptr;
-        p.kept_bytes = got;
-    }
-    char *k = (char *)p.kept;
-    if (dense) p.dense_bits = (uint32_t *)(k + dense_at);
-    if (tiny) p.tiny_perm = (uint16_t *)(k + tiny_at);
+    if (dense && reserve_block(p, &p.kept, &p.kept_bytes, dense))
+        p.dense_bits = (uint32_t *)p.kept;
 }
 
 static int sync_counters(Plan &p) {
@@ -708,14 +719,21 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     }
     // flops and symbolic bins came with the plan; a later run clears what the
     // previous symbolic run accumulated
+    bool early = false;
     if (p.symbolic_runs++ == 0) {
+        early = p.n <= kEarlyTinyCols && p.th.tiny_max_flop > 0;
+        if (early) {
+            reserve_tiny(p, p.n);
+            if ((rc = launch_sym_tiny(p, true))) return rc;
+        }
         SPG_HIP(wait_flag(p, kFlagCounts, [&] { return hipEventSynchronize(p.counts_ready); }));
         for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hpub->sym_count[b];
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;
     }
-    reserve_kept(p);
-    if ((rc = launch_symbolic_bins(p))) return rc;
+    if (!early) reserve_tiny(p, p.sym_count[kBinTiny]);
+    reserve_dense(p);
+    if ((rc = launch_symbolic_bins(p, early))) return rc;
     __atomic_store_n(p.hflags + kFlagColptr, 0u, __ATOMIC_RELEASE);
     if ((rc = launch_colptr_scan(p))) return rc;  // publishes its counters to hpub
     SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
@@ -769,6 +787,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     // counts_ready follows (later copies were waited for on the host)
     pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream, p.counts_ready);
     pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
+    pool_put(p.kept_tiny, p.kept_tiny_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;
 }

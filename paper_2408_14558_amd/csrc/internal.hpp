@@ -190,10 +190,12 @@ struct Plan {
     int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
     // What the symbolic phase keeps for the numeric phase, per column: its
     // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
-    int32_t *col_slot = nullptr;
-    int32_t *arrive = nullptr;    // n: chunks of the flops pass done per long column    // n
-    void *kept = nullptr;           // pooled block holding the two parts below
+    int32_t *col_slot = nullptr;  // n
+    int32_t *arrive = nullptr;    // n: chunks of the flops pass done per long column
+    void *kept = nullptr;           // pooled block holding dense_bits
     size_t kept_bytes = 0;
+    void *kept_tiny = nullptr;      // pooled block holding tiny_perm
+    size_t kept_tiny_bytes = 0;
     uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns
     uint16_t *tiny_perm = nullptr;  // sorted order of the terms of tiny columns
     int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
@@ -259,7 +261,13 @@ int launch_plan_kernels(Plan &p);
 int launch_gather_values(Plan &p, const void *Avals);
 int launch_export_blocks(Plan &p, int64_t *blocks);
 int launch_flop_bin_gather(Plan &p);
-int launch_symbolic_bins(Plan &p);
+// B_i with at most kEarlyTinyCols columns: the tiny symbolic kernel is
+// launched before the host has the bin counts (sized for every column, the
+// count read on the device), so it follows the flops pass without the
+// host's round trip in between.
+constexpr int64_t kEarlyTinyCols = 16384;
+int launch_sym_tiny(Plan &p, bool early);
+int launch_symbolic_bins(Plan &p, bool tiny_launched);
 int launch_colptr_scan(Plan &p);
 int launch_symbolic_reset(Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);

@@ -397,8 +397,13 @@ __device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1, TermRange 
     return wave_sum(nh);
 }
 
+// count_dev NULL: `count` columns, in `list` (NULL: every column is tiny).
+// count_dev set (a launch before the host has the counts, sized for n
+// columns): the count is read there, and the list is used unless it holds
+// every column.
 template <int EMAX>
 __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ list, int count,
+                                                  const int *__restrict__ count_dev, int n,
                                                   const int64_t *__restrict__ Bcolptr,
                                                   TermRange tr,
                                                   const int32_t *__restrict__ At_rowidx,
@@ -407,6 +412,10 @@ __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ li
                                                   uint16_t *__restrict__ tiny_perm,
                                                   int32_t *__restrict__ col_slot) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (count_dev) {
+        count = *count_dev;
+        if (count == n) list = nullptr;
+    }
     if (w >= count) return;  // whole wave leaves together
     const int32_t j = list ? list[w] : w;  // NULL list: every column is tiny
     const int64_t q0 = Bcolptr[j], q1 = Bcolptr[j + 1], f = flop[j];
@@ -732,24 +741,32 @@ static int sym_hash_launch(Plan &p, int bin) {
 }
 
 
-int launch_symbolic_bins(Plan &p) {
+// early: launched before the host has the bin counts; sized for every
+// column, the count read from the device counters.
+int launch_sym_tiny(Plan &p, bool early) {
+    const int64_t cols = early ? p.n : p.sym_count[kBinTiny];
+    if (cols <= 0) return SPGEMM_OK;
+    const unsigned g = (unsigned)((cols + 3) / 4);
+    // the bin holds every column: the kernel takes column w directly
+    const int32_t *list = p.sym_list + (int64_t)kBinTiny * p.n;
+    if (!early && cols == p.n) list = nullptr;
+    const int *count_dev = early ? &p.ctr->sym_count[kBinTiny].v : nullptr;
+    if (p.th.tiny_max_flop <= 4 * kWave)
+        hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream, list, (int)cols,
+                           count_dev, (int)p.n, p.Bcolptr, p.term_range(), p.At_rowidx, p.flop,
+                           p.C_colptr, p.tiny_perm, p.col_slot);
+    else
+        hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream, list, (int)cols,
+                           count_dev, (int)p.n, p.Bcolptr, p.term_range(), p.At_rowidx, p.flop,
+                           p.C_colptr, p.tiny_perm, p.col_slot);
+    SPG_LAUNCHED(early ? "k_sym_tiny (before the counts)" : "k_sym_tiny");
+    return SPGEMM_OK;
+}
+
+int launch_symbolic_bins(Plan &p, bool tiny_launched) {
     if (p.n == 0) return SPGEMM_OK;
-    if (p.sym_count[kBinTiny] > 0) {
-        const unsigned g = (unsigned)((p.sym_count[kBinTiny] + 3) / 4);
-        // the bin holds every column: the kernel takes column w directly
-        const int32_t *list =
-            p.sym_count[kBinTiny] == p.n ? nullptr : p.sym_list + (int64_t)kBinTiny * p.n;
-        if (p.th.tiny_max_flop <= 4 * kWave)
-            hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream, list,
-                               p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
-                               p.flop, p.C_colptr, p.tiny_perm, p.col_slot);
-        else
-            hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream, list,
-                               p.sym_count[kBinTiny], p.Bcolptr, p.term_range(), p.At_rowidx,
-                               p.flop, p.C_colptr, p.tiny_perm, p.col_slot);
-        SPG_LAUNCHED("k_sym_tiny");
-    }
     int rc;
+    if (!tiny_launched && (rc = launch_sym_tiny(p, false))) return rc;
     if ((rc = sym_hash_launch<kSymTable[0], 64>(p, kBinH0))) return rc;
     if ((rc = sym_hash_launch<kSymTable[1], 64>(p, kBinH1))) return rc;
     if ((rc = sym_hash_launch<kSymTable[2], 256>(p, kBinH2))) return rc;
