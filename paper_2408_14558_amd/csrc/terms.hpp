@@ -463,35 +463,36 @@ __device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     if ((r & jj) == 0) {
-                        const int i = lane * E + r;
-                        const bool up = (i & kk) == 0;
+                        // ascending pair unless bit kk of the element index is set
+                        const bool up = kk < E ? (r & kk) == 0 : ((lane * E) & kk) == 0;
                         const int a = key[r], b = key[r ^ jj];
-                        if ((a > b) == up) {
-                            key[r] = b;
-                            key[r ^ jj] = a;
-                            if constexpr (kVals) {
-                                const V t = val[r];
-                                val[r] = val[r ^ jj];
-                                val[r ^ jj] = t;
-                            }
+                        const int lo = min(a, b), hi = max(a, b);
+                        if constexpr (kVals) {
+                            const bool sw = (a > b) == up;
+                            const V va = val[r], vb = val[r ^ jj];
+                            val[r] = sw ? vb : va;
+                            val[r ^ jj] = sw ? va : vb;
                         }
+                        key[r] = up ? lo : hi;
+                        key[r ^ jj] = up ? hi : lo;
                     }
                 }
             } else {
+                // partner in lane ^ (jj / E); both bits depend on the lane
+                // alone, so one direction serves the lane's E elements
                 const int ld = jj / E;
+                const bool up = ((lane * E) & kk) == 0;
+                const bool lower = ((lane * E) & jj) == 0;
+                const bool keep_min = lower == up;
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
-                    const int i = lane * E + r;
                     const int ok = __shfl_xor(key[r], ld);
-                    V ov = V(0);
-                    if constexpr (kVals) ov = __shfl_xor(val[r], ld);
-                    const bool up = (i & kk) == 0;
-                    const bool lower = (i & jj) == 0;
-                    const bool take = (lower == up) ? (ok < key[r]) : (ok > key[r]);
-                    if (take) {
-                        key[r] = ok;
-                        if constexpr (kVals) val[r] = ov;
+                    if constexpr (kVals) {
+                        const V ov = __shfl_xor(val[r], ld);
+                        const bool take = keep_min ? (ok < key[r]) : (ok > key[r]);
+                        val[r] = take ? ov : val[r];
                     }
+                    key[r] = keep_min ? min(key[r], ok) : max(key[r], ok);
                 }
             }
         }
