@@ -58,38 +58,57 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
     V val[E];
     if (perm) {
         // the symbolic phase kept the sorted order of the slots: rows and
-        // values wait in LDS by slot and are read back in that order
+        // values wait in LDS by slot and are read back in that order.  Every
+        // slot loads and parks (an empty one reads A~'s entry 0, and the kept
+        // order never names it), so the loads carry no branches and are in
+        // flight together.
+        int32_t rw[E];
+        V av[E];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            if (p[r] >= 0) {
-                const int slot = r * kWave + lane;
-                s_rows[slot] = a.At_rowidx[p[r]];
-                s_vals[slot] = a.At_vals[p[r]] * bv[r];
-            }
+            const int64_t q = p[r] >= 0 ? p[r] : 0;
+            rw[r] = a.At_rowidx[q];
+            av[r] = a.At_vals[q];
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int slot = r * kWave + lane;
+            s_rows[slot] = rw[r];
+            s_vals[slot] = av[r] * bv[r];
         }
         wave_sync();
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            key[r] = sl[r] != kNoSlot ? s_rows[sl[r]] : kNoRow;
-            val[r] = sl[r] != kNoSlot ? s_vals[sl[r]] : V(0);
+            const bool some = sl[r] != kNoSlot;
+            const int at = some ? sl[r] : 0;
+            const int rr = s_rows[at];
+            const V vv = s_vals[at];
+            key[r] = some ? rr : kNoRow;
+            val[r] = some ? vv : V(0);
         }
         wave_sync();  // every slot is read before the buffers are reused below
     } else {
+    // loads without branches, as above
+    int32_t rw[E];
+    V av[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int64_t q = p[r] >= 0 ? p[r] : 0;
+        rw[r] = a.At_rowidx[q];
+        av[r] = a.At_vals[q];
+    }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         key[r] = kNoRow;
         val[r] = V(0);
-        if (p[r] >= 0) {
-            const int32_t row = a.At_rowidx[p[r]];
-            const V v = a.At_vals[p[r]] * bv[r];
-            if constexpr (kPacked) {
-                const int slot = r * kWave + lane;
-                key[r] = (row << kSlotBits) | slot;
-                s_vals[slot] = v;
-            } else {
-                key[r] = row;
-                val[r] = v;
-            }
+        const V v = av[r] * bv[r];
+        if constexpr (kPacked) {
+            const int slot = r * kWave + lane;
+            s_vals[slot] = v;
+            if (p[r] >= 0) key[r] = (rw[r] << kSlotBits) | slot;
+        } else if (p[r] >= 0) {
+            key[r] = rw[r];
+            val[r] = v;
         }
     }
     if constexpr (kPacked) {

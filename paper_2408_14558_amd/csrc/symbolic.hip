@@ -371,12 +371,16 @@ __device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1, TermRange 
     float bv[E];
     wave_terms<E, float>(q0, q1, tr, nullptr, p, bv);
     const int lane = lane_id();
+    // loads without branches (an empty slot reads A~'s entry 0 and drops
+    // it), so they are in flight together
+    int32_t rw[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) rw[r] = At_rowidx[p[r] >= 0 ? p[r] : 0];
     int key[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         key[r] = kNoRow;
-        if (p[r] >= 0)
-            key[r] = perm ? (At_rowidx[p[r]] << kSlotBits) | (r * kWave + lane) : At_rowidx[p[r]];
+        if (p[r] >= 0) key[r] = perm ? (rw[r] << kSlotBits) | (r * kWave + lane) : rw[r];
     }
     wave_sort<E, false, float>(key, bv);
     if (perm) {
