@@ -66,17 +66,24 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
     const long long t = take_ticket(&ctr->tickets[kTkRank], &s_ticket);
     const RankTile d = tiles[t];
     const int tid = threadIdx.x;
+    // every item loads (past the tile's end: its last column again, not
+    // counted), so the loads carry no branches and are in flight together
+    int64_t a0[kScanItems], a1[kScanItems];
+    int hh[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t c = d.col0 + min(tid * kScanItems + i, d.ncols - 1);
+        a0[i] = Acolptr[c];
+        a1[i] = Acolptr[c + 1];
+        hh[i] = H[c];
+    }
     int nz[kScanItems];
     int cnt = 0, hcnt = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const int off = tid * kScanItems + i;
-        nz[i] = 0;
-        if (off < d.ncols) {
-            const int64_t c = d.col0 + off;
-            nz[i] = Acolptr[c + 1] > Acolptr[c] ? 1 : 0;
-            hcnt += H[c];
-        }
+        const bool in = tid * kScanItems + i < d.ncols;
+        nz[i] = in && a1[i] > a0[i] ? 1 : 0;
+        hcnt += in ? hh[i] : 0;
         cnt += nz[i];
     }
     int total;
@@ -97,7 +104,7 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
         if (nz[i]) {
             const int64_t g = base + rank / b;
             gid[c] = (int32_t)g;
-            if (H[c] || d.part == own_whole) hit[g] = 1;
+            if (hh[i] || d.part == own_whole) hit[g] = 1;
             const long long r = rank % b;
             if (r == 0) gfirst[g] = (int32_t)c;
             if (r == b - 1 || rank == part_last) glast[g] = (int32_t)c;
@@ -134,6 +141,24 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
     const long long t = take_ticket(&ctr->tickets[kTkSelect], &s_ticket);
     const int tid = threadIdx.x;
     const int64_t c0 = t * kScanTile + (int64_t)tid * kScanItems;
+    // every item loads (past the end: A's last column, a group id of -1:
+    // group 0; neither counted), so the loads carry no branches and each
+    // kind is in flight together
+    int32_t g[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) g[i] = gid[min(c0 + i, k - 1)];
+    int hv[kScanItems];
+    int32_t gf[kScanItems];
+    int64_t a0[kScanItems], a1[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t cc = min(c0 + i, k - 1);
+        const int32_t gg = g[i] >= 0 ? g[i] : 0;
+        hv[i] = hit[gg];
+        gf[i] = gfirst[gg];
+        a0[i] = Acolptr[cc];
+        a1[i] = Acolptr[cc + 1];
+    }
     int sel[kScanItems];
     long long len[kScanItems];
     int cnt = 0, mcnt = 0;
@@ -141,16 +166,10 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t c = c0 + i;
-        sel[i] = 0;
-        len[i] = 0;
-        if (c < k) {
-            const int32_t g = gid[c];
-            if (g >= 0 && hit[g]) {
-                sel[i] = 1;
-                len[i] = Acolptr[c + 1] - Acolptr[c];
-                if (gfirst[g] == (int32_t)c) ++mcnt;
-            }
-        }
+        const bool s = c < k && g[i] >= 0 && hv[i];
+        sel[i] = s ? 1 : 0;
+        len[i] = s ? a1[i] - a0[i] : 0;
+        mcnt += s && gf[i] == (int32_t)c;
         cnt += sel[i];
         nnz += len[i];
     }

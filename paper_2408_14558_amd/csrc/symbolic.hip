@@ -545,6 +545,14 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     __syncthreads();
     const int64_t j0 = t * kScanTile;
     const int nloc = (int)min<int64_t>(kScanTile, n - j0);
+    // loads without branches (past the end: the tile's last column again)
+    long long fl[kScanItems], cc[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t j = j0 + min(tid * kScanItems + i, nloc - 1);
+        fl[i] = flop[j];
+        cc[i] = Ccolptr[j];
+    }
     long long cnt[kScanItems];
     long long sum = 0;
 #pragma unroll
@@ -553,9 +561,9 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
         cnt[i] = 0;
         if (lc < nloc) {
             const int64_t j = j0 + lc;
-            cnt[i] = flop[j] == 0 ? 0 : Ccolptr[j];  // empty columns have no count
-            int b = num_bin_of(flop[j], cnt[i], th);
-            if (b == kBinDense && th.dense_first_flop > 0 && flop[j] >= th.dense_first_flop)
+            cnt[i] = fl[i] == 0 ? 0 : cc[i];  // empty columns have no count
+            int b = num_bin_of(fl[i], cnt[i], th);
+            if (b == kBinDense && th.dense_first_flop > 0 && fl[i] >= th.dense_first_flop)
                 b = kBinDenseFirst;
             num_bin[j] = b;
             s_bin[lc] = b;
@@ -610,6 +618,14 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
     for (int64_t j0 = 0; j0 < n; j0 += CH) {
         if (tid < kNumBins) s_cnt[tid] = 0;
         __syncthreads();
+        // loads without branches (past the end: the last column again)
+        long long fl[kSmallScanItems], cc[kSmallScanItems];
+#pragma unroll
+        for (int i = 0; i < kSmallScanItems; ++i) {
+            const int64_t j = min(j0 + (int64_t)tid * kSmallScanItems + i, n - 1);
+            fl[i] = flop[j];
+            cc[i] = Ccolptr[j];
+        }
         long long cnt[kSmallScanItems];
         int bin[kSmallScanItems], lpos[kSmallScanItems];
         long long sum = 0;
@@ -620,8 +636,8 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
             bin[i] = kBinEmpty;
             lpos[i] = 0;
             if (j < n) {
-                const long long f = flop[j];
-                cnt[i] = f == 0 ? 0 : Ccolptr[j];  // empty columns have no count
+                const long long f = fl[i];
+                cnt[i] = f == 0 ? 0 : cc[i];  // empty columns have no count
                 int b = num_bin_of(f, cnt[i], th);
                 if (b == kBinDense && th.dense_first_flop > 0 && f >= th.dense_first_flop)
                     b = kBinDenseFirst;
