@@ -74,7 +74,7 @@ SIGNATURES = {
     "spgemm_version": (ctypes.c_char_p, []),
     "spgemm_default_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "spgemm_plan": (ctypes.c_int, [ctypes.POINTER(Csc), ctypes.POINTER(Csc), ctypes.c_int,
-                                   ctypes.POINTER(ctypes.c_int64), _i32, _i64,
+                                   _vp, _i32, _i64,
                                    ctypes.POINTER(Tuning), _vp, ctypes.POINTER(_vp)]),
     "spgemm_plan_set_stream": (ctypes.c_int, [_vp, _vp]),
     "spgemm_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),

@@ -52,9 +52,18 @@ class DeviceCsc:
         return cls(int(M.nrows), int(M.ncols), colptr, rowidx, vals)
 
     def c_struct(self) -> _lib.Csc:
-        return _lib.Csc(self.nrows, self.ncols, self.nnz, self.colptr.data_ptr(),
-                        self.rowidx.data_ptr() if self.nnz else None,
-                        self.vals.data_ptr() if (self.vals is not None and self.nnz) else None)
+        # kept while the shape and the arrays' addresses stay the same (a
+        # plan per step marshals the same matrices again)
+        nnz = self.rowidx.numel()
+        key = (self.nrows, self.ncols, nnz, self.colptr.data_ptr(), self.rowidx.data_ptr(),
+               None if self.vals is None else self.vals.data_ptr())
+        kept = self.__dict__.get("_c_struct")
+        if kept is not None and kept[0] == key:
+            return kept[1]
+        s = _lib.Csc(self.nrows, self.ncols, nnz, key[3], key[4] if nnz else None,
+                     key[5] if nnz else None)
+        self.__dict__["_c_struct"] = (key, s)
+        return s
 
     def to_host(self):
         v = None if self.vals is None else self.vals.cpu().numpy()
@@ -118,7 +127,7 @@ class Plan:
         a, b = A.c_struct(), Bi.c_struct()
         tun = ctypes.byref(tuning) if tuning is not None else None
         check(self.lib.spgemm_plan(ctypes.byref(a), ctypes.byref(b), self.dtype,
-                                   offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.P,
+                                   offs.ctypes.data, self.P,
                                    self.block_size, tun, _stream(stream), ctypes.byref(handle)),
               "spgemm_plan")
         self.handle = handle
