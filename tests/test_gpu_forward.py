@@ -136,6 +136,30 @@ def test_long_columns_split_over_chunks(case):
     check_local(A, Bi, synth.partition_offsets(k, 8), 64)
 
 
+@pytest.mark.parametrize("n", [16384, 16385])
+def test_tiny_symbolic_before_and_after_the_counts(n):
+    # up to 16384 columns the tiny symbolic kernel is launched before the
+    # host has the bin counts (count read on the device, bin list used since
+    # not every column is tiny); above, after them.  Both must agree with
+    # the oracle, and a second symbolic run (always after the counts) too.
+    rng = np.random.default_rng(n)
+    k = 2000
+    A = rand_csc(rng, 4000, k, 0.004)
+    Bi = _with_long_columns(rng, k, n, 2, {3: 400, 700: 900, n - 1: 1500})
+    offs = synth.partition_offsets(k, 4)
+    st, sbin, _ = check_local(A, Bi, offs, 32)
+    assert 0 < int((sbin == 1).sum()) < n  # tiny and other bins both present
+    ref = oracle.local_product(A, Bi, offs, 32)
+    Ad, Bd = _dev(A, torch.float64), _dev(Bi, torch.float64)
+    with spg.Plan(Ad, Bd, offs, 32) as p:
+        for _ in range(2):
+            colptr = p.symbolic()
+            assert np.array_equal(colptr.cpu().numpy(), ref.C.colptr)
+            rows, vals = p.numeric()
+            assert np.array_equal(rows.cpu().numpy(), ref.C.rowidx)
+            assert_values(vals.cpu().numpy(), ref.C.vals, ref.C.absvals, True)
+
+
 @pytest.mark.parametrize("case", ["emptyB", "one_row", "one_col", "P_equals_k", "all_empty_A"])
 def test_edge_cases(case):
     rng = np.random.default_rng(7)
