@@ -120,7 +120,7 @@ def _with_long_columns(rng, k, n, base, longs):
     return synth.from_triplets(k, n, r, c, rng.uniform(-1.0, 1.0, r.size))
 
 
-@pytest.mark.parametrize("case", ["wide_lanes", "one_lane"])
+@pytest.mark.parametrize("case", ["wide_lanes", "one_lane", "chunk_edges"])
 def test_long_columns_split_over_chunks(case):
     # columns longer than 16 entries per lane are walked in chunks of 8192
     # entries of B_i by several workgroups; the chunk that completes a
@@ -131,8 +131,14 @@ def test_long_columns_split_over_chunks(case):
     A = rand_csc(rng, 300, k, 2.0 / 300)
     if case == "wide_lanes":
         Bi = _with_long_columns(rng, k, 50, 3, {7: 30000, 8: 8192, 49: 300})
-    else:
+    elif case == "one_lane":
         Bi = _with_long_columns(rng, k, 20000, 1, {0: 17, 5: 5000, 19999: 4000})
+    else:
+        # entries [0, 8192): exactly chunk 0; [8192, 16383): inside chunk 1;
+        # a short column across the next edge; then a long column from
+        # chunk 2 into chunk 3 by one entry, an empty and a short column
+        Bi = _with_long_columns(rng, k, 6, 0, {0: 8192, 1: 8191, 2: 2, 3: 8192, 4: 0, 5: 7})
+        assert list(np.diff(Bi.colptr)) == [8192, 8191, 2, 8192, 0, 7]
     check_local(A, Bi, synth.partition_offsets(k, 8), 64)
 
 
