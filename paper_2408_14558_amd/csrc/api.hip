@@ -617,6 +617,9 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     // only: computed here, in one launch with the gather of A~, with their
     // counts on their way to the host by the time spgemm_symbolic needs them
     if (pl.n > 0) __atomic_store_n(pl.hflags + kFlagCounts, 0u, __ATOMIC_RELEASE);
+    // the first symbolic run launches the tiny kernel before it has the
+    // counts, and that launch publishes them
+    pl.early_tiny = pl.n > 0 && pl.n <= kEarlyTinyCols && pl.th.tiny_max_flop > 0;
     if ((rc = launch_flop_bin_gather(pl))) return cleanup(rc);
     if (pl.n > 0) {
         e = take_event(&pl.counts_ready);
@@ -721,12 +724,14 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     // previous symbolic run accumulated
     bool early = false;
     if (p.symbolic_runs++ == 0) {
-        early = p.n <= kEarlyTinyCols && p.th.tiny_max_flop > 0;
+        early = p.early_tiny;
         if (early) {
             reserve_tiny(p, p.n);
-            if ((rc = launch_sym_tiny(p, true))) return rc;
+            if ((rc = launch_sym_tiny(p, true))) return rc;  // publishes the counts
         }
-        SPG_HIP(wait_flag(p, kFlagCounts, [&] { return hipEventSynchronize(p.counts_ready); }));
+        SPG_HIP(wait_flag(p, kFlagCounts, [&] {
+            return early ? hipStreamSynchronize(p.stream) : hipEventSynchronize(p.counts_ready);
+        }));
         for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hpub->sym_count[b];
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;

@@ -209,13 +209,33 @@ __device__ __forceinline__ long long chained_prefix(uint64_t *status, long long 
     return prefix;
 }
 
+// Run by every thread of one workgroup once the counters are final: copies
+// the counters the host needs to `out` (pinned host memory), so no separate
+// device-to-host copy is needed, then sets *ready to 1 with a system-scope
+// release store: the host may read `out` as soon as it sees the flag.
+__device__ __forceinline__ void publish_counters(const DevCounters *ctr, PublishedCounts *out,
+                                                 unsigned int *ready) {
+    const int t = threadIdx.x;
+    if (t == 0)
+        out->flops = __hip_atomic_load(&ctr->flops.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (t == 1)
+        out->nnzC = __hip_atomic_load(&ctr->nnzC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (t < 2 + kNumBins)
+        out->sym_count[t - 2] = __hip_atomic_load(&ctr->sym_count[t - 2].v, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    else if (t < 2 + 2 * kNumBins)
+        out->num_count[t - 2 - kNumBins] = __hip_atomic_load(
+            &ctr->num_count[t - 2 - kNumBins].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (t == 0) {
+        __threadfence_system();
+        __hip_atomic_store(ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // Called by every thread of each of `groups` workgroups of a kernel, once,
 // after the workgroup's last update of the counters: the workgroup that
-// finishes last
-// copies the counters the host needs to `out` (pinned host memory), so
-// no separate device-to-host copy is needed, then sets *ready to 1 with a
-// system-scope release store: the host may read `out` as soon as it sees the
-// flag.  `done` counts the finished workgroups.
+// finishes last publishes them.  `done` counts the finished workgroups.
 __device__ __forceinline__ void publish_when_last(unsigned long long *done,
                                                   unsigned long long groups,
                                                   const DevCounters *ctr, PublishedCounts *out,
@@ -228,22 +248,7 @@ __device__ __forceinline__ void publish_when_last(unsigned long long *done,
     __syncthreads();
     if (*lds_flag) {
         __threadfence();  // every other workgroup's updates are visible
-        const int t = threadIdx.x;
-        if (t == 0)
-            out->flops = __hip_atomic_load(&ctr->flops.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (t == 1)
-            out->nnzC = __hip_atomic_load(&ctr->nnzC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (t < 2 + kNumBins)
-            out->sym_count[t - 2] = __hip_atomic_load(&ctr->sym_count[t - 2].v, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-        else if (t < 2 + 2 * kNumBins)
-            out->num_count[t - 2 - kNumBins] = __hip_atomic_load(
-                &ctr->num_count[t - 2 - kNumBins].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence_system();
-            __hip_atomic_store(ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        publish_counters(ctr, out, ready);
     }
 }
 

@@ -170,6 +170,7 @@ struct Plan {
     int32_t *colid = nullptr;
     // k: where column c of A sits in A~ (first entry, length; 0, 0 when not
     // chosen), so a row of B_i finds its products with one load
+    bool early_tiny = false;  // the first symbolic run launches the tiny kernel early
     int64_t *col_start = nullptr;
     int32_t *col_len = nullptr;
     int64_t *At_colptr = nullptr;
@@ -266,6 +267,9 @@ int launch_flop_bin_gather(Plan &p);
 // count read on the device), so it follows the flops pass without the
 // host's round trip in between.
 constexpr int64_t kEarlyTinyCols = 16384;
+// Such a launch also publishes the flops pass's counters (from a workgroup
+// of its own), so the flops pass ends without that round trip; set by
+// spgemm_plan for the plan's first symbolic run.
 int launch_sym_tiny(Plan &p, bool early);
 int launch_symbolic_bins(Plan &p, bool tiny_launched);
 int launch_colptr_scan(Plan &p);

@@ -350,8 +350,9 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
         if (blk < ncols_tiles) flop_column_tile<S>(blk, ncols_tiles, rounds, a);
         else flop_long_chunk<S>(blk - ncols_tiles, a);
         __shared__ int s_last;
-        publish_when_last(&a.ctr->tickets[kTkFlopDone], (unsigned long long)nflop, a.ctr, hout,
-                          hready, &s_last);
+        if (hout)  // NULL: the early tiny symbolic kernel publishes instead
+            publish_when_last(&a.ctr->tickets[kTkFlopDone], (unsigned long long)nflop, a.ctr,
+                              hout, hready, &s_last);
     } else {
         __shared__ GatherStage st;
         gather_tile<V, true>(blk - nflop, Acolptr, Arowidx, Avals, map, At_colptr, k, At_rowidx,
@@ -403,8 +404,9 @@ __device__ __forceinline__ int sym_wave_count(int64_t q0, int64_t q1, TermRange 
 
 // count_dev NULL: `count` columns, in `list` (NULL: every column is tiny).
 // count_dev set (a launch before the host has the counts, sized for n
-// columns): the count is read there, and the list is used unless it holds
-// every column.
+// columns plus one workgroup): the count is read there, and the list is used
+// unless it holds every column; the extra last workgroup publishes the
+// flops pass's counters (hout, hready) for the host.
 template <int EMAX>
 __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ list, int count,
                                                   const int *__restrict__ count_dev, int n,
@@ -414,7 +416,14 @@ __global__ __launch_bounds__(256) void k_sym_tiny(const int32_t *__restrict__ li
                                                   const int64_t *__restrict__ flop,
                                                   int64_t *__restrict__ Ccount,
                                                   uint16_t *__restrict__ tiny_perm,
-                                                  int32_t *__restrict__ col_slot) {
+                                                  int32_t *__restrict__ col_slot,
+                                                  const DevCounters *__restrict__ ctr,
+                                                  PublishedCounts *__restrict__ hout,
+                                                  unsigned int *__restrict__ hready) {
+    if (hout && blockIdx.x == gridDim.x - 1) {  // the whole workgroup
+        publish_counters(ctr, hout, hready);
+        return;
+    }
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (count_dev) {
         count = *count_dev;
@@ -724,8 +733,9 @@ static int flop_bin_gather_launch(Plan &p) {
                      p.th,        p.tstart, p.tlen,    p.col_slot, p.flop,      p.arrive,
                      p.sym_bin,   p.sym_list, p.st_colptr, p.n_col_tiles, p.ctr};
     hipLaunchKernelGGL((k_flop_bin_gather<S, V>), dim3((unsigned)(ntiles + nchunks + ngather)),
-                       dim3(kFlopThreads), 0, p.stream, a, ntiles, rounds, nchunks, p.hpub_dev,
-                       p.hflags_dev + kFlagCounts, p.k, p.Acolptr, p.Arowidx,
+                       dim3(kFlopThreads), 0, p.stream, a, ntiles, rounds, nchunks,
+                       p.early_tiny ? nullptr : p.hpub_dev, p.hflags_dev + kFlagCounts, p.k,
+                       p.Acolptr, p.Arowidx,
                        (const V *)p.Avals, p.map, p.At_colptr, p.At_rowidx, (V *)p.At_vals);
     SPG_LAUNCHED("k_flop_bin_gather (" + std::to_string(ntiles) + " column tiles, " +
                  std::to_string(nchunks) + " chunks, " + std::to_string(ngather) +
@@ -766,19 +776,22 @@ static int sym_hash_launch(Plan &p, int bin) {
 int launch_sym_tiny(Plan &p, bool early) {
     const int64_t cols = early ? p.n : p.sym_count[kBinTiny];
     if (cols <= 0) return SPGEMM_OK;
-    const unsigned g = (unsigned)((cols + 3) / 4);
+    // early: one more workgroup, which publishes the flops pass's counters
+    const unsigned g = (unsigned)((cols + 3) / 4) + (early ? 1u : 0u);
     // the bin holds every column: the kernel takes column w directly
     const int32_t *list = p.sym_list + (int64_t)kBinTiny * p.n;
     if (!early && cols == p.n) list = nullptr;
     const int *count_dev = early ? &p.ctr->sym_count[kBinTiny].v : nullptr;
+    PublishedCounts *hout = early ? p.hpub_dev : nullptr;
+    unsigned int *hready = p.hflags_dev + kFlagCounts;
     if (p.th.tiny_max_flop <= 4 * kWave)
         hipLaunchKernelGGL(k_sym_tiny<4>, dim3(g), dim3(256), 0, p.stream, list, (int)cols,
                            count_dev, (int)p.n, p.Bcolptr, p.term_range(), p.At_rowidx, p.flop,
-                           p.C_colptr, p.tiny_perm, p.col_slot);
+                           p.C_colptr, p.tiny_perm, p.col_slot, p.ctr, hout, hready);
     else
         hipLaunchKernelGGL(k_sym_tiny<8>, dim3(g), dim3(256), 0, p.stream, list, (int)cols,
                            count_dev, (int)p.n, p.Bcolptr, p.term_range(), p.At_rowidx, p.flop,
-                           p.C_colptr, p.tiny_perm, p.col_slot);
+                           p.C_colptr, p.tiny_perm, p.col_slot, p.ctr, hout, hready);
     SPG_LAUNCHED(early ? "k_sym_tiny (before the counts)" : "k_sym_tiny");
     return SPGEMM_OK;
 }
