@@ -334,8 +334,9 @@ __device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
 // flops and bins (column tiles, then chunk workgroups; first, since the host
 // waits for their counts) and the gather tiles of A~.  Neither reads what
 // the other writes, so their chains of dependent loads overlap instead of
-// running one after the other.  The last of the flop workgroups publishes
-// the counters.
+// running one after the other.  With hout set, the last of the flop
+// workgroups publishes the counters (else the early tiny symbolic launch
+// does).
 static_assert(kFlopThreads == kGatherThreads, "all tiles use the whole workgroup");
 template <int S, typename V>
 __global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
