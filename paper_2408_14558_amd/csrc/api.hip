@@ -352,6 +352,18 @@ static int sync_counters(Plan &p) {
     return SPGEMM_OK;
 }
 
+// The flops total and the numeric bin counts of a symbolic run that returned
+// nnz(C_i) early (one-workgroup scan): waits for the scan's flag and reads
+// them from the pinned block.
+int finish_symbolic_counts(Plan &p) {
+    if (!p.counts_pending) return SPGEMM_OK;
+    SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
+    p.flops = p.hpub->flops;
+    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
+    p.counts_pending = false;
+    return SPGEMM_OK;
+}
+
 }  // namespace spg
 
 using namespace spg;
@@ -640,7 +652,9 @@ int spgemm_plan_set_stream(spgemm_plan_t plan, void *stream) {
 int spgemm_plan_stats(spgemm_plan_t plan, spgemm_stats *s) {
     if (!plan || !s) return fail(SPGEMM_EINVAL, "plan or stats is NULL");
     Plan &p = *plan;
-    int rc = sync_counters(p);
+    int rc = finish_symbolic_counts(p);
+    if (rc) return rc;
+    rc = sync_counters(p);
     if (rc) return rc;
     const DevCounters &c = *p.hctr;
     std::memset(s, 0, sizeof(*s));
@@ -708,9 +722,11 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
     if (!C_colptr || !nnzC) return fail(SPGEMM_EINVAL, "C_colptr and nnzC must not be NULL");
     Plan &p = *plan;
+    int rc;
+    // a previous run's late publish must land before the flags are reset
+    if ((rc = finish_symbolic_counts(p))) return rc;
     p.C_colptr = C_colptr;
     p.symbolic_done = false;
-    int rc;
     if (p.n == 0) {
         SPG_HIP(hipMemsetAsync(C_colptr, 0, sizeof(int64_t), p.stream));
         p.nnzC = 0;
@@ -740,11 +756,34 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     reserve_dense(p);
     if ((rc = launch_symbolic_bins(p, early))) return rc;
     __atomic_store_n(p.hflags + kFlagColptr, 0u, __ATOMIC_RELEASE);
+    // the one-workgroup scan stores nnz(C_i) + 1 ahead of the rest: return
+    // it as soon as it lands and collect the rest when it is needed
+    uint64_t *hnnz = reinterpret_cast<uint64_t *>(p.hflags + kNnzSlot);
+    const bool small = p.n <= kSmallScanCols;
+    if (small) __atomic_store_n(hnnz, (uint64_t)0, __ATOMIC_RELEASE);
     if ((rc = launch_colptr_scan(p))) return rc;  // publishes its counters to hpub
-    SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
-    p.nnzC = p.hpub->nnzC;
-    p.flops = p.hpub->flops;
-    for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
+    if (small) {
+        const auto t0 = std::chrono::steady_clock::now();
+        uint64_t v = 0;
+        for (unsigned i = 0; (v = __atomic_load_n(hnnz, __ATOMIC_ACQUIRE)) == 0; ++i) {
+            if ((i & 255u) == 255u &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros)) {
+                SPG_HIP(hipStreamSynchronize(p.stream));
+                v = __atomic_load_n(hnnz, __ATOMIC_ACQUIRE);
+                break;
+            }
+            __builtin_ia32_pause();
+        }
+        if (v == 0) return fail(SPGEMM_EHIP, "the column-pointer scan did not report nnz(C_i)");
+        p.nnzC = (int64_t)(v - 1);
+        p.counts_pending = true;
+    } else {
+        SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
+        p.nnzC = p.hpub->nnzC;
+        p.flops = p.hpub->flops;
+        for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
+        p.counts_pending = false;
+    }
     p.symbolic_done = true;
     *nnzC = p.nnzC;
     return SPGEMM_OK;
@@ -756,6 +795,8 @@ int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
     if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
     Plan &p = *plan;
     if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_numeric needs spgemm_symbolic first");
+    int rc0;
+    if ((rc0 = finish_symbolic_counts(p))) return rc0;
     if (p.nnzC > 0 && (!C_rowidx || !C_vals))
         return fail(SPGEMM_EINVAL, "C_rowidx and C_vals must not be NULL");
     const void *Bv = Bi_vals ? Bi_vals : p.Bvals;
@@ -773,6 +814,8 @@ int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *
     if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
     Plan &p = *plan;
     if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_backward needs spgemm_symbolic first");
+    int rc0;
+    if ((rc0 = finish_symbolic_counts(p))) return rc0;
     if (!dA_vals && !dB_vals) return SPGEMM_OK;
     const void *Av = A_vals ? A_vals : p.Avals;
     const void *Bv = Bi_vals ? Bi_vals : p.Bvals;
@@ -787,6 +830,8 @@ int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *
 int spgemm_plan_destroy(spgemm_plan_t plan) {
     if (!plan) return SPGEMM_OK;
     Plan &p = *plan;
+    // the scan's publish into the pinned block lands before the block is reused
+    (void)finish_symbolic_counts(p);
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
     // the pinned block's last device-side use is the counters copy that
     // counts_ready follows (later copies were waited for on the host)

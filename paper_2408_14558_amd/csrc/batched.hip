@@ -117,6 +117,7 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         const std::string who = "product " + std::to_string(t);
         if (!p) return fail(SPGEMM_EINVAL, who + ": plan is NULL");
         if (!p->symbolic_done) return fail(SPGEMM_ESTATE, who + " has not run symbolic");
+        if (int rc = finish_symbolic_counts(*p)) return rc;
         if (p->dtype != dt) return fail(SPGEMM_EINVAL, "plans must share one dtype");
         for (int u = 0; u < t; ++u)
             if (plans[u] == p)

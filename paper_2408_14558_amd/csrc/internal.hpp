@@ -82,6 +82,12 @@ struct DevCounters {
 };
 
 enum PinnedFlag { kFlagCounts = 0, kFlagColptr = 1 };
+// u32 index, in the same pinned block, of a 64-bit word where the
+// one-workgroup scan stores nnz(C_i) + 1 as soon as it has the total, ahead
+// of its other writes and of kFlagColptr (8-byte aligned).
+constexpr int kNnzSlot = 16;
+// B_i with at most this many columns is scanned by one workgroup.
+constexpr int64_t kSmallScanCols = 8192;
 
 // What the symbolic phase needs from the device counters, copied by the
 // kernel that completes them to pinned host memory (one wave's writes).
@@ -216,6 +222,9 @@ struct Plan {
 
     // symbolic results
     bool symbolic_done = false;
+    // nnzC is known but the flops total and the numeric bin counts are still
+    // on their way to hpub (kFlagColptr); finish_symbolic_counts collects them
+    bool counts_pending = false;
     int symbolic_runs = 0;
     hipEvent_t counts_ready = nullptr;  // the plan's counters (flops, bins) reached hctr
     int64_t *C_colptr = nullptr;
@@ -273,6 +282,7 @@ constexpr int64_t kEarlyTinyCols = 16384;
 int launch_sym_tiny(Plan &p, bool early);
 int launch_symbolic_bins(Plan &p, bool tiny_launched);
 int launch_colptr_scan(Plan &p);
+int finish_symbolic_counts(Plan &p);
 int launch_symbolic_reset(Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,

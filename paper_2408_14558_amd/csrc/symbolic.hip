@@ -610,14 +610,16 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
 // columns follow one another, the running total and each bin's list length
 // carried over; the counters the host needs are then published as by the
 // tiled scan's last workgroup.
+// nnz(C_i) + 1 goes to *hnnz (pinned host memory) the moment the total is
+// known, so the host can return it before the rest is published.
 constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallScanItems = 4;
-constexpr int64_t kSmallScanCols = 2 * kSmallScanThreads * kSmallScanItems;
+static_assert(kSmallScanCols == 2 * kSmallScanThreads * kSmallScanItems, "two chunks at most");
 __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
     int64_t n, int64_t *__restrict__ Ccolptr, const int64_t *__restrict__ flop, Thresholds th,
     int32_t *__restrict__ num_bin, int32_t *__restrict__ num_list,
     DevCounters *__restrict__ ctr, PublishedCounts *__restrict__ hout,
-    unsigned int *__restrict__ hready) {
+    unsigned int *__restrict__ hready, unsigned long long *__restrict__ hnnz) {
     constexpr int CH = kSmallScanThreads * kSmallScanItems;
     __shared__ long long s_tmp64[kSmallScanThreads / kWave + 1];
     __shared__ int s_cnt[kNumBins];   // this chunk's columns per bin
@@ -676,6 +678,8 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
     }
     __syncthreads();
     if (tid == 0) {
+        __hip_atomic_store(hnnz, (unsigned long long)carry + 1ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
         Ccolptr[n] = carry;
         ctr->nnzC = carry;
         hout->flops = ctr->flops.v;
@@ -826,7 +830,8 @@ int launch_colptr_scan(Plan &p) {
     if (p.n <= kSmallScanCols) {
         hipLaunchKernelGGL(k_colptr_scan_small, dim3(1), dim3(kSmallScanThreads), 0, p.stream, p.n,
                            p.C_colptr, p.flop, p.th, p.num_bin, p.num_list, p.ctr, p.hpub_dev,
-                           p.hflags_dev + kFlagColptr);
+                           p.hflags_dev + kFlagColptr,
+                           reinterpret_cast<unsigned long long *>(p.hflags_dev + kNnzSlot));
         SPG_HIP(hipGetLastError());
         return SPGEMM_OK;
     }
