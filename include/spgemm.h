@@ -198,10 +198,12 @@ int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
  * stored whenever a product reaches it, even if values later cancel) and
  * scans the counts.  Waits on the host twice: for the bin sizes (first call
  * on a plan only) and for nnzC.  Both are written to pinned host memory by
- * the last workgroup of the kernel that computes them, followed by a flag
- * the host polls for a short while before it falls back to a blocking
- * synchronisation of the plan's stream; C_colptr is complete when the call
- * returns, and later work on the plan's stream is ordered after it.
+ * the device (the bin sizes by the kernel after the flops pass; nnzC by the
+ * scan as soon as it has the total, for n_i <= 8192 ahead of its other
+ * writes), each behind a flag the host polls for a short while before it
+ * falls back to a blocking synchronisation of the plan's stream.  C_colptr
+ * is written by work enqueued on the plan's stream: later work on that
+ * stream, or a synchronisation of it, sees it complete.
  */
 int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
 
