@@ -141,3 +141,29 @@ def test_state_and_null_handle_errors(lib):
     assert lib.spgemm_plan_destroy(None) == _lib.OK
     assert lib.spgemm_batch_destroy(None) == _lib.OK
     assert lib.spgemm_plan_stats(None, None) == _lib.EINVAL
+
+
+def test_c_struct_follows_the_arrays():
+    # the binding keeps a matrix's C struct while its arrays stay the same
+    # and builds a new one when an array, the shape or nnz changes
+    import torch
+    spg = pytest.importorskip("paper_2408_14558_amd")
+    M = spg.DeviceCsc(5, 3, torch.tensor([0, 1, 2, 2], dtype=torch.int64),
+                      torch.tensor([0, 4], dtype=torch.int32),
+                      torch.tensor([1.0, 2.0], dtype=torch.float64))
+    s1 = M.c_struct()
+    assert M.c_struct() is s1
+    assert (s1.nrows, s1.ncols, s1.nnz) == (5, 3, 2)
+    assert s1.colptr == M.colptr.data_ptr() and s1.vals == M.vals.data_ptr()
+    M.vals = torch.tensor([3.0, 4.0], dtype=torch.float64)
+    s2 = M.c_struct()
+    assert s2 is not s1 and s2.vals == M.vals.data_ptr()
+    M.rowidx = torch.tensor([1], dtype=torch.int32)
+    M.vals = torch.tensor([5.0], dtype=torch.float64)
+    M.colptr = torch.tensor([0, 1, 1, 1], dtype=torch.int64)
+    s3 = M.c_struct()
+    assert s3.nnz == 1 and s3.rowidx == M.rowidx.data_ptr() and s3.colptr == M.colptr.data_ptr()
+    E = spg.DeviceCsc(4, 2, torch.zeros(3, dtype=torch.int64),
+                      torch.zeros(0, dtype=torch.int32), None)
+    se = E.c_struct()
+    assert se.nnz == 0 and not se.rowidx and not se.vals
