@@ -208,11 +208,17 @@ class Plan:
             vals = torch.empty(self.nnzC, dtype=self.torch_dtype, device=self.device)
         else:
             rows, vals = out
-        for t, what in ((A_vals, "A_vals"), (B_vals, "B_vals")):
-            if t is not None and (t.dtype != self.torch_dtype or not t.is_contiguous()):
-                raise ValueError(f"{what} must be contiguous {self.torch_dtype}")
-        check(self.lib.spgemm_numeric(self.handle, _ptr(A_vals), _ptr(B_vals), _ptr(rows),
-                                      _ptr(vals)), "spgemm_numeric")
+        if A_vals is not None or B_vals is not None:
+            for t, what in ((A_vals, "A_vals"), (B_vals, "B_vals")):
+                if t is not None and (t.dtype != self.torch_dtype or not t.is_contiguous()):
+                    raise ValueError(f"{what} must be contiguous {self.torch_dtype}")
+        # addresses as plain ints (the argument types are void pointers)
+        rc = self.lib.spgemm_numeric(self.handle,
+                                     None if A_vals is None else A_vals.data_ptr(),
+                                     None if B_vals is None else B_vals.data_ptr(),
+                                     rows.data_ptr(), vals.data_ptr())
+        if rc:
+            check(rc, "spgemm_numeric")
         return rows, vals
 
     def backward(self, C_rowidx: torch.Tensor, dC: torch.Tensor,
