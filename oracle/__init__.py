@@ -6,8 +6,10 @@ smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
 code with the HIP library and never imports it.
 
 The arithmetic lives in ``oracle.c`` (FP64, built with gcc
-``-O2 -ffp-contract=off``, single-threaded); this module only marshals numpy
-arrays through ctypes.  Matrices are accepted duck-typed: any object with
+``-O2 -ffp-contract=off -fopenmp``; the two product passes hand output
+columns to OpenMP threads, each column computed by one thread in the same
+order whatever the thread count); this module only marshals numpy arrays
+through ctypes.  :func:`set_threads` fixes the thread count.  Matrices are accepted duck-typed: any object with
 ``nrows, ncols, colptr, rowidx, vals`` attributes (CSC, int64 column
 pointers, int32 row ids ascending per column).
 
@@ -42,13 +44,15 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 _f64p = ctypes.POINTER(ctypes.c_double)
 
 
+# flags of every build of oracle.c (the sanitizer test adds its own)
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-Wall", "-Werror"]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so next to it (gcc, no GPU code)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-Wall", "-Werror", _SRC,
-                               "-o", tmp])
+        subprocess.check_call(["gcc", *CFLAGS, "-fPIC", "-shared", _SRC, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -75,12 +79,26 @@ def _load():
     lib.oracle_backward.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f64p,
                                     ctypes.c_int64, _i64p, _i32p, _f64p, _i64p, _i32p,
                                     _f64p, _f64p, _f64p]
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     for name in ("oracle_rows_of_b", "oracle_block_select", "oracle_gather",
                  "oracle_column_flops", "oracle_spgemm_count", "oracle_spgemm_fill",
                  "oracle_backward"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the product passes (n <= 0: OpenMP's default)."""
+    _load().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    """Threads the next product pass will use."""
+    return int(_load().oracle_threads())
 
 
 def _p(a: Optional[np.ndarray], ptype):

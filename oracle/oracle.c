@@ -15,11 +15,17 @@
  *   scratch allocation fails.
  *
  * Everything is computed in FP64 with the summation order stated at each
- * function; build with -ffp-contract=off so a*b+c is never fused.
+ * function; build with -ffp-contract=off so a*b+c is never fused.  The two
+ * product passes (count, fill) hand output columns to OpenMP threads when
+ * built with -fopenmp; one thread computes a whole column, so the results do
+ * not depend on the thread count.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_OK 0
 #define ORACLE_EINVAL (-1)
@@ -195,6 +201,58 @@ static int cmp_i32(const void *x, const void *y)
 }
 
 /*
+ * Output columns are independent (Sec. III-A computes C column by column),
+ * so the two product passes below hand requested columns to OpenMP threads,
+ * each with its own dense accumulator.  A column's own arithmetic and its
+ * order are the same whatever the thread count.  oracle_set_threads(n)
+ * fixes the thread count (n <= 0: OpenMP's default); oracle_threads()
+ * returns the count the next pass will use.
+ */
+static int g_threads = 0;
+
+void oracle_set_threads(int n) { g_threads = n > 0 ? n : 0; }
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads > 0 ? g_threads : omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * Number of distinct rows of column j of A*B: the union of A(:,k) over the
+ * stored b_kj.  flag (m bytes, all 0 on entry and on return) and list (m
+ * ints) are the caller's scratch.  Returns the count, or -1 for a row id of
+ * B outside A's columns.
+ */
+static int64_t count_column(int64_t k, const int64_t *Acolptr, const int32_t *Arowidx,
+                            const int64_t *Bcolptr, const int32_t *Browidx, int64_t j,
+                            uint8_t *flag, int32_t *list)
+{
+    int64_t len = 0;
+    for (int64_t q = Bcolptr[j]; q < Bcolptr[j + 1]; ++q) {
+        int32_t kk = Browidx[q];
+        if (kk < 0 || kk >= k) {
+            for (int64_t e = 0; e < len; ++e)
+                flag[list[e]] = 0;
+            return -1;
+        }
+        for (int64_t p = Acolptr[kk]; p < Acolptr[kk + 1]; ++p) {
+            int32_t i = Arowidx[p];
+            if (!flag[i]) {
+                flag[i] = 1;
+                list[len++] = i;
+            }
+        }
+    }
+    for (int64_t e = 0; e < len; ++e)
+        flag[list[e]] = 0;
+    return len;
+}
+
+/*
  * Number of stored entries of each requested column of C = A*B (Sec. III-A,
  * column-by-column formula C(:,j) = sum_k A(:,k) b_kj): the number of
  * distinct row ids in the union of A(:,k) over the stored b_kj.  A row is
@@ -210,42 +268,90 @@ int oracle_spgemm_count(int64_t m, int64_t k, const int64_t *Acolptr,
 {
     if (m < 0 || k < 0 || n < 0 || ncols < 0 || !Acolptr || !Bcolptr)
         return ORACLE_EINVAL;
-    uint8_t *flag = (uint8_t *)calloc((size_t)(m > 0 ? m : 1), 1);
-    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
-    if (!flag || !list) {
+    int rc = ORACLE_OK;
+#pragma omp parallel num_threads(oracle_threads())
+    {
+        uint8_t *flag = (uint8_t *)calloc((size_t)(m > 0 ? m : 1), 1);
+        int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+        if (!flag || !list) {
+#pragma omp atomic write
+            rc = ORACLE_ENOMEM;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < ncols; ++t) {
+            int bad;
+#pragma omp atomic read
+            bad = rc;
+            if (bad != ORACLE_OK)
+                continue;
+            int64_t j = cols ? cols[t] : t;
+            int64_t len = j < 0 || j >= n ? -1
+                          : count_column(k, Acolptr, Arowidx, Bcolptr, Browidx, j, flag, list);
+            if (len < 0) {
+#pragma omp atomic write
+                rc = ORACLE_EINVAL;
+                continue;
+            }
+            counts[t] = len;
+        }
         free(flag);
         free(list);
-        return ORACLE_ENOMEM;
     }
-    int rc = ORACLE_OK;
-    for (int64_t t = 0; t < ncols && rc == ORACLE_OK; ++t) {
-        int64_t j = cols ? cols[t] : t;
-        if (j < 0 || j >= n) {
-            rc = ORACLE_EINVAL;
+    return rc;
+}
+
+/*
+ * Values of column j of A*B into out (rows), outval and outabs (may be NULL)
+ * at their final places: the dense accumulator spa/spa_abs (m doubles each),
+ * flag (m bytes, 0 on entry and on return) and list (m ints) are the
+ * caller's scratch.  want is the count the caller sized the column for.
+ * Returns 0, or -1 on a bad row id of B or a count that differs from want.
+ */
+static int fill_column(int64_t k, const int64_t *Acolptr, const int32_t *Arowidx,
+                       const double *Avals, const int64_t *Bcolptr,
+                       const int32_t *Browidx, const double *Bvals, int64_t j,
+                       int64_t want, int32_t *outrow, double *outval, double *outabs,
+                       uint8_t *flag, double *spa, double *spa_abs, int32_t *list)
+{
+    int64_t len = 0;
+    int bad = 0;
+    for (int64_t q = Bcolptr[j]; q < Bcolptr[j + 1] && !bad; ++q) {
+        int32_t kk = Browidx[q];
+        double bv = Bvals[q];
+        if (kk < 0 || kk >= k) {
+            bad = 1;
             break;
         }
-        int64_t len = 0;
-        for (int64_t q = Bcolptr[j]; q < Bcolptr[j + 1]; ++q) {
-            int32_t kk = Browidx[q];
-            if (kk < 0 || kk >= k) {
-                rc = ORACLE_EINVAL;
-                break;
-            }
-            for (int64_t p = Acolptr[kk]; p < Acolptr[kk + 1]; ++p) {
-                int32_t i = Arowidx[p];
-                if (!flag[i]) {
-                    flag[i] = 1;
-                    list[len++] = i;
-                }
+        for (int64_t p = Acolptr[kk]; p < Acolptr[kk + 1]; ++p) {
+            int32_t i = Arowidx[p];
+            double prod = Avals[p] * bv;
+            double mag = (Avals[p] < 0 ? -Avals[p] : Avals[p]) * (bv < 0 ? -bv : bv);
+            if (!flag[i]) {
+                flag[i] = 1;
+                list[len++] = i;
+                spa[i] = prod;
+                spa_abs[i] = mag;
+            } else {
+                spa[i] = spa[i] + prod;
+                spa_abs[i] = spa_abs[i] + mag;
             }
         }
+    }
+    if (bad || len != want) {
         for (int64_t e = 0; e < len; ++e)
             flag[list[e]] = 0;
-        counts[t] = len;
+        return -1;
     }
-    free(flag);
-    free(list);
-    return rc;
+    qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+    for (int64_t e = 0; e < len; ++e) {
+        int32_t i = list[e];
+        outrow[e] = i;
+        outval[e] = spa[i];
+        if (outabs)
+            outabs[e] = spa_abs[i];
+        flag[i] = 0;
+    }
+    return 0;
 }
 
 /*
@@ -268,67 +374,39 @@ int oracle_spgemm_fill(int64_t m, int64_t k, const int64_t *Acolptr,
     if (m < 0 || k < 0 || n < 0 || ncols < 0 || !Acolptr || !Bcolptr || !outptr)
         return ORACLE_EINVAL;
     size_t mm = (size_t)(m > 0 ? m : 1);
-    uint8_t *flag = (uint8_t *)calloc(mm, 1);
-    double *spa = (double *)malloc(sizeof(double) * mm);
-    double *spa_abs = (double *)malloc(sizeof(double) * mm);
-    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * mm);
-    if (!flag || !spa || !spa_abs || !list) {
+    int rc = ORACLE_OK;
+#pragma omp parallel num_threads(oracle_threads())
+    {
+        uint8_t *flag = (uint8_t *)calloc(mm, 1);
+        double *spa = (double *)malloc(sizeof(double) * mm);
+        double *spa_abs = (double *)malloc(sizeof(double) * mm);
+        int32_t *list = (int32_t *)malloc(sizeof(int32_t) * mm);
+        if (!flag || !spa || !spa_abs || !list) {
+#pragma omp atomic write
+            rc = ORACLE_ENOMEM;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < ncols; ++t) {
+            int bad;
+#pragma omp atomic read
+            bad = rc;
+            if (bad != ORACLE_OK)
+                continue;
+            int64_t j = cols ? cols[t] : t;
+            int64_t o = outptr[t];
+            if (j < 0 || j >= n ||
+                fill_column(k, Acolptr, Arowidx, Avals, Bcolptr, Browidx, Bvals, j,
+                            outptr[t + 1] - o, outrow + o, outval + o,
+                            outabs ? outabs + o : NULL, flag, spa, spa_abs, list) != 0) {
+#pragma omp atomic write
+                rc = ORACLE_EINVAL;
+            }
+        }
         free(flag);
         free(spa);
         free(spa_abs);
         free(list);
-        return ORACLE_ENOMEM;
     }
-    int rc = ORACLE_OK;
-    for (int64_t t = 0; t < ncols && rc == ORACLE_OK; ++t) {
-        int64_t j = cols ? cols[t] : t;
-        if (j < 0 || j >= n) {
-            rc = ORACLE_EINVAL;
-            break;
-        }
-        int64_t len = 0;
-        for (int64_t q = Bcolptr[j]; q < Bcolptr[j + 1]; ++q) {
-            int32_t kk = Browidx[q];
-            double bv = Bvals[q];
-            if (kk < 0 || kk >= k) {
-                rc = ORACLE_EINVAL;
-                break;
-            }
-            for (int64_t p = Acolptr[kk]; p < Acolptr[kk + 1]; ++p) {
-                int32_t i = Arowidx[p];
-                double prod = Avals[p] * bv;
-                double mag = (Avals[p] < 0 ? -Avals[p] : Avals[p]) * (bv < 0 ? -bv : bv);
-                if (!flag[i]) {
-                    flag[i] = 1;
-                    list[len++] = i;
-                    spa[i] = prod;
-                    spa_abs[i] = mag;
-                } else {
-                    spa[i] = spa[i] + prod;
-                    spa_abs[i] = spa_abs[i] + mag;
-                }
-            }
-        }
-        if (rc != ORACLE_OK)
-            break;
-        if (outptr[t + 1] - outptr[t] != len) {
-            rc = ORACLE_EINVAL;
-            break;
-        }
-        qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
-        for (int64_t e = 0; e < len; ++e) {
-            int32_t i = list[e];
-            outrow[outptr[t] + e] = i;
-            outval[outptr[t] + e] = spa[i];
-            if (outabs)
-                outabs[outptr[t] + e] = spa_abs[i];
-            flag[i] = 0;
-        }
-    }
-    free(flag);
-    free(spa);
-    free(spa_abs);
-    free(list);
     return rc;
 }
 
