@@ -5,10 +5,13 @@ A step is one pass of the whole path for one partition: spgemm_plan (H_i,
 Alg. 2 block selection, column map, gather of A~), spgemm_symbolic (flops,
 binning, nnz count, scan) and spgemm_numeric, with inputs resident in HBM.
 
-Default workload (N=1): C_0 = A * B_0 for one of 16 column blocks, A and B
-independent 65536 x 65536 Erdos-Renyi matrices with 16 entries per column,
-U(-1,1) FP64 values, block size b = 256.  Other workloads are selectable with
---workload for reporting, the JSON line always names the one it ran.
+Default workload (N=1): C = A * A for A the R-MAT scale-18 matrix (262,144
+rows and columns, edge factor 16, (a,b,c,d) = (0.57, 0.19, 0.19, 0.05),
+duplicates merged, U(0,1) values, FP64), one partition (the largest
+single-GPU configuration).  The other configurations are reported beside it
+under "workloads" (warm and with the 256 MB last-level cache flushed before
+every step), with the batched and differentiable forms under "batched" and
+"backward".  --workload selects another headline.
 
 Prints ONE JSON line.  value = 2 * sparse flops / step time (GFLOP/s).
 """
@@ -19,8 +22,11 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -30,21 +36,18 @@ METRIC = "SpGEMM GFLOP/s + achieved HBM GB/s (% peak); batched/backward vs plain
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the numeric phase, from two rocprofv3 counter
-# passes (FETCH_SIZE, then WRITE_SIZE, summed over the phase's kernels and
-# divided by the launches), scaled by what the same counters read for a
-# plain 1 GiB device copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0.  A value only
-# holds for the kernel sources it was taken on; when their digest differs,
-# traffic is reported as null.
+# passes (FETCH_SIZE, then WRITE_SIZE) summarised in
+# profiles/numeric_phase_hbm_traffic.md: each of its "traffic-record:" lines
+# holds a JSON object with the workload, the scaled bytes and the digest of
+# the kernel sources the counters were taken on.  When the sources have
+# changed since, traffic is reported as null.
 TRAFFIC_SOURCES = ("numeric.hip", "numeric.hpp", "terms.hpp", "common.hpp", "internal.hpp")
-MEASURED_TRAFFIC = {
-    "er65536_d16_p16_block0_b256": {"bytes": 32006870, "sources": "23eaa6e3ced2ebcc"},
-    "rmat18_ef16_AxA_f64": {"bytes": 49112124716, "sources": "23eaa6e3ced2ebcc"},
-}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_phase_hbm_traffic.md")
 
 
 def kernel_sources_digest():
     h = hashlib.sha256()
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2408_14558_amd", "csrc")
+    csrc = os.path.join(ROOT, "paper_2408_14558_amd", "csrc")
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
@@ -52,10 +55,21 @@ def kernel_sources_digest():
 
 
 def measured_traffic(workload_desc):
-    m = MEASURED_TRAFFIC.get(workload_desc)
-    if m is None or m["sources"] != kernel_sources_digest():
-        return None
-    return m["bytes"]
+    """(bytes, record) of the counter summary for this workload while the
+    kernel sources are unchanged, else (None, reason)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln for ln in fh if ln.startswith("traffic-record:")]
+    except OSError:
+        return None, "no counter summary"
+    digest = kernel_sources_digest()
+    for ln in lines:
+        rec = json.loads(ln.split(":", 1)[1])
+        if rec.get("workload") == workload_desc:
+            if rec.get("sources") != digest:
+                return None, f"kernels changed since the counters ({rec.get('sources')} != {digest})"
+            return rec["bytes"], rec
+    return None, "no counter record for this workload"
 
 
 def workload(name):
@@ -71,10 +85,11 @@ def workload(name):
                             "partitions": 16, "partition": 0, "block_size": 256})
     if name in ("rmat18", "rmat18-f32"):
         w = synth.workload("rmat18")
+        f32 = name.endswith("f32")
         return dict(A=w["A"], Bi=w["A"], offs=w["offsets"], b=256,
-                    dtype="f32" if name.endswith("f32") else "f64",
-                    desc=f"rmat18_ef16_AxA_{'f32' if name.endswith('f32') else 'f64'}",
-                    config={"A": "R-MAT scale 18, ef 16, (0.57,0.19,0.19,0.05), seed 3",
+                    dtype="f32" if f32 else "f64",
+                    desc=f"rmat18_ef16_AxA_{'f32' if f32 else 'f64'}",
+                    config={"A": "R-MAT scale 18, ef 16, (0.57,0.19,0.19,0.05), U(0,1), seed 3",
                             "B": "A", "partitions": 1, "block_size": 256})
     if name == "lap2d":
         w = synth.workload("lap2d_64_p4")
@@ -92,35 +107,65 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The oracle as it stands (single-threaded FP64 C) on the host cores:
-    the whole local step (H_i, Alg. 2, A~, flops, C_i) over consecutive
-    blocks of at most 4096 columns of B_i, cycling, until about budget_s
-    seconds have run."""
+def phase_bytes(st, vsize):
+    """Algorithmic bytes of the three phases (each input array read once,
+    each output written once): plan (H_i, Alg. 2, map, A~), symbolic (counts
+    and scan), numeric (values)."""
+    k, n, kt = st["k"], st["n"], st["kt"]
+    nb, nt, nc = st["nnz_B"], st["nnz_At"], st["nnz_C"]
+    plan = 4 * nb + 8 * (k + 1) + k + 4 * k + 2 * (4 + vsize) * nt + 8 * (kt + 1)
+    symbolic = 8 * (n + 1) + 4 * nb + 4 * nt + 8 * n
+    numeric = (4 + vsize) * (nb + nt + nc) + 8 * (n + 1)
+    return {"plan": plan, "symbolic": symbolic, "numeric": numeric}
+
+
+def _host_cpu():
+    model = "?"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The oracle as it stands (FP64 C, output columns on OpenMP threads)
+    on the host cores: the whole local step (H_i, Alg. 2, A~, flops, C_i)
+    for an evenly strided sample of B_i's columns, grown until one pass takes
+    between budget_s / 4 and budget_s seconds on one thread; then the same
+    sample on every thread the host offers."""
     import oracle
     import synth
     A, Bi = w["A"], w["Bi"]
     if w["dtype"] == "f32":
         A, Bi = synth.as_fp32(A), synth.as_fp32(Bi)
-    chunk = min(Bi.ncols, 4096)
-    starts = list(range(0, Bi.ncols, chunk))
-    flops = 0
-    cols = 0
-    t0 = time.perf_counter()
-    i = 0
-    while True:
-        c0 = starts[i % len(starts)]
-        blk = synth.column_slice(Bi, c0, min(Bi.ncols, c0 + chunk))
+    model, ncpu = _host_cpu()
+
+    def run(cols, threads):
+        oracle.set_threads(threads)
+        blk = synth.column_subset(Bi, cols)
+        t0 = time.perf_counter()
         loc = oracle.local_product(A, blk, w["offs"], w["b"])
-        flops += int(loc.flop.sum())
-        cols += blk.ncols
-        i += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or el * (i + 1) / i > 30.0:
-            break
-    return {"value": 2.0 * flops / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{i} blocks of <= {chunk} columns of B_i ({cols} columns, {flops} "
-                      f"flops) through the whole local step, {el:.1f} s"}
+        return time.perf_counter() - t0, int(loc.flop.sum()), oracle.threads()
+
+    stride = max(1, Bi.ncols // 256)
+    el, flops, _ = run(np.arange(0, Bi.ncols, stride), 1)
+    while el < budget_s / 4 and stride > 1:
+        stride = max(1, stride // 4)
+        el, flops, _ = run(np.arange(0, Bi.ncols, stride), 1)
+    cols = np.arange(0, Bi.ncols, stride)
+    el_all, flops_all, used = run(cols, 0)
+    oracle.set_threads(0)
+    sample = (f"{cols.size} of {Bi.ncols} columns of B_i (every {stride}th) through the whole "
+              f"local step, {flops} flops")
+    return {"value": round(2.0 * flops_all / el_all / 1e9, 4), "unit": "GFLOP/s", "cores": used,
+            "kind": "oracle", "sample": sample, "seconds": round(el_all, 3),
+            "one_core": {"value": round(2.0 * flops / el / 1e9, 4), "cores": 1,
+                         "seconds": round(el, 3)},
+            "host": {"cpu_model": model, "nproc": ncpu}}
 
 
 def _time_on(stream, fn, reps):
@@ -402,15 +447,96 @@ def study_outer(spg, parts=(4, 8, 16), reps=3):
     return rows
 
 
+def step_timer(spg, w, tun=None):
+    """Uploads a workload and returns (run_step, plan_stats): run_step(record)
+    runs one whole step (plan, symbolic, numeric, release) on the current
+    stream; with record=True it returns HIP events at the phase borders."""
+    import torch
+    tdt = torch.float64 if w["dtype"] == "f64" else torch.float32
+    Ad = spg.DeviceCsc.from_host(w["A"], dtype=tdt)
+    Bd = spg.DeviceCsc.from_host(w["Bi"], dtype=tdt)
+    stream = torch.cuda.current_stream()
+
+    def run_step(record=False):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        if record:
+            ev[0].record(stream)
+        p = spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun)
+        if record:
+            ev[1].record(stream)
+        p.symbolic()
+        if record:
+            ev[2].record(stream)
+        p.numeric()
+        if record:
+            ev[3].record(stream)
+        p.close()
+        return ev
+
+    with spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun) as p:
+        p.symbolic()
+        rows, vals = p.numeric()
+        st = p.stats()
+    return run_step, st, (Ad, Bd)
+
+
+def timed_steps(run_step, steps, flush=None):
+    """Wall-clock ms of `steps` single steps, each bracketed by device
+    synchronisations; with `flush` (a device tensor larger than the
+    last-level cache) every step starts after that tensor is rewritten."""
+    import torch
+    out = []
+    for r in range(steps):
+        if flush is not None:
+            flush.fill_(float(r))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_step()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return out
+
+
+def side_workloads(spg, names, steps=10):
+    """Warm and cache-flushed step times of the other configurations."""
+    import torch
+    flush = torch.empty(512 << 20 >> 3, dtype=torch.float64, device="cuda")
+    res = {}
+    for name in names:
+        w = workload(name)
+        run_step, st, keep = step_timer(spg, w)
+        vs = 8 if w["dtype"] == "f64" else 4
+        for _ in range(2):
+            run_step()
+        warm = timed_steps(run_step, steps)
+        cold = timed_steps(run_step, steps, flush)
+        mw, mc = float(np.median(warm)), float(np.median(cold))
+        byt = phase_bytes(st, vs)
+        res[w["desc"]] = {
+            "flops": st["flops"], "nnz_C": st["nnz_C"], "dtype": w["dtype"],
+            "ms_per_step_warm": round(mw, 4), "ms_per_step_flushed": round(mc, 4),
+            "GFLOPs_warm": round(2 * st["flops"] / (mw * 1e-3) / 1e9, 3),
+            "GFLOPs_flushed": round(2 * st["flops"] / (mc * 1e-3) / 1e9, 3),
+            "algorithmic_bytes_per_step": int(sum(byt.values())),
+            "step_GBs_flushed": round(sum(byt.values()) / (mc * 1e-3) / 1e9, 1)}
+        print(json.dumps({name: res[w["desc"]]}), file=sys.stderr, flush=True)
+        del keep, run_step
+        torch.cuda.synchronize()
+    del flush
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="er65536")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat18")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and backward measurements")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the other configurations' warm/flushed step times")
     ap.add_argument("--study", choices=["gather-volume", "bfs", "outer"],
                     help="instead of the benchmark, run a study and print its table as JSON")
     ap.add_argument("--tune", action="append", default=[], metavar="FIELD=VALUE",
@@ -420,8 +546,9 @@ def main():
                          "(reference for HBM byte counters), and print its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library computes one partition's local "
+              "product on one device and has no multi-GPU path; run it with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -457,67 +584,45 @@ def main():
         return
 
     w = workload(args.workload)
-    tdt = torch.float64 if w["dtype"] == "f64" else torch.float32
     vsize = 8 if w["dtype"] == "f64" else 4
-    dev = "cuda"
-    Ad = spg.DeviceCsc.from_host(w["A"], dtype=tdt, device=dev)
-    Bd = spg.DeviceCsc.from_host(w["Bi"], dtype=tdt, device=dev)
     stream = torch.cuda.current_stream()
-
-    ev = []  # (numeric start, numeric end) per instrumented step
-
     tun = spg.tuning(**{k: int(v) for k, v in (t.split("=", 1) for t in args.tune)}) \
         if args.tune else None
-
-    def step(record=False):
-        p = spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun)
-        p.symbolic()
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        rows, vals = p.numeric()
-        if record:
-            e1.record(stream)
-            ev.append((e0, e1))
-        p.close()
-        return rows, vals
+    run_step, st, keep = step_timer(spg, w, tun)
+    print(f"workload {w['desc']}: flops {st['flops']} nnz_C {st['nnz_C']}", file=sys.stderr,
+          flush=True)
 
     for _ in range(args.warmup):
-        step()
+        run_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        run_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    # the numeric phase inside steps, timed in extra steps outside the timed region
-    for _ in range(min(args.steps, 10)):
-        step(record=True)
-    torch.cuda.synchronize()
-    num_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
-    # sizes of the workload (from the library's own statistics), and the
-    # numeric phase alone: back-to-back launches on one plan between two
-    # events, so the launch gap of a lone call does not count
+    # phase times inside steps (extra steps, outside the timed region)
+    evs = [run_step(record=True) for _ in range(min(args.steps, 5))]
+    torch.cuda.synchronize()
+    ph = {name: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+          for i, name in enumerate(("plan", "symbolic", "numeric"))}
+
+    # the numeric phase alone (the step's dominant kernels): back-to-back
+    # launches on one plan between two HIP events on the launch stream
+    Ad, Bd = keep
+    reps = 10 if st["flops"] > 10 ** 8 else 50
     with spg.Plan(Ad, Bd, w["offs"], w["b"], tuning=tun) as p:
         p.symbolic()
         rows, vals = p.numeric()
-        st = p.stats()
-        loop_ms = _time_on(stream, lambda: p.numeric(out=(rows, vals)), 50)
+        loop_ms = _time_on(stream, lambda: p.numeric(out=(rows, vals)), reps)
+    del rows, vals
     flops = st["flops"]
     value = 2.0 * flops / (ms_per_step * 1e-3) / 1e9
-    num_bytes = (4 + vsize) * (st["nnz_B"] + st["nnz_At"] + st["nnz_C"]) + 8 * (st["n"] + 1)
-    achieved = num_bytes / (loop_ms * 1e-3) / 1e9
-    # what a plain device copy moving the same bytes (half read, half
-    # written) reaches at this size: the practical ceiling of a single
-    # launch of this volume, launch ramp included
-    half = max(1, num_bytes // 16)
-    csrc = torch.ones(half, dtype=torch.float64, device=dev)
-    cdst = torch.empty_like(csrc)
-    copy_ms = _time_on(stream, lambda: cdst.copy_(csrc), 50)
-    del csrc, cdst
+    byt = phase_bytes(st, vsize)
+    step_bytes = sum(byt.values())
+    achieved = byt["numeric"] / (loop_ms * 1e-3) / 1e9
+    traffic, trec = measured_traffic(w["desc"])
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -535,23 +640,38 @@ def main():
                    **({"tuning": dict(t.split("=", 1) for t in args.tune)} if args.tune else {})},
         "roofline": {
             "bound": "hbm",
-            "kernel": "numeric phase (spgemm_numeric)",
+            "kernel": "numeric phase (the k_num_* launches of one spgemm_numeric)",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(w["desc"]),
-            "algorithmic_bytes": int(num_bytes),
+            "traffic": traffic,
+            "traffic_note": trec if traffic is None else "rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                            "profiles/numeric_phase_hbm_traffic.md",
+            "algorithmic_bytes": int(byt["numeric"]),
             "avg_ms": round(loop_ms, 5),
-            "avg_ms_in_step": round(num_ms, 5),
-            "plain_copy_same_bytes": {
-                "ms": round(copy_ms, 5),
-                "GBps": round(16 * half / (copy_ms * 1e-3) / 1e9, 1)},
+            "avg_ms_in_step": round(ph["numeric"], 5),
+        },
+        "roofline_step": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "algorithmic_bytes": {k: int(v) for k, v in byt.items()},
+            "achieved": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+            "frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phase_ms": {k: round(v, 4) for k, v in ph.items()},
+            "phase_frac": {k: round(byt[k] / (ph[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                           for k in ph},
+            "GFLOPs_symbolic_plus_numeric": round(
+                2 * flops / ((ph["symbolic"] + ph["numeric"]) * 1e-3) / 1e9, 2),
         },
         "sizes": {"flops": flops, "nnz_C": st["nnz_C"], "nnz_At": st["nnz_At"], "kt": st["kt"],
                   "M": st["M"], "K": st["K"], "cv_memA": round(st["cv_memA"], 4),
-                  "num_bins": st["num_bins"]},
+                  "sym_bins": st["sym_bins"], "num_bins": st["num_bins"]},
     }
+    del keep, run_step, Ad, Bd
+    torch.cuda.synchronize()
+    if not args.no_side:
+        names = [n for n in ("rmat18-f32", "er65536", "lap2d", "sketch") if n != args.workload]
+        out["workloads"] = side_workloads(spg, names)
     if not args.no_forms:
         out["batched"] = bench_batched(spg)
         out["backward"] = bench_backward(spg)

@@ -12,6 +12,7 @@
  *   spgemm_numeric   values of C_i (rows ascending inside every column)
  *   spgemm_backward  (dC*B_i^T) o pattern(A) and (A^T*dC) o pattern(B_i)
  *   spgemm_batched   numeric of many planned products as one DAG (or one hipGraph)
+ *                    (spgemm_batch_create/run/destroy: the same with an explicit batch handle)
  *
  * Conventions for every entry point:
  *   - Matrices are CSC: colptr int64[ncols+1], rowidx int32[nnz] with row ids
@@ -266,29 +267,47 @@ typedef struct {
 typedef struct spgemm_batch_s *spgemm_batch_t;
 
 /*
- * Builds a batch over `count` distinct plans that have all finished
- * spgemm_symbolic and share one dtype.  Dependencies must point to lower
- * indices, and a product that reads another's C must name it (dep_A/dep_B)
- * and pass that C's value buffer as A_vals/B_vals.  Products of one
- * dependency depth run concurrently on up to tuning->batch_streams side
- * streams.  The io table is copied; plans and buffers must outlive the
- * batch.  Synchronises the plans' streams once.  Errors: EINVAL (bad table,
- * repeated plan), ESTATE (no symbolic), EUNSUPPORTED (batch_persistent != 0),
+ * spgemm_batched - the numeric phase of `count` planned products of one
+ * dtype, as one launch DAG on `stream`:
+ *   count    number of products (>= 1).
+ *   plans    HOST array of `count` distinct plans that have all finished
+ *            spgemm_symbolic.
+ *   io       HOST array of `count` entries: per product the value inputs, the
+ *            output buffers and the dependency indices (spgemm_batch_io).
+ *            Dependencies point to lower indices; a product that reads
+ *            another's C names it (dep_A/dep_B) and passes that C's value
+ *            buffer as A_vals/B_vals.
+ *   mode     0 enqueue the DAG's kernels directly;
+ *            1 capture the DAG into a hipGraph, instantiate it and launch it;
+ *            2 relaunch the graph captured by mode 1 for the same (plans, io)
+ *              table (SPGEMM_ESTATE if there is none).
+ *   stream   hipStream_t (NULL = null stream); side streams fork from it and
+ *            join back, so every product has finished when `stream` reaches
+ *            the end of the call.
+ * The library keeps one batch per distinct (plans, io) table (built with the
+ * default tuning on first use, so that call synchronises the plans'
+ * streams once) until one of its plans is destroyed.  Runs of one table
+ * must not overlap (they share the plans' A~ and scratch); work on the
+ * plans' own streams is not ordered with the batch.  Errors: EINVAL (bad
+ * table or mode, repeated plan), ESTATE (no symbolic, replay without
+ * capture), EHIP.
+ */
+int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
+                   int32_t mode, void *stream);
+
+/*
+ * The same batch with an explicit handle, for callers that choose its
+ * tuning (batch_streams) or its lifetime: spgemm_batch_create validates the
+ * table exactly as spgemm_batched does and synchronises the plans' streams
+ * once; spgemm_batch_run takes spgemm_batched's mode and stream; the io
+ * table is copied and the plans and buffers must outlive the batch.
+ * Errors of create: EINVAL, ESTATE, EUNSUPPORTED (batch_persistent != 0),
  * EHIP.
  */
 int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
                         const spgemm_tuning *tuning, spgemm_batch_t *out);
 
-/*
- * Runs the batch on `stream` (side streams fork from it and join back, so
- * every product has finished when `stream` reaches the end of the call):
- *   mode 0  enqueue the DAG's kernels directly;
- *   mode 1  capture the DAG into a hipGraph, instantiate it and launch it;
- *   mode 2  relaunch the instantiated graph (SPGEMM_ESTATE without mode 1).
- * Runs of one batch must not overlap (they share the plans' A~ and scratch).
- * Work on the plans' own streams is not ordered with the batch.
- */
-int spgemm_batched(spgemm_batch_t batch, int32_t mode, void *stream);
+int spgemm_batch_run(spgemm_batch_t batch, int32_t mode, void *stream);
 
 /* Side streams the batch uses, and kernels one run enqueues. */
 int spgemm_batch_info(spgemm_batch_t batch, int64_t *streams, int64_t *launches);

@@ -8,9 +8,9 @@ include/spgemm.h.  This package is the thin Python binding.
 
 from ._lib import SpgemmError, load  # noqa: F401
 from . import tune  # noqa: F401
-from .api import (DeviceCsc, HostCsc, Plan, SpGEMM, Batch, default_tuning, spgemm,  # noqa: F401
+from .api import (DeviceCsc, HostCsc, Plan, SpGEMM, Batch, batched, default_tuning, spgemm,  # noqa: F401
                   tuning, galerkin_chain, BIN_NAMES, row_block, sum_parts, outer_product)
 
-__all__ = ["DeviceCsc", "HostCsc", "Plan", "SpGEMM", "Batch", "SpgemmError", "default_tuning",
+__all__ = ["DeviceCsc", "HostCsc", "Plan", "SpGEMM", "Batch", "batched", "SpgemmError", "default_tuning",
            "spgemm", "tuning", "galerkin_chain", "load", "BIN_NAMES", "tune", "row_block",
            "sum_parts", "outer_product"]

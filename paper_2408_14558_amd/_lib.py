@@ -86,7 +86,9 @@ SIGNATURES = {
     "spgemm_plan_destroy": (ctypes.c_int, [_vp]),
     "spgemm_batch_create": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(BatchIO),
                                            ctypes.POINTER(Tuning), ctypes.POINTER(_vp)]),
-    "spgemm_batched": (ctypes.c_int, [_vp, _i32, _vp]),
+    "spgemm_batch_run": (ctypes.c_int, [_vp, _i32, _vp]),
+    "spgemm_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(BatchIO), _i32,
+                                      _vp]),
     "spgemm_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "spgemm_batch_check": (ctypes.c_int, [_vp]),
     "spgemm_batch_destroy": (ctypes.c_int, [_vp]),

@@ -270,10 +270,35 @@ class SpGEMM(torch.autograd.Function):
         return dA, dB, None
 
 
+def _io_table(io):
+    arr = (_lib.BatchIO * len(io))()
+    for t, d in enumerate(io):
+        arr[t].A_vals = _ptr(d.get("A_vals"))
+        arr[t].B_vals = _ptr(d.get("B_vals"))
+        arr[t].C_rowidx = _ptr(d["C_rowidx"])
+        arr[t].C_vals = _ptr(d["C_vals"])
+        arr[t].dep_A = int(d.get("dep_A", -1))
+        arr[t].dep_B = int(d.get("dep_B", -1))
+    return arr
+
+
+def batched(plans, io, mode: int = 0, stream=None):
+    """spgemm_batched(count, plans, io, mode, stream): the numeric phase of
+    the planned products as one launch DAG (mode 0), captured into a hipGraph
+    and launched (1), or that graph relaunched (2).  ``io`` as for
+    :class:`Batch`; the caller keeps its tensors alive while the library
+    keeps the batch (until one of the plans is closed)."""
+    lib = _lib.load()
+    plans = list(plans)
+    handles = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    check(lib.spgemm_batched(len(plans), handles, _io_table(io), mode, _stream(stream)),
+          "spgemm_batched")
+
+
 class Batch:
     """Numeric phase of many planned products as one dependency DAG of the
     per-bin kernels, optionally captured into a hipGraph and replayed
-    (spgemm_batch_create / spgemm_batched).
+    (spgemm_batch_create / spgemm_batch_run).
 
     ``io`` has one dict per plan with keys ``C_rowidx``, ``C_vals`` (output
     tensors), optional ``A_vals``/``B_vals`` (None = the plan's values) and
@@ -286,14 +311,7 @@ class Batch:
         self.plans = list(plans)
         self.io = [dict(x) for x in io]
         n = len(self.plans)
-        arr = (_lib.BatchIO * n)()
-        for t, d in enumerate(self.io):
-            arr[t].A_vals = _ptr(d.get("A_vals"))
-            arr[t].B_vals = _ptr(d.get("B_vals"))
-            arr[t].C_rowidx = _ptr(d["C_rowidx"])
-            arr[t].C_vals = _ptr(d["C_vals"])
-            arr[t].dep_A = int(d.get("dep_A", -1))
-            arr[t].dep_B = int(d.get("dep_B", -1))
+        arr = _io_table(self.io)
         handles = (ctypes.c_void_p * n)(*[p.handle for p in self.plans])
         h = ctypes.c_void_p()
         tun = ctypes.byref(tuning) if tuning is not None else None
@@ -304,7 +322,7 @@ class Batch:
     def run(self, mode: int = 0, stream=None):
         """mode 0: launch; 1: capture into a hipGraph and launch; 2: replay.
         Capture needs a stream other than the null stream."""
-        check(self.lib.spgemm_batched(self.handle, mode, _stream(stream)), "spgemm_batched")
+        check(self.lib.spgemm_batch_run(self.handle, mode, _stream(stream)), "spgemm_batch_run")
 
     def check(self):
         """Synchronises the device and raises if a launch failed."""

@@ -832,6 +832,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     Plan &p = *plan;
     // the scan's publish into the pinned block lands before the block is reused
     (void)finish_symbolic_counts(p);
+    batch_cache_drop(plan);
     pool_put(p.ws, p.ws_bytes, false, p.device, p.stream);
     // the pinned block's last device-side use is the counters copy that
     // counts_ready follows (later copies were waited for on the host)

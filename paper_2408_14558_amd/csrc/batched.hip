@@ -12,6 +12,7 @@
 // the kernels its plain spgemm_numeric call would run (value gather of A~
 // when new A values are given, then one launch per non-empty numeric bin).
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -92,6 +93,46 @@ static void release(spgemm_batch_s *b) {
     for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
     delete b;
 }
+
+// The batches spgemm_batched builds for itself, one per distinct (plans, io)
+// table, so a capture (mode 1) and its replays (mode 2) meet the same graph.
+// A batch is dropped when one of its plans is destroyed.
+namespace {
+struct CachedBatch {
+    std::vector<spgemm_plan_t> plans;
+    std::vector<spgemm_batch_io> io;
+    spgemm_batch_t batch;
+};
+std::mutex g_cache_mtx;
+std::vector<CachedBatch> g_cache;
+
+bool same_io(const spgemm_batch_io &a, const spgemm_batch_io &b) {
+    return a.A_vals == b.A_vals && a.B_vals == b.B_vals && a.C_rowidx == b.C_rowidx &&
+           a.C_vals == b.C_vals && a.dep_A == b.dep_A && a.dep_B == b.dep_B;
+}
+}  // namespace
+
+namespace spg {
+void batch_cache_drop(const Plan *plan) {
+    std::vector<spgemm_batch_t> gone;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mtx);
+        for (size_t i = 0; i < g_cache.size();) {
+            const auto &pl = g_cache[i].plans;
+            if (std::find(pl.begin(), pl.end(), plan) != pl.end()) {
+                gone.push_back(g_cache[i].batch);
+                g_cache.erase(g_cache.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
+    for (spgemm_batch_t b : gone) {
+        (void)hipDeviceSynchronize();
+        release(b);
+    }
+}
+}  // namespace spg
 
 extern "C" {
 
@@ -176,7 +217,7 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
     return SPGEMM_OK;
 }
 
-int spgemm_batched(spgemm_batch_t b, int32_t mode, void *stream) {
+int spgemm_batch_run(spgemm_batch_t b, int32_t mode, void *stream) {
     (void)hipGetLastError();
     if (!b) return fail(SPGEMM_EINVAL, "batch is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -211,6 +252,35 @@ int spgemm_batched(spgemm_batch_t b, int32_t mode, void *stream) {
         return SPGEMM_OK;
     }
     return fail(SPGEMM_EINVAL, "mode must be 0, 1 or 2");
+}
+
+int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
+                   int32_t mode, void *stream) {
+    (void)hipGetLastError();
+    if (count < 1 || !plans || !io) return fail(SPGEMM_EINVAL, "need count >= 1, plans and io");
+    if (mode < 0 || mode > 2) return fail(SPGEMM_EINVAL, "mode must be 0, 1 or 2");
+    spgemm_batch_t b = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mtx);
+        for (const CachedBatch &c : g_cache) {
+            if ((int32_t)c.plans.size() != count) continue;
+            bool same = true;
+            for (int32_t t = 0; t < count && same; ++t)
+                same = c.plans[t] == plans[t] && same_io(c.io[t], io[t]);
+            if (same) {
+                b = c.batch;
+                break;
+            }
+        }
+        if (!b) {
+            if (mode == 2)
+                return fail(SPGEMM_ESTATE, "replay needs a capture (mode 1) of the same table first");
+            if (int rc = spgemm_batch_create(count, plans, io, nullptr, &b)) return rc;
+            g_cache.push_back(CachedBatch{std::vector<spgemm_plan_t>(plans, plans + count),
+                                          std::vector<spgemm_batch_io>(io, io + count), b});
+        }
+    }
+    return spgemm_batch_run(b, mode, stream);
 }
 
 int spgemm_batch_info(spgemm_batch_t b, int64_t *streams, int64_t *launches) {

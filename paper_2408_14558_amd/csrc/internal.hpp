@@ -287,6 +287,8 @@ int launch_symbolic_reset(Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);
+// Drops (and frees) every batch spgemm_batched keeps that names this plan.
+void batch_cache_drop(const Plan *plan);
 
 }  // namespace spg
 

@@ -117,6 +117,17 @@ def column_slice(M: CSC, lo: int, hi: int) -> CSC:
                M.rowidx[a:b].copy(), M.vals[a:b].copy())
 
 
+def column_subset(M: CSC, cols) -> CSC:
+    """The chosen columns of M, in the given order."""
+    cols = np.asarray(cols, dtype=np.int64)
+    lens = M.colptr[cols + 1] - M.colptr[cols]
+    colptr = np.zeros(cols.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=colptr[1:])
+    idx = np.concatenate([np.arange(M.colptr[c], M.colptr[c + 1]) for c in cols]) \
+        if cols.size else np.zeros(0, np.int64)
+    return CSC(M.nrows, cols.size, colptr, M.rowidx[idx].copy(), M.vals[idx].copy())
+
+
 def transpose(M: CSC) -> CSC:
     """M^T in CSC (a stable counting sort of the entries by row)."""
     cols = np.repeat(np.arange(M.ncols, dtype=np.int64), np.diff(M.colptr))

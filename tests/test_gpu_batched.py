@@ -140,8 +140,8 @@ def test_batched_errors(workload):
     assert e.value.code == -4
     b = spg.Batch(plans[:2], io[:2])
     lib = spg.load()
-    assert lib.spgemm_batched(b.handle, 2, None) == -5  # replay before capture
-    assert lib.spgemm_batched(b.handle, 7, None) == -1
+    assert lib.spgemm_batch_run(b.handle, 2, None) == -5  # replay before capture
+    assert lib.spgemm_batch_run(b.handle, 7, None) == -1
     b.close()
     A = spg.DeviceCsc.from_host(synth.erdos_renyi(100, 100, 4, seed=1))
     p = spg.Plan(A, A)
@@ -189,3 +189,45 @@ def test_graph_replays_of_dense_queue_kernels():
         b.close()
         for p in plans:
             p.close()
+
+
+def test_spgemm_batched_by_table(workload):
+    """spgemm_batched(count, plans, io, mode, stream): mode 0 runs the table,
+    mode 1 captures and launches it, mode 2 replays that capture (with new
+    fine-level values propagating down the chain); a replay of a table that
+    was never captured is an ordering error."""
+    A0, plans, io, outs, er = workload
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for C in outs:
+            C.vals.fill_(-7.0)
+        spg.batched(plans, io, 0, stream=s)
+    s.synchronize()
+    _check_amg(outs)
+    _check_er(outs, er)
+    with torch.cuda.stream(s):
+        for C in outs:
+            C.vals.zero_()
+        spg.batched(plans, io, 1, stream=s)
+    s.synchronize()
+    _check_amg(outs)
+    for rep in range(2):
+        with torch.cuda.stream(s):
+            for C in outs:
+                C.vals.zero_()
+            A0.vals.mul_(2.0)
+            spg.batched(plans, io, 2, stream=s)
+        s.synchronize()
+        _check_amg(outs, scale=2.0 ** (rep + 1))
+    with torch.cuda.stream(s):
+        A0.vals.mul_(0.25)
+        spg.batched(plans, io, 2, stream=s)
+    s.synchronize()
+    _check_amg(outs)
+    _check_er(outs, er)
+    with pytest.raises(spg.SpgemmError) as e:  # this sub-table was never captured
+        spg.batched(plans[:2], io[:2], 2)
+    assert e.value.code == -5
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.batched(plans[:2], io[:2], 3)
+    assert e.value.code == -1
