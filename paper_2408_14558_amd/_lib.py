@@ -102,13 +102,17 @@ SIGNATURES = {
 _lib = None
 
 
-def load():
-    """Loads libspgemm.so once (or the build named by the SPGEMM_LIBRARY
-    environment variable); raises if it is missing."""
+def load(path: str = None):
+    """Loads the in-tree libspgemm.so once and returns it; raises if it is
+    missing.  `path` names another build of the same sources (for example one
+    compiled with different settings by build.build(out=...)); it is honoured
+    only by the first call of the process, and the product never passes it."""
     global _lib
     if _lib is not None:
+        if path is not None and getattr(_lib, "_name", None) != path:
+            raise RuntimeError(f"{_lib._name} is already loaded")
         return _lib
-    path = os.environ.get("SPGEMM_LIBRARY") or LIB_PATH
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: the HIP library is required "
                            "(build it with __graft_entry__.build())")

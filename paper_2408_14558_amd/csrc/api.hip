@@ -352,9 +352,17 @@ static int sync_counters(Plan &p) {
     return SPGEMM_OK;
 }
 
-// The flops total and the numeric bin counts of a symbolic run that returned
-// nnz(C_i) early (one-workgroup scan): waits for the scan's flag and reads
-// them from the pinned block.
+// Windows of dense columns reach A~ through the split table, which depends
+// on the patterns only: built once per plan, by the first numeric run (or
+// batch) that has dense columns.
+int ensure_split_table(Plan &p) {
+    if (p.split_ready || !p.split || p.num_count[kBinDense] + p.num_count[kBinDenseFirst] == 0)
+        return SPGEMM_OK;
+    if (int rc = launch_split_table(p)) return rc;
+    p.split_ready = true;
+    return SPGEMM_OK;
+}
+
 int finish_symbolic_counts(Plan &p) {
     if (!p.counts_pending) return SPGEMM_OK;
     SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
@@ -524,7 +532,8 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_nbin = cv.take<int32_t>(pl.n);
     const size_t o_slist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
-    const size_t o_cur = cv.take<int32_t>(pl.nnzB);
+    pl.nblk = pl.m <= kMaxDenseRows ? (int32_t)((pl.m + kSplitRows - 1) / kSplitRows) : 0;
+    const size_t o_split = cv.take<int32_t>(pl.nblk > 1 ? pl.k * (pl.nblk + 1) : 0);
     const size_t o_tst = cv.take<int64_t>(pl.nnzB);
     const size_t o_dsl = cv.take<int32_t>(pl.n);
     const size_t o_arr = cv.take<int32_t>(pl.n);
@@ -577,7 +586,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.num_bin = (int32_t *)(w + o_nbin);
     pl.sym_list = (int32_t *)(w + o_slist);
     pl.num_list = (int32_t *)(w + o_nlist);
-    pl.cursor = (int32_t *)(w + o_cur);
+    pl.split = pl.nblk > 1 ? (int32_t *)(w + o_split) : nullptr;
     pl.tstart = (int64_t *)(w + o_tst);
     pl.col_slot = (int32_t *)(w + o_dsl);
     pl.arrive = (int32_t *)(w + o_arr);
@@ -804,6 +813,7 @@ int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
     if (!A_vals && !p.Avals && p.nnzC > 0) return fail(SPGEMM_EINVAL, "no values for A");
     int rc;
     if (A_vals && (rc = launch_gather_values(p, A_vals))) return rc;
+    if ((rc = ensure_split_table(p))) return rc;
     return launch_numeric_bins(p, Bv, C_rowidx, C_vals);
 }
 

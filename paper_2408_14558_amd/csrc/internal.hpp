@@ -36,6 +36,15 @@ constexpr int kNumTable[4] = {256, 512, 2048, 4096};
 constexpr int64_t kMaxDenseRows = 1 << 18;  // 32 KiB bitmap
 constexpr int kDenseThreads = 1024;
 
+// Row blocks of the split table: the rows of C are cut into blocks of
+// kSplitRows, and for every column of A~ longer than a short entry the table
+// holds, per block border b, how many of the column's entries lie above row
+// b * kSplitRows.  A dense output column whose values do not fit in LDS at
+// once is computed in windows of whole blocks, and each window reaches
+// exactly its part of every long column of A~ through the table.
+constexpr int kSplitShift = 13;
+constexpr int64_t kSplitRows = int64_t(1) << kSplitShift;  // 256 bitmap words
+
 // Tiles of the chained scans.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
@@ -194,7 +203,12 @@ struct Plan {
     int32_t *num_bin = nullptr;
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
-    int32_t *cursor = nullptr;    // nnzB (numeric dense windows)
+    // split table: k x (nblk + 1) int32, rows of the columns of A that are
+    // long in A~ (built once per plan, by the first symbolic run that has
+    // dense columns); nblk = ceil(m / kSplitRows), 0 when m > kMaxDenseRows
+    int32_t *split = nullptr;
+    int32_t nblk = 0;
+    bool split_ready = false;
     // What the symbolic phase keeps for the numeric phase, per column: its
     // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
     int32_t *col_slot = nullptr;  // n
@@ -284,6 +298,8 @@ int launch_symbolic_bins(Plan &p, bool tiny_launched);
 int launch_colptr_scan(Plan &p);
 int finish_symbolic_counts(Plan &p);
 int launch_symbolic_reset(Plan &p);
+int launch_split_table(Plan &p);
+int ensure_split_table(Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);

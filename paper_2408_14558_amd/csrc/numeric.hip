@@ -123,9 +123,9 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
 
 template <typename V>
 static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
-    NumArgs<V> a{p.m,        p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, (const V *)p.At_vals,
-                 p.C_colptr, Crow,      Cval,           p.flop, p.cursor,    p.col_slot,
-                 p.dense_bits, p.tiny_perm};
+    NumArgs<V> a{p.m,         p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, (const V *)p.At_vals,
+                 p.C_colptr,  Crow,      Cval,           p.flop, p.Browidx,   p.split,
+                 p.col_slot,  p.dense_bits, p.tiny_perm};
     const int64_t n = p.n;
     auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
     if (p.num_count[kBinTiny] > 0)

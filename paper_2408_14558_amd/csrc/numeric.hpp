@@ -21,7 +21,8 @@ struct NumArgs {
     int32_t *Crow;
     V *Cval;
     const int64_t *flop;  // sparse flops per column (picks the wave-sort width)
-    int32_t *cursor;      // nnz(B_i) scratch for windowed dense columns
+    const int32_t *Browidx;      // B_i's row ids (the split table is indexed by them)
+    const int32_t *split;        // split table (windows of dense columns), see internal.hpp
     const int32_t *col_slot;     // per column: its slot in dense_bits or tiny_perm, or -1
     const uint32_t *dense_bits;  // row bitmaps kept by the symbolic phase
     const uint16_t *tiny_perm;   // sorted term order of tiny columns kept by the symbolic phase
@@ -415,12 +416,17 @@ constexpr int kDenseChunk = SPG_DENSE_CHUNK;
 // word's rank relative to its superblock of 2048 words (65536 rows), whose
 // absolute rank is in sbase, so ranks above 65535 need no 32-bit table.
 
+// Windows of one dense column computed at once (a column needing more is
+// done in several batches).
+constexpr int kWinBatch = 64;
+
 template <int G, typename V>
 struct NumDenseStatic {
-    TermStageCursor<kDenseChunk < G ? kDenseChunk : G, V> st;
+    TermStage<kDenseChunk < G ? kDenseChunk : G, V> st;
     int red[G / kWave + 2];
     int sbase[kMaxSuper];
-    int r_hi;
+    int win[kWinBatch][6];  // first block, end block, first rank, end rank, first row, end row
+    int nwin;
 };
 
 
@@ -444,18 +450,163 @@ __device__ __forceinline__ int32_t row_of_rank(const uint32_t *bits, const uint1
     return (lo << 5) + __ffs(w) - 1;
 }
 
-// G threads (the whole workgroup) compute column j.  VC values fit in LDS
-// at once; columns with more rows are done in windows of VC consecutive
-// ranks, each window resuming every entry's walk where the previous one
-// stopped.
+// Visits the terms of one window of a dense column: rows [rlo, rhi) of C,
+// inside row blocks [b0, b1) of the split table (full: the whole column).
+// For every entry q of B(:,j), a long column of A~ (more than kShortLen
+// entries) is cut to its part in the window's blocks by the split table
+// (no cut when full); a short one is taken whole.  Every term whose row lies
+// in [rlo, rhi) gets ap(row, a_ik, b_kj), each exactly once: the blocks
+// cover the window's rows, and rows outside it (the rest of a short column,
+// the part of a block outside a window that splits it) are skipped.
+// Segments of at most kShortLen terms form one flat list over the group;
+// longer ones are walked by whole waves in pieces of U*64 claimed from a
+// per-entry counter, with row ids and values loaded together.
+template <int G, typename V, int U, int CH, typename AP>
+__device__ __forceinline__ void for_each_window_term(
+    int64_t q0, int64_t q1, bool full, int b0, int b1, int nblk, int32_t rlo, int32_t rhi,
+    TermRange tr, const int32_t *__restrict__ Browidx, const int32_t *__restrict__ split,
+    const V *__restrict__ Bvals, const int32_t *__restrict__ At_rowidx,
+    const V *__restrict__ At_vals, TermStage<CH, V> *st, int gt, AP &&ap) {
+    static_assert(G > kWave && CH <= G && G <= kMaxGroupWaves * kWave, "group and chunk sizes");
+    const int team = gt / kWave, tl = lane_id();
+    auto inside = [&](int32_t r) { return r >= rlo && r < rhi; };
+    for (int64_t qb = q0; qb < q1; qb += CH) {
+        if (gt == 0) {
+            st->nlong = 0;
+            st->qnext = 0;
+        }
+        group_sync<G>();
+        const int64_t q = qb + gt;
+        long long start = 0;
+        int len = 0;
+        V bv = V(0);
+        if (gt < CH && q < q1) {
+            len = tr.len[q];
+            if (len > 0) {
+                start = tr.start[q];
+                bv = Bvals[q];
+                if (!full && len > kShortLen) {
+                    const int32_t *sp = split + (int64_t)Browidx[q] * (nblk + 1);
+                    const int lo = b0 > 0 ? sp[b0] : 0;
+                    const int hi = b1 < nblk ? sp[b1] : len;
+                    start += lo;
+                    len = hi - lo;
+                }
+            }
+        }
+        if (len > kShortLen) {
+            const int slot = atomicAdd(&st->nlong, 1);
+            st->lstart[slot] = start;
+            st->lend[slot] = start + len;
+            st->lbv[slot] = bv;
+            st->lnext[slot] = 0;
+        }
+        int tot;
+        const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0), st->tmp, &tot);
+        const int ns = tot >> 16, nt = tot & 0xFFFF;
+        if (len > 0 && len <= kShortLen) {
+            const int slot = CH - ns + (sp >> 16);
+            st->lstart[slot] = start;
+            st->lbv[slot] = bv;
+            st->lnext[slot] = sp & 0xFFFF;
+        }
+        group_sync<G>();
+        const int nl = st->nlong;
+        constexpr int SU = short_unroll<G>();
+        for (int t0 = 0; t0 < nt; t0 += SU * G) {
+            int32_t r[SU];
+            V av[SU], b[SU];
+            // threads past the list's end load its last term again (in
+            // bounds, no divergent branch) and do not apply it
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int t = min(t0 + u * G + gt, nt - 1);
+                const int sl = short_slot<CH, V>(st, ns, t);
+                const long long pos = st->lstart[sl] + (t - st->lnext[sl]);
+                r[u] = At_rowidx[pos];
+                av[u] = At_vals[pos];
+                b[u] = st->lbv[sl];
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                if (t0 + u * G + gt < nt && inside(r[u])) ap(r[u], av[u], b[u]);
+        }
+        constexpr int PS = U * kWave;
+        auto walk = [&](int e) {
+            const long long s0 = st->lstart[e];
+            const int elen = (int)(st->lend[e] - s0);
+            const V b = st->lbv[e];
+            while (true) {
+                const int off = claim_piece<CH, V>(st, e, PS);
+                if (off >= elen) break;
+                // rows of 64 terms this piece holds (wave-uniform): a short
+                // last piece issues no loads past its end
+                const int nu = min(U, (elen - off + kWave - 1) / kWave);
+                int32_t r[U];
+                V av[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (u < nu) {
+                        const int p = off + u * kWave + tl;
+                        const long long at = s0 + min(p, elen - 1);  // in bounds
+                        r[u] = At_rowidx[at];
+                        av[u] = At_vals[at];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < nu && off + u * kWave + tl < elen && inside(r[u])) ap(r[u], av[u], b);
+            }
+        };
+        for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
+        auto lim = [&](int e) { return (int)(st->lend[e] - st->lstart[e]); };
+        for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
+             e = entry_with_work(st->lnext, nl, team, lim))
+            walk(e);
+        group_sync<G>();
+    }
+}
+
+// Writes the set rows of bitmap words [wb, we) whose ranks lie in
+// [r0, r0 + cnt) to out[0, cnt): every lane takes one word and stages its
+// rows at their ranks in LDS (stage, cnt ints), then the group copies them
+// out coalesced.  All G threads call; ends with a group barrier.
+template <int G>
+__device__ __forceinline__ void window_rows_out(const uint32_t *bits, const uint16_t *wpre,
+                                                const int *sbase, int wb, int we, int r0, int cnt,
+                                                int32_t *stage, int32_t *__restrict__ out) {
+    for (int w = wb + (int)threadIdx.x; w < we; w += G) {
+        uint32_t b = bits[w];
+        int rk = word_rank(wpre, sbase, w) - r0;
+        while (b) {
+            if (rk >= 0 && rk < cnt) stage[rk] = (w << 5) + __ffs(b) - 1;
+            ++rk;
+            b &= b - 1;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += G) out[i] = stage[i];
+    __syncthreads();
+}
+
+// G threads (the whole workgroup) compute column j.  The column's row
+// bitmap (kept by the symbolic phase, or built here) and the rank of every
+// word are held in LDS.  The column is done in windows of at most VC ranks:
+// a window covers as many consecutive row blocks of the split table as fit,
+// so it visits exactly the products whose rows it holds; a block with more
+// than VC rows of C is split into windows of VC ranks that skip the rows
+// outside.  One wave lays out the windows from the ranks at the block
+// borders; per window the group writes the window's row ids, accumulates
+// its values by rank in LDS and writes them.
 template <int G, typename V>
 __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
                                                  uint16_t *wpre, V *vals, int VC,
                                                  NumDenseStatic<G, V> &S) {
+    constexpr int CH = kDenseChunk < G ? kDenseChunk : G;
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
     const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    const int slot = a.col_slot[j];
+    const int slot = a.dense_bits ? a.col_slot[j] : -1;  // a kept bitmap, if this run kept them
     if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
         const uint32_t *src = a.dense_bits + (size_t)slot * nw;
         copy_words<G>(bits, src, nw);
@@ -463,42 +614,79 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     } else {
         zero_words<G>(bits, nw);
         __syncthreads();
-        for_each_term<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
+        for_each_term<G, V, kDenseUnroll, CH>(
             q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
             [&](int64_t p) { return a.At_rowidx[p]; },
             [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     }
-    const int cap = (int)(((size_t)VC * sizeof(V)) / sizeof(int32_t));
-    int32_t *stage = reinterpret_cast<int32_t *>(vals);
-    const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, stage, cap);
+    const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, nullptr, 0);
     const int64_t o = a.Ccolptr[j];
-    bitmap_rows_out<G>(bits, wpre, S.sbase, nw, total, stage, cap, a.Crow + o);
-    int32_t *cursor = a.cursor + q0;
-    for (int w0r = 0; w0r < total; w0r += VC) {
-        const int w1r = min(total, w0r + VC);
-        const int cnt = w1r - w0r;
-        for (int i = gt; i < cnt; i += G) vals[i] = V(0);
-        if (gt == 0)
-            S.r_hi = (w1r == total) ? (int32_t)a.m : row_of_rank(bits, wpre, S.sbase, nw, w1r);
-        __syncthreads();
-        if (cnt == total) {
-            for_each_term<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
-                q0, q1, a.tr, a.Bvals, &S.st, gt,
-                [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
-                [&](const RowVal<V> &t, V bv) {
-                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, t.r)], t.v * bv);
-                });
-        } else {
-            const int32_t rh = S.r_hi;
-            for_each_term_below<G, V, kDenseUnroll, (kDenseChunk < G ? kDenseChunk : G)>(
-                q0, q1, rh, w0r == 0, a.tr, a.Bvals, a.At_rowidx, cursor,
-                &S.st, gt, [&](int64_t p) { return a.At_vals[p]; },
-                [&](int32_t r, V av, V bv) {
-                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - w0r], av * bv);
-                });
+    constexpr int kBlockWords = (int)(kSplitRows >> 5);
+    const int nblk = (nw + kBlockWords - 1) / kBlockWords;  // at most 32 (m <= 2^18)
+    const int lane = lane_id();
+    int32_t *stage = reinterpret_cast<int32_t *>(vals);
+    for (int w0r = 0; w0r < total;) {
+        if (gt < kWave) {
+            // lane b holds the rank at the start of block b (b == nblk: total)
+            const int rb = lane < nblk ? word_rank(wpre, S.sbase, lane * kBlockWords)
+                                       : (lane == nblk ? total : 0x7fffffff);
+            int n = 0;
+            int r0 = w0r;
+            while (r0 < total && n < kWinBatch) {
+                // the last block starting at or before rank r0, then the
+                // last block border at most VC ranks further
+                const uint64_t m0 = __ballot(lane < nblk && rb <= r0);
+                const int b0 = 63 - __clzll((long long)m0);
+                const uint64_t m1 = __ballot(lane > b0 && lane <= nblk && rb - r0 <= VC);
+                int b1, r1;
+                if (m1) {
+                    b1 = 63 - __clzll((long long)m1);
+                    r1 = __shfl(rb, b1);
+                } else {  // block b0 alone holds more than VC rows of C
+                    b1 = b0 + 1;
+                    r1 = r0 + VC;
+                }
+                if (lane == 0) {
+                    int *wd = S.win[n];
+                    wd[0] = b0;
+                    wd[1] = b1;
+                    wd[2] = r0;
+                    wd[3] = r1;
+                    // rows of the window: block borders when the ranks sit on
+                    // them, else the rows holding ranks r0 and r1
+                    const int rb0 = word_rank(wpre, S.sbase, b0 * kBlockWords);
+                    const int rb1 = b1 < nblk ? word_rank(wpre, S.sbase, b1 * kBlockWords) : total;
+                    wd[4] = r0 == rb0 ? (b0 << kSplitShift)
+                                      : row_of_rank(bits, wpre, S.sbase, nw, r0);
+                    wd[5] = r1 == rb1 ? (int)min<int64_t>((int64_t)b1 << kSplitShift, a.m)
+                                      : row_of_rank(bits, wpre, S.sbase, nw, r1);
+                }
+                ++n;
+                r0 = r1;
+            }
+            if (lane == 0) S.nwin = n;
         }
-        for (int i = gt; i < cnt; i += G) a.Cval[o + w0r + i] = vals[i];
         __syncthreads();
+        const int nwin = S.nwin;
+        for (int wi = 0; wi < nwin; ++wi) {
+            const int wb0 = S.win[wi][0], wb1 = S.win[wi][1];
+            const int r0 = S.win[wi][2], r1 = S.win[wi][3];
+            const int32_t rlo = S.win[wi][4], rhi = S.win[wi][5];
+            const int cnt = r1 - r0;
+            window_rows_out<G>(bits, wpre, S.sbase, wb0 * kBlockWords,
+                               min(nw, wb1 * kBlockWords), r0, cnt, stage, a.Crow + o + r0);
+            for (int i = gt; i < cnt; i += G) vals[i] = V(0);
+            __syncthreads();
+            const bool full = r0 == 0 && r1 == total;
+            for_each_window_term<G, V, kDenseUnroll, CH>(
+                q0, q1, full, wb0, wb1, nblk, rlo, rhi, a.tr, a.Browidx, a.split, a.Bvals,
+                a.At_rowidx, a.At_vals, &S.st, gt, [&](int32_t r, V av, V bv) {
+                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - r0], av * bv);
+                });
+            for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = vals[i];
+            __syncthreads();
+            w0r = r1;
+        }
     }
 }
 

@@ -712,9 +712,43 @@ __global__ void k_symbolic_reset(DevCounters *__restrict__ ctr, uint64_t *__rest
     for (int64_t s = t; s < nstatus; s += blockDim.x) status[s] = 0;
 }
 
+// Split table: for every column c of A that is long in A~ (more than
+// kShortLen entries), split[c * (nblk + 1) + b] = the number of its entries
+// with row below b * kSplitRows, b = 0 .. nblk.  One wave per column; lane b
+// finds border b by a binary search over the column's ascending rows.
+__global__ __launch_bounds__(256) void k_split_table(int64_t k, int32_t nblk,
+                                                     const int64_t *__restrict__ col_start,
+                                                     const int32_t *__restrict__ col_len,
+                                                     const int32_t *__restrict__ At_rowidx,
+                                                     int32_t *__restrict__ split) {
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= k) return;
+    const int len = col_len[c];
+    if (len <= kShortLen) return;
+    const int32_t *rows = At_rowidx + col_start[c];
+    int32_t *out = split + c * (nblk + 1);
+    for (int b = lane_id(); b <= nblk; b += kWave) {
+        const int64_t border = (int64_t)b << kSplitShift;
+        int lo = 0, hi = len;  // first position whose row is at least the border
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rows[mid] < border) lo = mid + 1; else hi = mid;
+        }
+        out[b] = lo;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+int launch_split_table(Plan &p) {
+    if (!p.split || p.k == 0) return SPGEMM_OK;
+    hipLaunchKernelGGL(k_split_table, dim3((unsigned)((p.k + 3) / 4)), dim3(256), 0, p.stream,
+                       p.k, p.nblk, p.col_start, p.col_len, p.At_rowidx, p.split);
+    SPG_LAUNCHED("k_split_table");
+    return SPGEMM_OK;
+}
+
 int launch_symbolic_reset(Plan &p) {
     hipLaunchKernelGGL(k_symbolic_reset, dim3(1), dim3(256), 0, p.stream, p.ctr, p.st_colptr,
                        p.n_col_tiles);

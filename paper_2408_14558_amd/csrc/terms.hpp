@@ -32,14 +32,6 @@ struct TermStage {
     int tmp[kMaxGroupWaves + 2];  // scratch for a group scan of the caller
 };
 
-// The same plus what a windowed walk needs to resume every entry.
-template <int CH, typename V>
-struct TermStageCursor : TermStage<CH, V> {
-    int llen[CH];  // length of the entry's column of A~
-    int lq[CH];    // entry index relative to the column's first entry
-    int lcut[CH];  // offset from lstart of the first term at or past the window
-};
-
 constexpr int next_pow2_const(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -258,144 +250,6 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
                 }
             }
         }
-        group_sync<G>();
-    }
-}
-
-// Visits the terms of column j whose row is below r_hi and that no earlier
-// call visited: cursor[q - q0] keeps, per entry of B(:,j), how far the
-// entry's column of A~ has been walked (rows ascend, so each call resumes
-// where the previous one stopped).  first == true starts every cursor at 0.
-// For each such term: ap(row, ldv(p), bv).  G >= 64 (long entries are
-// walked by whole waves).
-template <int G, typename V, int U = kUnroll, int CH = G, typename LDV, typename AP>
-__device__ __forceinline__ void for_each_term_below(int64_t q0, int64_t q1, int32_t r_hi,
-                                                    bool first, TermRange tr,
-                                                    const V *__restrict__ Bvals,
-                                                    const int32_t *__restrict__ At_rowidx,
-                                                    int32_t *__restrict__ cursor,
-                                                    TermStageCursor<CH, V> *st, int gt,
-                                                    LDV &&ldv,
-                                                    AP &&ap) {
-    static_assert(G >= kWave, "teams are whole waves");
-    constexpr int NTEAM = G / kWave;
-    const int team = gt / kWave, tl = lane_id();
-    static_assert(CH <= G && G <= kMaxGroupWaves * kWave, "chunk and group sizes");
-    for (int64_t qb = q0; qb < q1; qb += CH) {
-        if (gt == 0) {
-            st->nlong = 0;
-            st->qnext = 0;
-        }
-        group_sync<G>();
-        const int64_t q = qb + gt;
-        int len = 0, rel = 0;
-        long long c0 = 0;
-        V bv = V(0);
-        if (gt < CH && q < q1) {
-            len = tr.len[q];
-            if (len > 0) {
-                c0 = tr.start[q];
-                rel = first ? 0 : cursor[q - q0];
-                bv = Bvals[q];
-            }
-        }
-        if (len > kShortLen && rel < len) {
-            const int slot = atomicAdd(&st->nlong, 1);
-            st->lstart[slot] = c0 + rel;
-            st->lend[slot] = c0 + len;
-            st->lbv[slot] = bv;
-            st->llen[slot] = len;
-            st->lq[slot] = (int)(q - q0);
-            st->lcut[slot] = len - rel;
-            st->lnext[slot] = 0;
-        }
-        // short entries: the unvisited rest of each is one run of a flat term
-        // list over the whole group; lcut counts the run's terms below r_hi
-        // (a prefix of the run, rows ascending)
-        const int rest = len <= kShortLen ? len - rel : 0;
-        int tot;
-        const int sp = group_excl_scan<G>(short_code(rest), st->tmp, &tot);
-        const int ns = tot >> 16, nt = tot & 0xFFFF;
-        if (rest > 0) {
-            const int slot = CH - ns + (sp >> 16);
-            st->lstart[slot] = c0 + rel;
-            st->lbv[slot] = bv;
-            st->lnext[slot] = sp & 0xFFFF;
-            st->llen[slot] = rel;
-            st->lq[slot] = (int)(q - q0);
-            st->lcut[slot] = 0;
-        }
-        group_sync<G>();
-        const int nl = st->nlong;
-        constexpr int SU = short_unroll<G>();
-        for (int t0 = 0; t0 < nt; t0 += SU * G) {
-            int32_t r[SU];
-            long long pos[SU];
-            int sl[SU];
-#pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                const int t = min(t0 + u * G + gt, nt - 1);
-                sl[u] = short_slot<CH, V>(st, ns, t);
-                pos[u] = st->lstart[sl[u]] + (t - st->lnext[sl[u]]);
-                r[u] = At_rowidx[pos[u]];
-                if (t0 + u * G + gt >= nt) r[u] = kNoRow;  // a repeat of the last term
-            }
-            V v[SU];
-#pragma unroll
-            for (int u = 0; u < SU; ++u)
-                if (r[u] < r_hi) v[u] = ldv((int64_t)pos[u]);
-#pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                if (r[u] < r_hi) {
-                    ap(r[u], v[u], st->lbv[sl[u]]);
-                    atomicAdd(&st->lcut[sl[u]], 1);
-                }
-            }
-        }
-        // long entries: a piece that meets r_hi sets the entry's cut (rows
-        // ascend inside an entry, so its later pieces hold nothing for this
-        // window)
-        constexpr int PS = U * kWave;
-        auto walk = [&](int e) {
-            const long long s0 = st->lstart[e];
-            const int len = (int)(st->lend[e] - s0);
-            const V b = st->lbv[e];
-            while (true) {
-                const int off = claim_piece<CH, V>(st, e, PS);
-                if (off >= st->lcut[e]) break;
-                int32_t r[U];
-                V v[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int p = off + u * kWave + tl;
-                    r[u] = p < len ? At_rowidx[s0 + p] : kNoRow;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (r[u] < r_hi) v[u] = ldv((int64_t)(s0 + off + u * kWave + tl));
-                int cnt = 0;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (r[u] < r_hi) ap(r[u], v[u], b);
-                    // the positions below r_hi are a prefix of the piece
-                    cnt += __popcll(__ballot(r[u] < r_hi));
-                }
-                if (off + cnt < min(len, off + PS)) {
-                    if (tl == 0) atomicMin(&st->lcut[e], off + cnt);
-                    break;
-                }
-            }
-        };
-        for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
-        auto lim = [&](int e) { return st->lcut[e]; };
-        for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
-             e = entry_with_work(st->lnext, nl, team, lim))
-            walk(e);
-        group_sync<G>();
-        if (gt >= CH - ns && gt < CH) cursor[st->lq[gt]] = st->llen[gt] + st->lcut[gt];
-        if (gt < nl)
-            cursor[st->lq[gt]] =
-                (int32_t)(st->lstart[gt] + st->lcut[gt] - (st->lend[gt] - st->llen[gt]));
         group_sync<G>();
     }
 }
