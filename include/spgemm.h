@@ -220,7 +220,9 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
  *
  * Requires spgemm_symbolic (SPGEMM_ESTATE otherwise) with the C_colptr it
  * filled still alive.  Can be re-run with new values on the same patterns.
- * Products are summed in an unspecified order (FP32 in FP32, FP64 in FP64).
+ * Products are summed in an unspecified order, in FP64 for both dtypes (a
+ * product of two FP32 values is exact in FP64); each FP32 entry is rounded
+ * once, when written.
  */
 int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
                    int32_t *C_rowidx, void *C_vals);

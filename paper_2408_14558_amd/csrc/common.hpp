@@ -345,6 +345,19 @@ __device__ __forceinline__ void zero_words(uint32_t *dst, int n) {
     for (int i = head + threadIdx.x; i < n; i += G) dst[i] = 0u;
 }
 
+// Position of element i of an LDS staging buffer of 32-bit words, XOR-
+// swizzled by its 32-word row: when every lane of a wave writes its own run
+// of consecutive elements (one run per bitmap word), runs that start a
+// multiple of 32 apart would all hit one LDS bank; swizzled they spread over
+// the banks.  A row of 32 elements stays a permutation of itself, so reading
+// 32 consecutive elements is conflict-free too.
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 5) & 31); }
+
+// The same for a buffer of 64-bit elements (two banks each, 16 to a row of
+// banks): accumulators whose indices a wave's lanes hit 8 or 16 apart
+// spread over the banks instead of piling on a few.
+__device__ __forceinline__ int swz64(int i) { return i ^ ((i >> 4) & 15); }
+
 __device__ __forceinline__ int next_pow2(int x) {
     int p = 1;
     while (p < x) p <<= 1;

@@ -11,7 +11,7 @@ template <typename V, int EMAX, bool kPacked>
 __global__ __launch_bounds__(256) void k_num_tiny(const int32_t *__restrict__ list, int count,
                                                   NumArgs<V> a) {
     __shared__ int s_rows[4][EMAX * kWave];
-    __shared__ V s_vals[4][EMAX * kWave];
+    __shared__ Acc s_vals[4][EMAX * kWave];
     const int wv = threadIdx.x >> 6;
     const int w = blockIdx.x * 4 + wv;
     if (w >= count) return;
@@ -54,12 +54,82 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
-    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
+    Acc *vals = reinterpret_cast<Acc *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
     // the columns with the most products (list `first`) go out first
     for (int w = queue_take(queue, &s_item); w < nfirst + count; w = queue_take(queue, &s_item))
         num_dense_column<kDenseThreads, V>(a, w < nfirst ? first[w] : list[w - nfirst], bits,
                                            wpre, vals, VC, S);
     queue_leave(queue);
+}
+
+// Row ids of the dense columns whose row bitmaps the symbolic phase kept,
+// one column per wave with no workgroup barrier: the wave streams the
+// column's bitmap 64 words at a time (a word per lane, kRowAhead rounds of
+// loads in flight), places each round's set rows by a wave scan of the bit
+// counts in its own LDS stage and writes them out coalesced, the running
+// count giving the next round's first position.  Columns whose values went
+// to a hash bin are skipped.
+constexpr int kRowThreads = 256;
+constexpr int kRowWaves = kRowThreads / kWave;
+constexpr int kRowAhead = 4;
+__global__ __launch_bounds__(kRowThreads) void k_dense_rows(
+    int count, const int32_t *__restrict__ list, const int32_t *__restrict__ num_bin, int nw,
+    const uint32_t *__restrict__ bits, const int64_t *__restrict__ Ccolptr,
+    int32_t *__restrict__ Crow) {
+    __shared__ int32_t stage[kRowWaves][kWave * 32];
+    const int wv = threadIdx.x / kWave, lane = lane_id();
+    int32_t *my = stage[wv];
+    for (int w = blockIdx.x * kRowWaves + wv; w < count; w += gridDim.x * kRowWaves) {
+        const int32_t j = list[w];
+        if (num_bin[j] < kBinDense) continue;  // the same for the whole wave
+        long long base = Ccolptr[j];
+        const uint32_t *src = bits + (size_t)w * nw;
+        // kRowAhead rounds of words per step, the next step's words loaded
+        // while this step's are expanded (loads without branches: past the
+        // end the last word again, masked; the copies into `cur` come after
+        // the work, so the wait for those loads does too)
+        uint32_t cur[kRowAhead];
+#pragma unroll
+        for (int d = 0; d < kRowAhead; ++d) cur[d] = src[min(d * kWave + lane, nw - 1)];
+        for (int s0 = 0; s0 < nw; s0 += kRowAhead * kWave) {
+            uint32_t nxt[kRowAhead];
+#pragma unroll
+            for (int d = 0; d < kRowAhead; ++d)
+                nxt[d] = src[min(s0 + (kRowAhead + d) * kWave + lane, nw - 1)];
+#pragma unroll
+            for (int d = 0; d < kRowAhead; ++d) {
+                const int wi = s0 + d * kWave + lane;
+                uint32_t word = wi < nw ? cur[d] : 0u;
+                const int pc = __popc(word);
+                const int incl = wave_incl_scan(pc);
+                const int n = __shfl(incl, kWave - 1);
+                int rk = incl - pc;
+                while (word) {
+                    my[swz(rk++)] = (wi << 5) + __ffs(word) - 1;
+                    word &= word - 1;
+                }
+                wave_sync();
+                // four LDS reads in flight before their stores
+                for (int i0 = 0; i0 < n; i0 += 4 * kWave) {
+                    int32_t v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u * kWave + lane;
+                        v[u] = my[swz(min(i, n - 1))];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u * kWave + lane;
+                        if (i < n) Crow[base + i] = v[u];
+                    }
+                }
+                wave_sync();
+                base += n;
+            }
+#pragma unroll
+            for (int d = 0; d < kRowAhead; ++d) cur[d] = nxt[d];
+        }
+    }
 }
 
 template <int G, typename V>
@@ -71,7 +141,7 @@ __global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ li
     const int nw = (int)((a.m + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
-    V *vals = reinterpret_cast<V *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
+    Acc *vals = reinterpret_cast<Acc *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
     num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, vcap, S);
 }
 
@@ -93,7 +163,8 @@ size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
                                    : sizeof(NumDenseStatic<kDenseThreads, float>);
     const size_t budget = (size_t)lds_max > stat + 1024 ? (size_t)lds_max - stat - 1024 : 0;
     const size_t vc_bytes = budget > head ? budget - head : 0;
-    const int VC = (int)std::max<size_t>(1, std::min<size_t>(vc_bytes / vsize, 1 << 20));
+    // a multiple of 16: the window's slots are swizzled in rows of 16
+    const int VC = (int)std::max<size_t>(16, std::min<size_t>(vc_bytes / vsize, 1 << 20) & ~(size_t)15);
     *VC_out = VC;
     return head + (size_t)VC * vsize;
 }
@@ -103,7 +174,7 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     const int cnt = p.num_count[bin];
     if (cnt <= 0) return SPGEMM_OK;
     size_t lds;
-    const bool fits = use_bitmap(p.m, T, sizeof(V), &lds);
+    const bool fits = use_bitmap(p.m, T, sizeof(Acc), &lds);
     const int mk = p.tun.medium_kernel;
     if ((mk == 0 && fits) || (mk == 2 && lds <= 96 * 1024)) {
         constexpr int GB = T <= 512 ? 128 : 256;
@@ -147,10 +218,21 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
             return fail(SPGEMM_EUNSUPPORTED,
                         "columns with more rows than the largest hash bin need m <= 262144");
         int VC;
-        size_t lds = dense_lds_bytes(p.m, sizeof(V), p.lds_max, &VC);
+        size_t lds = dense_lds_bytes(p.m, sizeof(Acc), p.lds_max, &VC);
         if (p.tun.dense_window > 0 && p.tun.dense_window < VC) {
-            lds -= (size_t)(VC - p.tun.dense_window) * sizeof(V);
+            lds -= (size_t)(VC - p.tun.dense_window) * sizeof(Acc);
             VC = p.tun.dense_window;
+        }
+        if (p.dense_bits && p.sym_count[kBinDense] > 0) {
+            const int nw = (int)((p.m + 31) / 32);
+            const unsigned rg = resident_groups((const void *)k_dense_rows, kRowThreads, 0,
+                                                p.device,
+                                                (p.sym_count[kBinDense] + kRowWaves - 1) /
+                                                    kRowWaves);
+            hipLaunchKernelGGL(k_dense_rows, dim3(rg), dim3(kRowThreads), 0, p.stream,
+                               p.sym_count[kBinDense], p.sym_list + (int64_t)kBinDense * n,
+                               p.num_bin, nw, p.dense_bits, p.C_colptr, Crow);
+            SPG_LAUNCHED("k_dense_rows");
         }
         const unsigned grid = resident_groups((const void *)k_num_dense<V>, kDenseThreads, lds,
                                               p.device, ndense);

@@ -8,6 +8,18 @@
 
 namespace spg {
 
+// Products are accumulated in LDS as doubles whatever the value type: an
+// FP32 product of two FP32 values is exact in FP64, and LDS atomic adds of
+// doubles run several times faster than those of floats on gfx950 (measured
+// on the R-MAT 18 term stream: 4.8 against 16.4 ms).  A column's values are
+// rounded to the value type once, when written.
+using Acc = double;
+
+template <typename V>
+__device__ __forceinline__ Acc prod(V a, V b) {
+    return (Acc)a * (Acc)b;
+}
+
 // Everything a numeric column routine needs about one product.
 template <typename V>
 struct NumArgs {
@@ -43,7 +55,7 @@ struct NumArgs {
 // they travel together instead of as a chain of round trips).
 template <int E, typename V, bool kPacked>
 __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0, int64_t q1,
-                                                int64_t o, int *s_rows, V *s_vals,
+                                                int64_t o, int *s_rows, Acc *s_vals,
                                                 const uint16_t *perm) {
     static_assert(E * kWave <= (1 << kSlotBits), "slot ids need kSlotBits bits");
     const int lane = lane_id();
@@ -56,7 +68,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
     V bv[E];
     wave_terms<E, V>(q0, q1, a.tr, a.Bvals, p, bv);
     int key[E];
-    V val[E];
+    Acc val[E];
     if (perm) {
         // the symbolic phase kept the sorted order of the slots: rows and
         // values wait in LDS by slot and are read back in that order.  Every
@@ -75,7 +87,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
         for (int r = 0; r < E; ++r) {
             const int slot = r * kWave + lane;
             s_rows[slot] = rw[r];
-            s_vals[slot] = av[r] * bv[r];
+            s_vals[slot] = prod(av[r], bv[r]);
         }
         wave_sync();
 #pragma unroll
@@ -83,9 +95,9 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
             const bool some = sl[r] != kNoSlot;
             const int at = some ? sl[r] : 0;
             const int rr = s_rows[at];
-            const V vv = s_vals[at];
+            const Acc vv = s_vals[at];
             key[r] = some ? rr : kNoRow;
-            val[r] = some ? vv : V(0);
+            val[r] = some ? vv : Acc(0);
         }
         wave_sync();  // every slot is read before the buffers are reused below
     } else {
@@ -101,8 +113,8 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         key[r] = kNoRow;
-        val[r] = V(0);
-        const V v = av[r] * bv[r];
+        val[r] = Acc(0);
+        const Acc v = prod(av[r], bv[r]);
         if constexpr (kPacked) {
             const int slot = r * kWave + lane;
             s_vals[slot] = v;
@@ -113,7 +125,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
         }
     }
     if constexpr (kPacked) {
-        wave_sort<E, false, V>(key, val);
+        wave_sort<E, false, Acc>(key, val);
         wave_sync();
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -124,7 +136,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
         }
         wave_sync();  // every value is read before the slots are reused below
     } else {
-        wave_sort<E, true, V>(key, val);
+        wave_sort<E, true, Acc>(key, val);
     }
     }
     const int prev_last = __shfl_up(key[E - 1], 1);
@@ -138,7 +150,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
     }
     const int incl = wave_incl_scan(nh);
     const int total = __shfl(incl, kWave - 1);
-    for (int e = lane; e < total; e += kWave) s_vals[e] = V(0);
+    for (int e = lane; e < total; e += kWave) s_vals[e] = Acc(0);
     wave_sync();
     int run = incl - nh - 1;
 #pragma unroll
@@ -154,7 +166,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
     wave_sync();
     for (int e = lane; e < total; e += kWave) {
         a.Crow[o + e] = s_rows[e];
-        a.Cval[o + e] = s_vals[e];
+        a.Cval[o + e] = (V)s_vals[e];
     }
     wave_sync();
 }
@@ -163,7 +175,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
 // kernel built for EMAX = 4 needs no registers for 8 terms per lane).
 template <typename V, int EMAX, bool kPacked>
 __device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j, int *s_rows,
-                                                  V *s_vals) {
+                                                  Acc *s_vals) {
     static_assert(EMAX == 4 || EMAX == 8, "EMAX is 4 or 8");
     // every per-column load at once
     const int64_t f = a.flop[j];
@@ -181,7 +193,7 @@ __device__ __forceinline__ void num_wave_dispatch(const NumArgs<V> &a, int32_t j
 template <int T, int G, typename V>
 struct NumHashLds {
     int keys[T];
-    V vals[T];
+    Acc vals[T];
     TermStage<G, V> st;
 };
 
@@ -194,7 +206,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     constexpr int SL = T / G;
     for (int s = gt; s < T; s += G) {
         L.keys[s] = -1;
-        L.vals[s] = V(0);
+        L.vals[s] = Acc(0);
     }
     group_sync<G>();
     for_each_term<G, V>(a.Bcolptr[j], a.Bcolptr[j + 1], a.tr, a.Bvals,
@@ -202,7 +214,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
                         [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                         [&](const RowVal<V> &t, V bv) {
                             const int32_t r = t.r;
-                            const V v = t.v * bv;
+                            const Acc v = prod(t.v, bv);
                             uint32_t h = hash_slot<T>(r);
                             while (true) {
                                 const int old = atomicCAS(&L.keys[h], -1, r);
@@ -215,7 +227,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
                         });
     // compaction: every thread lifts its slots into registers
     int kk[SL];
-    V vv[SL];
+    Acc vv[SL];
     int c = 0;
 #pragma unroll
     for (int i = 0; i < SL; ++i) {
@@ -251,7 +263,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
                 if ((a0 > a1) == up) {
                     L.keys[lo] = a1;
                     L.keys[hi] = a0;
-                    const V t0 = L.vals[lo];
+                    const Acc t0 = L.vals[lo];
                     L.vals[lo] = L.vals[hi];
                     L.vals[hi] = t0;
                 }
@@ -262,7 +274,7 @@ __device__ __forceinline__ void num_hash_column(const NumArgs<V> &a, int32_t j,
     const int64_t o = a.Ccolptr[j];
     for (int e = gt; e < nnz; e += G) {
         a.Crow[o + e] = L.keys[e];
-        a.Cval[o + e] = L.vals[e];
+        a.Cval[o + e] = (V)L.vals[e];
     }
     group_sync<G>();
 }
@@ -277,7 +289,8 @@ constexpr int kSuperShift = 11;
 constexpr int kMaxSuper = 16;
 
 // Fills wpre (and sbase), stages the row ids of ranks [0, cap) in stage[]
-// (LDS, int32) and returns the number of set bits.  Every wave takes a
+// (LDS, int32, at swz(rank); cap a multiple of 32) and returns the number of
+// set bits.  Every wave takes a
 // power-of-two range of consecutive words (at most 2048 when superblocks are
 // used, so every superblock starts a wave's range) and its lanes consecutive
 // words, so the LDS accesses are free of bank conflicts.  All G threads
@@ -313,7 +326,7 @@ __device__ __forceinline__ int bitmap_ranks(const uint32_t *bits, uint16_t *wpre
         if (w < we) {
             wpre[w] = (uint16_t)(rk - sb);
             while (b && rk < cap) {
-                stage[rk] = (w << 5) + __ffs(b) - 1;
+                stage[swz(rk)] = (w << 5) + __ffs(b) - 1;
                 ++rk;
                 b &= b - 1;
             }
@@ -346,14 +359,14 @@ __device__ __forceinline__ void bitmap_rows_out(const uint32_t *bits, const uint
                 int rk = word_rank(wpre, sbase, w);
                 if (rk >= r1 || rk + __popc(b) <= r0) continue;
                 while (b) {
-                    if (rk >= r0 && rk < r1) stage[rk - r0] = (w << 5) + __ffs(b) - 1;
+                    if (rk >= r0 && rk < r1) stage[swz(rk - r0)] = (w << 5) + __ffs(b) - 1;
                     ++rk;
                     b &= b - 1;
                 }
             }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < r1 - r0; i += G) out[r0 + i] = stage[i];
+        for (int i = threadIdx.x; i < r1 - r0; i += G) out[r0 + i] = stage[swz(i)];
         __syncthreads();
     }
 }
@@ -371,7 +384,7 @@ struct NumBitmapStatic {
 
 template <int G, typename V>
 __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
-                                                  uint16_t *wpre, V *vals, int vcap,
+                                                  uint16_t *wpre, Acc *vals, int vcap,
                                                   NumBitmapStatic<G, V> &S) {
     const int gt = threadIdx.x;
     const int nw = (int)((a.m + 31) >> 5);
@@ -382,21 +395,21 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
                         [&](int64_t p) { return a.At_rowidx[p]; },
                         [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
     // vals holds every value of the column: as int32 slots it stages the row ids
-    const int cap = vcap * (int)(sizeof(V) / sizeof(int32_t));
+    const int cap = vcap * (int)(sizeof(Acc) / sizeof(int32_t));
     int32_t *stage = reinterpret_cast<int32_t *>(vals);
     const int total = bitmap_ranks<G>(bits, wpre, nullptr, nw, S.red, stage, cap);
     const int64_t o = a.Ccolptr[j];
     bitmap_rows_out<G>(bits, wpre, nullptr, nw, total, stage, cap, a.Crow + o);
-    for (int i = gt; i < total; i += G) vals[i] = V(0);
+    for (int i = gt; i < total; i += G) vals[i] = Acc(0);
     __syncthreads();
     for_each_term<G, V>(q0, q1, a.tr, a.Bvals, &S.st, gt,
                         [&](int64_t p) { return RowVal<V>{a.At_rowidx[p], a.At_vals[p]}; },
                         [&](const RowVal<V> &t, V bv) {
                             const uint32_t w = bits[t.r >> 5];
                             const int rk = wpre[t.r >> 5] + __popc(w & ((1u << (t.r & 31)) - 1u));
-                            lds_atomic_add(&vals[rk], t.v * bv);
+                            lds_atomic_add(&vals[rk], prod(t.v, bv));
                         });
-    for (int i = gt; i < total; i += G) a.Cval[o + i] = vals[i];
+    for (int i = gt; i < total; i += G) a.Cval[o + i] = (V)vals[i];
     __syncthreads();
 }
 
@@ -450,6 +463,13 @@ __device__ __forceinline__ int32_t row_of_rank(const uint32_t *bits, const uint1
     return (lo << 5) + __ffs(w) - 1;
 }
 
+// b_kj of term u of a batch: one value for all of a long entry's terms, or
+// one per term (the flat list of short segments).
+template <typename V>
+__device__ __forceinline__ V pick(V b, int) { return b; }
+template <typename V, int N>
+__device__ __forceinline__ V pick(const V (&b)[N], int u) { return b[u]; }
+
 // Visits the terms of one window of a dense column: rows [rlo, rhi) of C,
 // inside row blocks [b0, b1) of the split table (full: the whole column).
 // For every entry q of B(:,j), a long column of A~ (more than kShortLen
@@ -470,6 +490,15 @@ __device__ __forceinline__ void for_each_window_term(
     static_assert(G > kWave && CH <= G && G <= kMaxGroupWaves * kWave, "group and chunk sizes");
     const int team = gt / kWave, tl = lane_id();
     auto inside = [&](int32_t r) { return r >= rlo && r < rhi; };
+    // applies the U terms of one lane of a piece at offset `off` of an entry
+    // of `elen` terms: ap gets the whole batch, so it can issue its LDS reads
+    // for all of them before it waits
+    auto ap_batch = [&](int off, int elen, const int32_t (&r)[U], const V (&av)[U], V b) {
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = off + u * kWave + tl < elen && inside(r[u]);
+        ap(r, av, b, ok);
+    };
     for (int64_t qb = q0; qb < q1; qb += CH) {
         if (gt == 0) {
             st->nlong = 0;
@@ -527,35 +556,46 @@ __device__ __forceinline__ void for_each_window_term(
                 av[u] = At_vals[pos];
                 b[u] = st->lbv[sl];
             }
+            bool ok[SU];
 #pragma unroll
-            for (int u = 0; u < SU; ++u)
-                if (t0 + u * G + gt < nt && inside(r[u])) ap(r[u], av[u], b[u]);
+            for (int u = 0; u < SU; ++u) ok[u] = t0 + u * G + gt < nt && inside(r[u]);
+            ap(r, av, b, ok);
         }
         constexpr int PS = U * kWave;
+        // a piece's row ids and values, loaded without branches (lanes past
+        // the entry's end load its last term again and do not apply it)
+        auto load = [&](long long s0, int elen, int off, int32_t (&r)[U], V (&av)[U]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long at = s0 + min(off + u * kWave + tl, elen - 1);
+                r[u] = At_rowidx[at];
+                av[u] = At_vals[at];
+            }
+        };
+        // the next piece is claimed and its loads are in flight while the
+        // current one is applied
         auto walk = [&](int e) {
             const long long s0 = st->lstart[e];
             const int elen = (int)(st->lend[e] - s0);
             const V b = st->lbv[e];
+            int off = claim_piece<CH, V>(st, e, PS);
+            if (off >= elen) return;
+            int32_t r[U];
+            V av[U];
+            load(s0, elen, off, r, av);
             while (true) {
-                const int off = claim_piece<CH, V>(st, e, PS);
-                if (off >= elen) break;
-                // rows of 64 terms this piece holds (wave-uniform): a short
-                // last piece issues no loads past its end
-                const int nu = min(U, (elen - off + kWave - 1) / kWave);
-                int32_t r[U];
-                V av[U];
+                const int nxt = claim_piece<CH, V>(st, e, PS);
+                int32_t r2[U];
+                V av2[U];
+                load(s0, elen, min(nxt, elen - 1), r2, av2);
+                ap_batch(off, elen, r, av, b);
+                if (nxt >= elen) break;
+                off = nxt;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (u < nu) {
-                        const int p = off + u * kWave + tl;
-                        const long long at = s0 + min(p, elen - 1);  // in bounds
-                        r[u] = At_rowidx[at];
-                        av[u] = At_vals[at];
-                    }
+                    r[u] = r2[u];
+                    av[u] = av2[u];
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (u < nu && off + u * kWave + tl < elen && inside(r[u])) ap(r[u], av[u], b);
             }
         };
         for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
@@ -579,13 +619,13 @@ __device__ __forceinline__ void window_rows_out(const uint32_t *bits, const uint
         uint32_t b = bits[w];
         int rk = word_rank(wpre, sbase, w) - r0;
         while (b) {
-            if (rk >= 0 && rk < cnt) stage[rk] = (w << 5) + __ffs(b) - 1;
+            if (rk >= 0 && rk < cnt) stage[swz(rk)] = (w << 5) + __ffs(b) - 1;
             ++rk;
             b &= b - 1;
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < cnt; i += G) out[i] = stage[i];
+    for (int i = threadIdx.x; i < cnt; i += G) out[i] = stage[swz(i)];
     __syncthreads();
 }
 
@@ -600,7 +640,7 @@ __device__ __forceinline__ void window_rows_out(const uint32_t *bits, const uint
 // its values by rank in LDS and writes them.
 template <int G, typename V>
 __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
-                                                 uint16_t *wpre, V *vals, int VC,
+                                                 uint16_t *wpre, Acc *vals, int VC,
                                                  NumDenseStatic<G, V> &S) {
     constexpr int CH = kDenseChunk < G ? kDenseChunk : G;
     const int gt = threadIdx.x;
@@ -673,17 +713,39 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
             const int r0 = S.win[wi][2], r1 = S.win[wi][3];
             const int32_t rlo = S.win[wi][4], rhi = S.win[wi][5];
             const int cnt = r1 - r0;
-            window_rows_out<G>(bits, wpre, S.sbase, wb0 * kBlockWords,
-                               min(nw, wb1 * kBlockWords), r0, cnt, stage, a.Crow + o + r0);
-            for (int i = gt; i < cnt; i += G) vals[i] = V(0);
+            if (slot < 0)  // kept columns have their rows written by k_dense_rows
+                window_rows_out<G>(bits, wpre, S.sbase, wb0 * kBlockWords,
+                                   min(nw, wb1 * kBlockWords), r0, cnt, stage, a.Crow + o + r0);
+            for (int i = gt; i < cnt; i += G) vals[swz64(i)] = Acc(0);
             __syncthreads();
             const bool full = r0 == 0 && r1 == total;
+            // per batch: every rank lookup's LDS reads first, then the adds
+            auto add = [&](const auto &r, const auto &av, const auto &bv, const auto &ok) {
+                constexpr int N = (int)(sizeof(ok) / sizeof(ok[0]));
+                constexpr int H = N < 4 ? N : 4;  // lookups in flight per step
+#pragma unroll
+                for (int h = 0; h < N; h += H) {
+                    uint32_t wb[H];
+                    int wr[H];
+#pragma unroll
+                    for (int u = 0; u < H; ++u) {
+                        const int w = (ok[h + u] ? r[h + u] : rlo) >> 5;
+                        wb[u] = bits[w];
+                        wr[u] = word_rank(wpre, S.sbase, w);
+                    }
+#pragma unroll
+                    for (int u = 0; u < H; ++u) {
+                        if (ok[h + u]) {
+                            const int rk = wr[u] + __popc(wb[u] & ((1u << (r[h + u] & 31)) - 1u));
+                            lds_atomic_add(&vals[swz64(rk - r0)], prod(av[h + u], pick(bv, h + u)));
+                        }
+                    }
+                }
+            };
             for_each_window_term<G, V, kDenseUnroll, CH>(
                 q0, q1, full, wb0, wb1, nblk, rlo, rhi, a.tr, a.Browidx, a.split, a.Bvals,
-                a.At_rowidx, a.At_vals, &S.st, gt, [&](int32_t r, V av, V bv) {
-                    lds_atomic_add(&vals[rank_of(bits, wpre, S.sbase, r) - r0], av * bv);
-                });
-            for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = vals[i];
+                a.At_rowidx, a.At_vals, &S.st, gt, add);
+            for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = (V)vals[swz64(i)];
             __syncthreads();
             w0r = r1;
         }

@@ -200,21 +200,33 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
                     if (t0 + u * G + gt < nt) ap(it[u], b[u]);
             }
             constexpr int PS = U * kWave;
+            // loads without branches (lanes past the entry's end load its
+            // last term again and do not apply it), and the next piece's
+            // loads in flight while the current piece is applied
+            auto load = [&](long long s0, int len, int off, Item (&it)[U]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    it[u] = ld((int64_t)(s0 + min(off + u * kWave + tl, len - 1)));
+            };
             auto walk = [&](int e) {
                 const long long s0 = st->lstart[e];
                 const int len = (int)(st->lend[e] - s0);
                 const V b = st->lbv[e];
+                int off = claim_piece<CH, V>(st, e, PS);
+                if (off >= len) return;
+                Item it[U];
+                load(s0, len, off, it);
                 while (true) {
-                    const int off = claim_piece<CH, V>(st, e, PS);
-                    if (off >= len) break;
-                    Item it[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (off + u * kWave + tl < len)
-                            it[u] = ld((int64_t)(s0 + off + u * kWave + tl));
+                    const int nxt = claim_piece<CH, V>(st, e, PS);
+                    Item it2[U];
+                    load(s0, len, min(nxt, len - 1), it2);
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         if (off + u * kWave + tl < len) ap(it[u], b);
+                    if (nxt >= len) break;
+                    off = nxt;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) it[u] = it2[u];
                 }
             };
             for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
