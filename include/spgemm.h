@@ -209,6 +209,29 @@ int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
 int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
 
 /*
+ * spgemm_symbolic_noalloc - spgemm_symbolic for callers that cannot allocate
+ * device or pinned memory once their plans exist (tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results, waits and
+ * errors as spgemm_symbolic; it calls no allocator.  What the symbolic phase
+ * keeps for the numeric phase (the sorted product order of every tiny
+ * column, the row bitmap of every dense column) goes to a fixed array of
+ * 64 MiB that the library holds on each device until the process ends,
+ * instead of pooled blocks.  Limits and sharing:
+ *   - SPGEMM_ENOMEM (with the byte count in spgemm_last_error) when the kept
+ *     data exceed 64 MiB: 1 KiB per tiny column (every column of a B_i with
+ *     at most 16384 columns) plus m/8 bytes per column with more flops than
+ *     the largest symbolic hash bin.  C_colptr is then undefined; the plan
+ *     accepts a later spgemm_symbolic.
+ *   - The plan's device must be current (SPGEMM_EINVAL otherwise).
+ *   - Every call on a device takes that device's array over: spgemm_numeric,
+ *     spgemm_backward and spgemm_batch_create/spgemm_batched then fail with
+ *     SPGEMM_ESTATE on a plan whose data an earlier call placed there, until
+ *     it runs a symbolic phase again.  Calls on one device whose work
+ *     overlaps in time (other streams, other threads) race on the array.
+ */
+int spgemm_symbolic_noalloc(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
+
+/*
  * spgemm_numeric - values of C_i = A * B_i.
  *
  *   A_vals    dtype[nnz(A)] new values of A on the planned pattern, or NULL

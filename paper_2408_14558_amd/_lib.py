@@ -81,6 +81,7 @@ SIGNATURES = {
     "spgemm_plan_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "spgemm_plan_export_bins": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "spgemm_symbolic": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "spgemm_symbolic_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "spgemm_numeric": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "spgemm_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "spgemm_plan_destroy": (ctypes.c_int, [_vp]),

@@ -336,14 +336,18 @@ static void reserve_tiny(Plan &p, int64_t cols) {
         p.tiny_perm = (uint16_t *)p.kept_tiny;
 }
 
-static void reserve_dense(Plan &p) {
+// Bytes of the kept row bitmaps of the dense columns.
+static size_t dense_part_bytes(const Plan &p) {
     const size_t nw = (size_t)((p.m + 31) / 32);
-    size_t dense = (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
+    return (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
+}
+
+static void reserve_dense(Plan &p) {
+    size_t dense = dense_part_bytes(p);
     const size_t tiny = p.tiny_perm ? p.kept_tiny_bytes : 0;
     if (dense > kDenseBitsMax || p.ws_bytes + tiny + dense > kept_limit(p)) dense = 0;
     p.dense_bits = nullptr;
-    if (dense && reserve_block(p, &p.kept, &p.kept_bytes, dense))
-        p.dense_bits = (uint32_t *)p.kept;
+    if (dense && reserve_block(p, &p.kept, &p.kept_bytes, dense)) p.dense_bits = (uint32_t *)p.kept;
 }
 
 static int sync_counters(Plan &p) {
@@ -352,6 +356,76 @@ static int sync_counters(Plan &p) {
     return SPGEMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The no-allocation symbolic phase (spgemm_symbolic_noalloc) keeps what the
+// symbolic phase hands to the numeric phase (the tiny columns' sort orders,
+// the dense columns' row bitmaps) in this array instead of pooled blocks.
+// Each device holds its own copy at its own address, taken once per device
+// with hipGetSymbolAddress; host code uses that address, never the name.
+// The array belongs to the last plan that ran spgemm_symbolic_noalloc on the
+// device (generation counter per device).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mtx;
+static std::vector<void *> g_scratch_ptr;     // per device
+static std::vector<uint64_t> g_scratch_gen;   // per device: the current owner's generation
+
+// Address of this device's array (the plan's device must be current) and a
+// new generation for the caller, who owns the array from now on.
+static int scratch_take(int device, void **ptr, uint64_t *gen) {
+    int cur = -1;
+    SPG_HIP(hipGetDevice(&cur));
+    if (cur != device)
+        return fail(SPGEMM_EINVAL, "the plan's device must be the current device");
+    std::lock_guard<std::mutex> lk(g_scratch_mtx);
+    if ((size_t)device >= g_scratch_ptr.size()) {
+        g_scratch_ptr.resize(device + 1, nullptr);
+        g_scratch_gen.resize(device + 1, 0);
+    }
+    if (!g_scratch_ptr[device]) {
+        void *addr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !addr) {
+            (void)hipGetLastError();
+            return fail(SPGEMM_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = addr;
+    }
+    *ptr = g_scratch_ptr[device];
+    *gen = ++g_scratch_gen[device];
+    return SPGEMM_OK;
+}
+
+// The plan's kept data lives in the device array and a later
+// spgemm_symbolic_noalloc on the device has taken the array over.
+static bool scratch_lost(const Plan &p) {
+    if (!p.kept_in_scratch) return false;
+    std::lock_guard<std::mutex> lk(g_scratch_mtx);
+    return (size_t)p.device >= g_scratch_gen.size() || g_scratch_gen[p.device] != p.scratch_gen;
+}
+
+int check_kept(const Plan &p) {
+    if (scratch_lost(p))
+        return fail(SPGEMM_ESTATE, "this plan's symbolic data sat in the no-allocation scratch, "
+                                   "which a later spgemm_symbolic_noalloc on the device has "
+                                   "taken over: run the symbolic phase again");
+    return SPGEMM_OK;
+}
+
+// Bytes of the tiny part for `cols` tiny columns (the kernels' 64*EMAX
+// product slots, 2 bytes each); 0 when the rows are too wide to pack.
+static size_t tiny_part_bytes(const Plan &p, int64_t cols) {
+    const size_t slots = p.th.tiny_max_flop <= 256 ? 256 : 512;
+    return p.m < kPackedRowLimit ? (size_t)cols * slots * 2 : 0;
+}
+
+
+// The flops total and the numeric bin counts of a symbolic run that returned
+// nnz(C_i) early (one-workgroup scan): waits for the scan's flag and reads
+// them from the pinned block.
 // Windows of dense columns reach A~ through the split table, which depends
 // on the patterns only: built once per plan, by the first numeric run (or
 // batch) that has dense columns.
@@ -726,7 +800,10 @@ int spgemm_plan_export_bins(spgemm_plan_t plan, int64_t *flop, int32_t *sym_bin,
     return SPGEMM_OK;
 }
 
-int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
+// The symbolic phase.  noalloc: what is kept for the numeric phase goes to
+// the device's scratch array (nothing is allocated; SPGEMM_ENOMEM when it
+// does not fit) instead of pooled blocks.
+static int symbolic_impl(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC, bool noalloc) {
     (void)hipGetLastError();  // drop errors left by other code on this thread
     if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
     if (!C_colptr || !nnzC) return fail(SPGEMM_EINVAL, "C_colptr and nnzC must not be NULL");
@@ -736,6 +813,23 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     if ((rc = finish_symbolic_counts(p))) return rc;
     p.C_colptr = C_colptr;
     p.symbolic_done = false;
+    p.kept_in_scratch = false;
+    p.tiny_perm = nullptr;
+    p.dense_bits = nullptr;
+    unsigned char *sbuf = nullptr;
+    if (noalloc && p.n > 0) {
+        void *addr = nullptr;
+        if ((rc = scratch_take(p.device, &addr, &p.scratch_gen))) return rc;
+        sbuf = (unsigned char *)addr;
+        p.kept_in_scratch = true;
+    }
+    // the tiny part at the start of the array, the dense part after it
+    auto scratch_tiny = [&](int64_t cols) {
+        const size_t t = tiny_part_bytes(p, cols);
+        p.tiny_perm = t ? (uint16_t *)sbuf : nullptr;
+        return t;
+    };
+    size_t tiny_bytes = 0;
     if (p.n == 0) {
         SPG_HIP(hipMemsetAsync(C_colptr, 0, sizeof(int64_t), p.stream));
         p.nnzC = 0;
@@ -751,7 +845,13 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     if (p.symbolic_runs++ == 0) {
         early = p.early_tiny;
         if (early) {
-            reserve_tiny(p, p.n);
+            if (noalloc) {
+                // sized for every column (the counts are not known yet): at
+                // most kEarlyTinyCols columns of 1 KiB, well inside the array
+                tiny_bytes = scratch_tiny(p.n);
+            } else {
+                reserve_tiny(p, p.n);
+            }
             if ((rc = launch_sym_tiny(p, true))) return rc;  // publishes the counts
         }
         SPG_HIP(wait_flag(p, kFlagCounts, [&] {
@@ -761,8 +861,20 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;
     }
-    if (!early) reserve_tiny(p, p.sym_count[kBinTiny]);
-    reserve_dense(p);
+    if (noalloc) {
+        if (!early) tiny_bytes = scratch_tiny(p.sym_count[kBinTiny]);
+        const size_t at = (tiny_bytes + 255) & ~(size_t)255;
+        const size_t dense = dense_part_bytes(p);
+        if (at + dense > kScratchBytes)
+            return fail(SPGEMM_ENOMEM,
+                        "spgemm_symbolic_noalloc needs " + std::to_string(at + dense) +
+                            " bytes of scratch for the kept sort orders and row bitmaps, above its " +
+                            std::to_string(kScratchBytes) + " bytes; use spgemm_symbolic");
+        p.dense_bits = dense ? (uint32_t *)(sbuf + at) : nullptr;
+    } else {
+        if (!early) reserve_tiny(p, p.sym_count[kBinTiny]);
+        reserve_dense(p);
+    }
     if ((rc = launch_symbolic_bins(p, early))) return rc;
     __atomic_store_n(p.hflags + kFlagColptr, 0u, __ATOMIC_RELEASE);
     // the one-workgroup scan stores nnz(C_i) + 1 ahead of the rest: return
@@ -798,6 +910,14 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
     return SPGEMM_OK;
 }
 
+int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
+    return symbolic_impl(plan, C_colptr, nnzC, false);
+}
+
+int spgemm_symbolic_noalloc(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC) {
+    return symbolic_impl(plan, C_colptr, nnzC, true);
+}
+
 int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
                    int32_t *C_rowidx, void *C_vals) {
     (void)hipGetLastError();  // drop errors left by other code on this thread
@@ -805,7 +925,7 @@ int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
     Plan &p = *plan;
     if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_numeric needs spgemm_symbolic first");
     int rc0;
-    if ((rc0 = finish_symbolic_counts(p))) return rc0;
+    if ((rc0 = check_kept(p)) || (rc0 = finish_symbolic_counts(p))) return rc0;
     if (p.nnzC > 0 && (!C_rowidx || !C_vals))
         return fail(SPGEMM_EINVAL, "C_rowidx and C_vals must not be NULL");
     const void *Bv = Bi_vals ? Bi_vals : p.Bvals;
@@ -825,7 +945,7 @@ int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *
     Plan &p = *plan;
     if (!p.symbolic_done) return fail(SPGEMM_ESTATE, "spgemm_backward needs spgemm_symbolic first");
     int rc0;
-    if ((rc0 = finish_symbolic_counts(p))) return rc0;
+    if ((rc0 = check_kept(p)) || (rc0 = finish_symbolic_counts(p))) return rc0;
     if (!dA_vals && !dB_vals) return SPGEMM_OK;
     const void *Av = A_vals ? A_vals : p.Avals;
     const void *Bv = Bi_vals ? Bi_vals : p.Bvals;

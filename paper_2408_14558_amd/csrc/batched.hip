@@ -158,6 +158,7 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         const std::string who = "product " + std::to_string(t);
         if (!p) return fail(SPGEMM_EINVAL, who + ": plan is NULL");
         if (!p->symbolic_done) return fail(SPGEMM_ESTATE, who + " has not run symbolic");
+        if (int rc = check_kept(*p)) return rc;
         if (int rc = finish_symbolic_counts(*p)) return rc;
         if (int rc = ensure_split_table(*p)) return rc;  // on the plan's stream, before the sync
         if (p->dtype != dt) return fail(SPGEMM_EINVAL, "plans must share one dtype");

@@ -218,6 +218,10 @@ struct Plan {
     void *kept_tiny = nullptr;      // pooled block holding tiny_perm
     size_t kept_tiny_bytes = 0;
     uint32_t *dense_bits = nullptr; // row bitmaps of the symbolic dense columns
+    // the two above point into the no-allocation scratch array of the device
+    // (spgemm_symbolic_noalloc), taken with generation scratch_gen
+    bool kept_in_scratch = false;
+    uint64_t scratch_gen = 0;
     uint16_t *tiny_perm = nullptr;  // sorted order of the terms of tiny columns
     int64_t *tstart = nullptr;    // nnzB: term range of every entry of B_i
     int32_t *tlen = nullptr;      // nnzB
@@ -300,6 +304,9 @@ int finish_symbolic_counts(Plan &p);
 int launch_symbolic_reset(Plan &p);
 int launch_split_table(Plan &p);
 int ensure_split_table(Plan &p);
+// SPGEMM_ESTATE when the plan's kept symbolic data sat in the no-allocation
+// scratch array and a later call has taken the array over.
+int check_kept(const Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);
