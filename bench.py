@@ -232,6 +232,24 @@ def bench_batched(spg, reps=20):
     graph_amg_ms = _time_on(s, lambda: b_amg.run(2, stream=s), reps)
     b.check()
     streams, launches = b.info()
+    # the persistent form (one launch per run) on the AMG chain, and on every
+    # product without dense columns against the stream DAG of the same table
+    persistent_tun = spg.tuning(batch_persistent=1)
+    p_amg = spg.Batch(plans[:8], io[:8], persistent_tun)
+    p_amg_ms = _time_on(s, lambda: p_amg.run(0, stream=s), reps)
+    p_amg.run(1, stream=s)
+    p_amg_graph_ms = _time_on(s, lambda: p_amg.run(2, stream=s), reps)
+    p_amg.check()
+    keep = [t for t, p in enumerate(plans)
+            if p.stats()["num_bins"][6] + p.stats()["num_bins"][7] == 0]
+    sub_plans, sub_io = [plans[t] for t in keep], [io[t] for t in keep]
+    p_all = spg.Batch(sub_plans, sub_io, persistent_tun)
+    p_all_ms = _time_on(s, lambda: p_all.run(0, stream=s), reps)
+    p_all.check()
+    d_all = spg.Batch(sub_plans, sub_io)
+    d_all.run(1, stream=s)
+    d_all_graph_ms = _time_on(s, lambda: d_all.run(2, stream=s), reps)
+    d_all.check()
     out = {
         "workload": "amg7pt64_4levels_plus_64er_f64",
         "products": len(plans), "launches": launches, "side_streams": streams,
@@ -242,10 +260,15 @@ def bench_batched(spg, reps=20):
         "graph_GFLOPs": round(2 * flops / (graph_ms * 1e-3) / 1e9, 2),
         "amg_only": {"products": 8, "flops": int(amg_flops), "plain_ms": round(plain_amg_ms, 4),
                      "graph_replay_ms": round(graph_amg_ms, 4),
-                     "speedup_vs_plain": round(plain_amg_ms / graph_amg_ms, 3)},
+                     "speedup_vs_plain": round(plain_amg_ms / graph_amg_ms, 3),
+                     "persistent_ms": round(p_amg_ms, 4),
+                     "persistent_graph_replay_ms": round(p_amg_graph_ms, 4),
+                     "persistent_speedup_vs_plain": round(plain_amg_ms / p_amg_ms, 3)},
+        "no_dense_table": {"products": len(keep), "persistent_ms": round(p_all_ms, 4),
+                           "dag_graph_replay_ms": round(d_all_graph_ms, 4)},
     }
-    b.close()
-    b_amg.close()
+    for x in (b, b_amg, p_amg, p_all, d_all):
+        x.close()
     for p in plans:
         p.close()
     return out

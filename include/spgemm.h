@@ -80,8 +80,10 @@ typedef struct {
                                    sort, 2 = LDS bitmap and rank */
     int32_t batch_streams;      /* batched: side streams independent products spread over
                                    (0 = 4, at most 8) */
-    int32_t batch_persistent;   /* must be 0: the single-launch persistent form of the
-                                   batch is switched off (SPGEMM_EUNSUPPORTED) */
+    int32_t batch_persistent;   /* batched: 0 = the stream DAG of per-bin kernels; 1 = one
+                                   persistent launch per run (products with tiny and hash
+                                   columns only: SPGEMM_EUNSUPPORTED when a product has
+                                   dense columns or tiny_max_flop > 256) */
     int32_t dense_first_flop;   /* dense output columns with at least this many products are
                                    handed out first (numeric bin 7), so the longest ones do
                                    not finish last; 0 = no such bin */
@@ -158,7 +160,11 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
                 const int64_t *a_part_offsets, int32_t P, int64_t block_size,
                 const spgemm_tuning *tuning, void *stream, spgemm_plan_t *out);
 
-/* Re-targets later calls on the plan to another stream (NULL = null stream). */
+/* Re-targets later calls on the plan to another stream (NULL = null stream).
+ * Work already enqueued on the old stream is ordered before the new
+ * stream's later work (an event wait), and counts a pending symbolic phase
+ * publishes are read first (which may wait for that phase).  EHIP on a
+ * failed event call. */
 int spgemm_plan_set_stream(spgemm_plan_t plan, void *stream);
 
 /* Synchronises the plan's stream and fills *stats (host struct). */
@@ -326,8 +332,16 @@ int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch
  * table exactly as spgemm_batched does and synchronises the plans' streams
  * once; spgemm_batch_run takes spgemm_batched's mode and stream; the io
  * table is copied and the plans and buffers must outlive the batch.
- * Errors of create: EINVAL, ESTATE, EUNSUPPORTED (batch_persistent != 0),
- * EHIP.
+ * With tuning.batch_persistent = 1 one run is ONE persistent launch: its
+ * workgroups take the products' work items (value-gather tiles of A~,
+ * numeric column groups) by an atomic ticket in dependency order and wait,
+ * bounded in time, for the completion flags of the items they read; the
+ * batch keeps a small control block (ticket, flags, error word) that the
+ * launch puts back to 0, so runs and graph replays of one batch must not
+ * overlap.  spgemm_batch_check then also reports (SPGEMM_EHIP) a run whose
+ * dependency wait ran out of time (its outputs are not valid).
+ * Errors of create: EINVAL, ESTATE, EUNSUPPORTED (batch_persistent = 1 and a
+ * product with dense columns or tiny_max_flop > 256), EHIP.
  */
 int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,
                         const spgemm_tuning *tuning, spgemm_batch_t *out);

@@ -208,10 +208,17 @@ class Plan:
             vals = torch.empty(self.nnzC, dtype=self.torch_dtype, device=self.device)
         else:
             rows, vals = out
-        if A_vals is not None or B_vals is not None:
-            for t, what in ((A_vals, "A_vals"), (B_vals, "B_vals")):
-                if t is not None and (t.dtype != self.torch_dtype or not t.is_contiguous()):
-                    raise ValueError(f"{what} must be contiguous {self.torch_dtype}")
+        # the library reads and writes these through raw device pointers
+        for t, what, dt, n in ((A_vals, "A_vals", self.torch_dtype, self.A.nnz),
+                               (B_vals, "B_vals", self.torch_dtype, self.Bi.nnz),
+                               (rows, "C_rowidx", torch.int32, self.nnzC),
+                               (vals, "C_vals", self.torch_dtype, self.nnzC)):
+            if t is None:
+                continue
+            if t.device != torch.device(self.device) or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{what} must be a contiguous {dt} tensor on {self.device}")
+            if t.numel() < n:
+                raise ValueError(f"{what} holds {t.numel()} elements, needs {n}")
         # addresses as plain ints (the argument types are void pointers)
         rc = self.lib.spgemm_numeric(self.handle,
                                      None if A_vals is None else A_vals.data_ptr(),

@@ -727,8 +727,25 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
 }
 
 int spgemm_plan_set_stream(spgemm_plan_t plan, void *stream) {
+    (void)hipGetLastError();
     if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
-    plan->stream = (hipStream_t)stream;
+    Plan &p = *plan;
+    const hipStream_t next = (hipStream_t)stream;
+    if (next == p.stream) return SPGEMM_OK;
+    // counts a symbolic phase publishes on the old stream are read before
+    // the switch (their fallback wait synchronises the stream they ran on),
+    // and the new stream's work starts after the old stream's
+    if (int rc = finish_symbolic_counts(p)) return rc;
+    hipEvent_t ev = nullptr;
+    SPG_HIP(take_event(&ev));
+    hipError_t e = hipEventRecord(ev, p.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mtx);
+        g_spare_events.push_back(ev);  // reusable once recorded again
+    }
+    if (e != hipSuccess) return fail(SPGEMM_EHIP, std::string("set_stream: ") + hipGetErrorString(e));
+    p.stream = next;
     return SPGEMM_OK;
 }
 

@@ -1,7 +1,8 @@
 // Batched numeric phase: the numeric work of many planned products (uneven
 // sizes, optionally chained like the two products of every AMG Galerkin
 // level) issued as one dependency DAG of the per-bin kernels, optionally
-// captured once into a hipGraph and replayed.
+// captured once into a hipGraph and replayed; or, with
+// tuning.batch_persistent = 1, as one persistent launch (persistent.hip).
 //
 // Products are ordered by dependency depth (a product's depth is one more
 // than the deepest product it reads).  Products of one depth are
@@ -36,6 +37,8 @@ struct spgemm_batch_s {
     std::vector<hipStream_t> side;         // default priority, non-blocking
     std::vector<hipEvent_t> fork, join;    // one fork event, one join event per side stream
     int64_t launches = 0;                  // kernels one run enqueues
+    bool persistent = false;               // one persistent launch per run
+    PersistentBatch pb;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -66,6 +69,7 @@ static int run_product(spgemm_batch_s &b, int t, hipStream_t s) {
 
 // Enqueues the whole DAG on s (eagerly, or into a capture that s is in).
 static int enqueue_dag(spgemm_batch_s &b, hipStream_t s) {
+    if (b.persistent) return persistent_launch(b.pb, s);
     for (const std::vector<int> &lvl : b.levels) {
         const int width = std::min<int>((int)b.side.size(), (int)lvl.size());
         if (width <= 1) {
@@ -91,6 +95,7 @@ static void release(spgemm_batch_s *b) {
     for (hipEvent_t e : b->fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
     for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    persistent_free(b->pb);
     delete b;
 }
 
@@ -145,10 +150,8 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
     spgemm_tuning tun;
     spgemm_default_tuning(&tun);
     if (tuning) tun = *tuning;
-    if (tun.batch_persistent != 0)
-        return fail(SPGEMM_EUNSUPPORTED,
-                    "the single-launch persistent batched kernel is switched off: its "
-                    "cross-workgroup dependency waits did not complete on MI355X");
+    if (tun.batch_persistent != 0 && tun.batch_persistent != 1)
+        return fail(SPGEMM_EINVAL, "batch_persistent must be 0 or 1");
     if (tun.batch_streams < 0 || tun.batch_streams > kMaxBatchStreams)
         return fail(SPGEMM_EINVAL, "batch_streams must be in 0..8");
     const spgemm_dtype dt = plans[0] ? plans[0]->dtype : SPGEMM_F64;
@@ -191,11 +194,27 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         b->levels[depth[t]].push_back(t);
         b->launches += product_launches(*plans[t], io[t]);
     }
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess && tun.batch_persistent) {
+        std::vector<Plan *> pv(plans, plans + count);
+        std::vector<spgemm_batch_io> iov(io, io + count);
+        // the products' symbolic phases (bin lists, counts) ran on the plans' streams
+        for (int t = 0; t < count && e == hipSuccess; ++t) e = hipStreamSynchronize(plans[t]->stream);
+        if (e == hipSuccess) {
+            if (int rc = persistent_build(pv, iov, b->levels, b->pb)) {
+                release(b);
+                return rc;
+            }
+            b->persistent = true;
+            b->launches = b->pb.nitems > 0 ? 1 : 0;
+            *out = b;
+            return SPGEMM_OK;
+        }
+    }
     size_t widest = 0;
     for (const auto &l : b->levels) widest = std::max(widest, l.size());
     const int nside = (int)std::min<size_t>(
         widest > 1 ? widest : 0, tun.batch_streams ? tun.batch_streams : kDefaultBatchStreams);
-    hipError_t e = hipGetDevice(&b->device);
     for (int i = 0; i < nside && e == hipSuccess; ++i) {
         hipStream_t st = nullptr;
         hipEvent_t ev = nullptr;
@@ -296,6 +315,13 @@ int spgemm_batch_check(spgemm_batch_t b) {
     (void)hipGetLastError();
     if (!b) return fail(SPGEMM_EINVAL, "batch is NULL");
     SPG_HIP(hipDeviceSynchronize());
+    if (b->persistent) {
+        unsigned err = 0;
+        if (int rc = persistent_error(b->pb, &err)) return rc;
+        if (err)
+            return fail(SPGEMM_EHIP, "a dependency wait of the persistent batch ran out of time; "
+                                     "its outputs are not valid (the error is cleared)");
+    }
     return SPGEMM_OK;
 }
 

@@ -310,6 +310,28 @@ int check_kept(const Plan &p);
 int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);
+// The single-launch form of a batch (persistent.hip): its work items,
+// per-product arguments and control block (ticket, exit count, error word,
+// one completion flag per item) in device memory.
+struct PersistentBatch {
+    int device = 0;
+    spgemm_dtype dtype = SPGEMM_F64;
+    void *items = nullptr;
+    void *prods = nullptr;
+    unsigned *ctr = nullptr;
+    size_t ctr_bytes = 0;
+    int nitems = 0;
+    int nprod = 0;
+    unsigned grid = 1;
+    long long wait_ticks = 0;  // bound of one dependency wait, in wall-clock ticks
+};
+int persistent_build(const std::vector<Plan *> &plans, const std::vector<spgemm_batch_io> &io,
+                     const std::vector<std::vector<int>> &levels, PersistentBatch &pb);
+int persistent_launch(const PersistentBatch &pb, hipStream_t s);
+// The batch's error word (1: a dependency wait ran out of time); synchronises.
+int persistent_error(const PersistentBatch &pb, unsigned *err);
+void persistent_free(PersistentBatch &pb);
+
 // Drops (and frees) every batch spgemm_batched keeps that names this plan.
 void batch_cache_drop(const Plan *plan);
 

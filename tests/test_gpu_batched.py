@@ -1,7 +1,8 @@
 """GPU tests of the batched form: the numeric phase of many planned products
 (the 64^3 AMG Galerkin hierarchy, four levels, chained; plus 64 independent
 ER products of uneven sizes) as one dependency DAG over side streams,
-directly and as a captured hipGraph replayed several times."""
+directly and as a captured hipGraph replayed several times; and the same
+table as one persistent launch (tuning.batch_persistent = 1)."""
 
 import numpy as np
 import pytest
@@ -134,10 +135,9 @@ def test_batched_errors(workload):
     with pytest.raises(spg.SpgemmError) as e:
         spg.Batch(plans[:2], io[:2], spg.tuning(batch_streams=9))
     assert e.value.code == -1
-    # the single-launch persistent form is switched off
     with pytest.raises(spg.SpgemmError) as e:
-        spg.Batch(plans[:2], io[:2], spg.tuning(batch_persistent=1))
-    assert e.value.code == -4
+        spg.Batch(plans[:2], io[:2], spg.tuning(batch_persistent=2))
+    assert e.value.code == -1
     b = spg.Batch(plans[:2], io[:2])
     lib = spg.load()
     assert lib.spgemm_batch_run(b.handle, 2, None) == -5  # replay before capture
@@ -172,6 +172,10 @@ def test_graph_replays_of_dense_queue_kernels():
     s = torch.cuda.Stream()
     for p in plans:
         p.set_stream(s)
+    # the persistent form takes tiny and hash columns only
+    with pytest.raises(spg.SpgemmError) as e:
+        spg.Batch(plans, io, spg.tuning(batch_persistent=1))
+    assert e.value.code == -4
     b = spg.Batch(plans, io)
     try:
         b.run(1, stream=s)
@@ -231,3 +235,63 @@ def test_spgemm_batched_by_table(workload):
     with pytest.raises(spg.SpgemmError) as e:
         spg.batched(plans[:2], io[:2], 3)
     assert e.value.code == -1
+
+
+def _no_dense(p):
+    st = p.stats()
+    return st["num_bins"][6] + st["num_bins"][7] == 0
+
+
+def test_persistent_batch_matches_plain(workload):
+    """tuning.batch_persistent = 1: the AMG chain and the ER products without
+    dense columns as ONE persistent launch (items by ticket in dependency
+    order, per-item completion flags, bounded waits).  Direct runs, a
+    capture and replays with new fine-level values give the plain results,
+    and the batch's error word stays clear."""
+    A0, plans, io, outs, er = workload
+    keep = [t for t, p in enumerate(plans) if _no_dense(p)]
+    assert keep[:8] == list(range(8))
+    print("persistent batch of", len(keep), "products", flush=True)
+    b = spg.Batch([plans[t] for t in keep], [io[t] for t in keep],
+                  spg.tuning(batch_persistent=1))
+    streams, launches = b.info()
+    assert streams == 0 and launches == 1
+
+    def check(scale=1.0):
+        _check_amg(outs, scale)
+        for t in keep[8:]:
+            A, B = er[t - 8]
+            ref = oracle.spgemm(A, B)
+            C = outs[t]
+            assert np.array_equal(C.rowidx.cpu().numpy(), ref.rowidx)
+            assert_values(C.vals.cpu().numpy(), ref.vals, ref.absvals, True)
+
+    s = torch.cuda.Stream()
+    try:
+        for rep in range(2):
+            with torch.cuda.stream(s):
+                for t in keep:
+                    outs[t].vals.fill_(-7.0)
+                    outs[t].rowidx.fill_(-1)
+                b.run(0, stream=s)
+            b.check()
+            check()
+        with torch.cuda.stream(s):
+            b.run(1, stream=s)
+        b.check()
+        check()
+        for rep in range(3):
+            with torch.cuda.stream(s):
+                for t in keep:
+                    outs[t].vals.zero_()
+                A0.vals.mul_(2.0)
+                b.run(2, stream=s)
+            b.check()
+            check(2.0 ** (rep + 1))
+        with torch.cuda.stream(s):
+            A0.vals.mul_(2.0 ** -3)
+            b.run(2, stream=s)
+        b.check()
+        check()
+    finally:
+        b.close()
