@@ -226,8 +226,12 @@ int spgemm_symbolic(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC);
  *   - SPGEMM_ENOMEM (with the byte count in spgemm_last_error) when the kept
  *     data exceed 64 MiB: 1 KiB per tiny column (every column of a B_i with
  *     at most 16384 columns) plus m/8 bytes per column with more flops than
- *     the largest symbolic hash bin.  C_colptr is then undefined; the plan
- *     accepts a later spgemm_symbolic.
+ *     the largest symbolic hash bin (m <= 2^18; taller plans keep no
+ *     bitmaps).  C_colptr is then undefined; the plan accepts a later
+ *     spgemm_symbolic.
+ *   - SPGEMM_ENOMEM for a plan of more than 2^18 rows with such columns
+ *     until one spgemm_symbolic run on it has built its split table
+ *     (4 * k * (ceil(m / 8192) + 1) bytes, kept by the plan).
  *   - The plan's device must be current (SPGEMM_EINVAL otherwise).
  *   - Every call on a device takes that device's array over: spgemm_numeric,
  *     spgemm_backward and spgemm_batch_create/spgemm_batched then fail with

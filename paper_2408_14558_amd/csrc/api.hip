@@ -338,6 +338,7 @@ static void reserve_tiny(Plan &p, int64_t cols) {
 
 // Bytes of the kept row bitmaps of the dense columns.
 static size_t dense_part_bytes(const Plan &p) {
+    if (p.m > kMaxDenseRows) return 0;  // banded columns rebuild their bitmaps
     const size_t nw = (size_t)((p.m + 31) / 32);
     return (size_t)p.sym_count[kBinDense] * nw * sizeof(uint32_t);
 }
@@ -426,12 +427,23 @@ static size_t tiny_part_bytes(const Plan &p, int64_t cols) {
 // The flops total and the numeric bin counts of a symbolic run that returned
 // nnz(C_i) early (one-workgroup scan): waits for the scan's flag and reads
 // them from the pinned block.
+static size_t split_table_bytes(const Plan &p) {
+    return sizeof(int32_t) * (size_t)p.k * (size_t)(p.nblk + 1);
+}
+
 // Windows of dense columns reach A~ through the split table, which depends
-// on the patterns only: built once per plan, by the first numeric run (or
-// batch) that has dense columns.
-int ensure_split_table(Plan &p) {
-    if (p.split_ready || !p.split || p.num_count[kBinDense] + p.num_count[kBinDenseFirst] == 0)
-        return SPGEMM_OK;
+// on the patterns only: built once per plan, by the first run that has dense
+// columns (numeric or batch; for m above 2^18 already the symbolic run, whose
+// bands need it, and the table is then taken from the pool).
+int ensure_split_table(Plan &p, int64_t dense_columns) {
+    if (dense_columns < 0) dense_columns = p.num_count[kBinDense] + p.num_count[kBinDenseFirst];
+    if (p.split_ready || dense_columns == 0 || p.nblk <= 1 || p.k == 0) return SPGEMM_OK;
+    if (!p.split) {
+        const size_t need = split_table_bytes(p);
+        if (!reserve_block(p, &p.split_block, &p.split_bytes, need))
+            return fail(SPGEMM_ENOMEM, "split table of " + std::to_string(need) + " bytes");
+        p.split = (int32_t *)p.split_block;
+    }
     if (int rc = launch_split_table(p)) return rc;
     p.split_ready = true;
     return SPGEMM_OK;
@@ -606,8 +618,12 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     const size_t o_nbin = cv.take<int32_t>(pl.n);
     const size_t o_slist = cv.take<int32_t>(kNumBins * pl.n);
     const size_t o_nlist = cv.take<int32_t>(kNumBins * pl.n);
-    pl.nblk = pl.m <= kMaxDenseRows ? (int32_t)((pl.m + kSplitRows - 1) / kSplitRows) : 0;
-    const size_t o_split = cv.take<int32_t>(pl.nblk > 1 ? pl.k * (pl.nblk + 1) : 0);
+    pl.nblk = (int32_t)((pl.m + kSplitRows - 1) / kSplitRows);
+    // the table of a plan of at most 2^18 rows sits in the workspace; a
+    // taller one is taken from the pool when a symbolic run first meets a
+    // dense column
+    const bool split_in_ws = pl.nblk > 1 && pl.m <= kMaxDenseRows;
+    const size_t o_split = cv.take<int32_t>(split_in_ws ? pl.k * (pl.nblk + 1) : 0);
     const size_t o_tst = cv.take<int64_t>(pl.nnzB);
     const size_t o_dsl = cv.take<int32_t>(pl.n);
     const size_t o_arr = cv.take<int32_t>(pl.n);
@@ -660,7 +676,7 @@ int spgemm_plan(const spgemm_csc *A, const spgemm_csc *Bi, spgemm_dtype dtype,
     pl.num_bin = (int32_t *)(w + o_nbin);
     pl.sym_list = (int32_t *)(w + o_slist);
     pl.num_list = (int32_t *)(w + o_nlist);
-    pl.split = pl.nblk > 1 ? (int32_t *)(w + o_split) : nullptr;
+    pl.split = split_in_ws ? (int32_t *)(w + o_split) : nullptr;
     pl.tstart = (int64_t *)(w + o_tst);
     pl.col_slot = (int32_t *)(w + o_dsl);
     pl.arrive = (int32_t *)(w + o_arr);
@@ -888,6 +904,13 @@ static int symbolic_impl(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC, b
                             " bytes of scratch for the kept sort orders and row bitmaps, above its " +
                             std::to_string(kScratchBytes) + " bytes; use spgemm_symbolic");
         p.dense_bits = dense ? (uint32_t *)(sbuf + at) : nullptr;
+        // the bands of a tall plan's dense columns need the split table,
+        // which this entry point cannot allocate
+        if (p.m > kMaxDenseRows && p.sym_count[kBinDense] > 0 && !p.split)
+            return fail(SPGEMM_ENOMEM,
+                        "a plan of more than 262144 rows with dense columns needs its split "
+                        "table (" + std::to_string(split_table_bytes(p)) +
+                            " bytes), which one spgemm_symbolic run builds first");
     } else {
         if (!early) reserve_tiny(p, p.sym_count[kBinTiny]);
         reserve_dense(p);
@@ -986,6 +1009,7 @@ int spgemm_plan_destroy(spgemm_plan_t plan) {
     pool_put(p.pinned, p.pinned_bytes, true, p.device, p.stream, p.counts_ready);
     pool_put(p.kept, p.kept_bytes, false, p.device, p.stream);
     pool_put(p.kept_tiny, p.kept_tiny_bytes, false, p.device, p.stream);
+    pool_put(p.split_block, p.split_bytes, false, p.device, p.stream);
     delete plan;
     return SPGEMM_OK;
 }

@@ -32,8 +32,9 @@ enum Bin : int {
 constexpr int kSymTable[4] = {256, 1024, 4096, 8192};
 constexpr int kNumTable[4] = {256, 512, 2048, 4096};
 
-// Dense-bin limits: the bitmap covers every row of C in LDS.
-constexpr int64_t kMaxDenseRows = 1 << 18;  // 32 KiB bitmap
+// Rows of C one pass of a dense column holds as a bitmap in LDS (32 KiB);
+// a taller column is done in bands of this many rows, one after another.
+constexpr int64_t kMaxDenseRows = 1 << 18;
 constexpr int kDenseThreads = 1024;
 
 // Row blocks of the split table: the rows of C are cut into blocks of
@@ -204,11 +205,14 @@ struct Plan {
     int32_t *sym_list = nullptr;  // kNumBins x n
     int32_t *num_list = nullptr;  // kNumBins x n
     // split table: k x (nblk + 1) int32, rows of the columns of A that are
-    // long in A~ (built once per plan, by the first symbolic run that has
-    // dense columns); nblk = ceil(m / kSplitRows), 0 when m > kMaxDenseRows
+    // long in A~ (built once per plan, by the first run that has dense
+    // columns); nblk = ceil(m / kSplitRows).  In the workspace for m up to
+    // kMaxDenseRows, else a pool block (split_block) taken when needed.
     int32_t *split = nullptr;
     int32_t nblk = 0;
     bool split_ready = false;
+    void *split_block = nullptr;
+    size_t split_bytes = 0;
     // What the symbolic phase keeps for the numeric phase, per column: its
     // slot in dense_bits (dense columns) or in tiny_perm (tiny columns), or -1
     int32_t *col_slot = nullptr;  // n
@@ -303,7 +307,8 @@ int launch_colptr_scan(Plan &p);
 int finish_symbolic_counts(Plan &p);
 int launch_symbolic_reset(Plan &p);
 int launch_split_table(Plan &p);
-int ensure_split_table(Plan &p);
+// dense_columns < 0: the numeric dense bins' count.
+int ensure_split_table(Plan &p, int64_t dense_columns = -1);
 // SPGEMM_ESTATE when the plan's kept symbolic data sat in the no-allocation
 // scratch array and a later call has taken the array over.
 int check_kept(const Plan &p);

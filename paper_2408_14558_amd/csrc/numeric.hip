@@ -51,7 +51,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ NumDenseStatic<kDenseThreads, V> S;
     __shared__ int s_item;
-    const int nw = (int)((a.m + 31) >> 5);
+    // the bitmap of one band: all m rows, or kMaxDenseRows of a taller column
+    const int nw = (int)((min<int64_t>(a.m, kMaxDenseRows) + 31) >> 5);
     uint32_t *bits = reinterpret_cast<uint32_t *>(s_dyn);
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + nw);
     Acc *vals = reinterpret_cast<Acc *>(s_dyn + (((size_t)nw * 6 + 15) & ~(size_t)15));
@@ -196,7 +197,7 @@ template <typename V>
 static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
     NumArgs<V> a{p.m,         p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, (const V *)p.At_vals,
                  p.C_colptr,  Crow,      Cval,           p.flop, p.Browidx,   p.split,
-                 p.col_slot,  p.dense_bits, p.tiny_perm};
+                 p.col_slot,  p.dense_bits, p.tiny_perm, p.nblk};
     const int64_t n = p.n;
     auto list = [&](int bin) { return p.num_list + (int64_t)bin * n; };
     if (p.num_count[kBinTiny] > 0)
@@ -214,11 +215,9 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
     if ((rc = num_hash_launch<kNumTable[3], kNumTable[3] / 8, V>(p, kBinH3, a))) return rc;
     const int ndense = p.num_count[kBinDense] + p.num_count[kBinDenseFirst];
     if (ndense > 0) {
-        if (p.m > kMaxDenseRows)
-            return fail(SPGEMM_EUNSUPPORTED,
-                        "columns with more rows than the largest hash bin need m <= 262144");
-        int VC;
-        size_t lds = dense_lds_bytes(p.m, sizeof(Acc), p.lds_max, &VC);
+        int VC;  // a column of more than kMaxDenseRows rows is done in bands
+        size_t lds = dense_lds_bytes(std::min<int64_t>(p.m, kMaxDenseRows), sizeof(Acc),
+                                     p.lds_max, &VC);
         if (p.tun.dense_window > 0 && p.tun.dense_window < VC) {
             lds -= (size_t)(VC - p.tun.dense_window) * sizeof(Acc);
             VC = p.tun.dense_window;

@@ -38,6 +38,7 @@ struct NumArgs {
     const int32_t *col_slot;     // per column: its slot in dense_bits or tiny_perm, or -1
     const uint32_t *dense_bits;  // row bitmaps kept by the symbolic phase
     const uint16_t *tiny_perm;   // sorted term order of tiny columns kept by the symbolic phase
+    int32_t nblk;                // row blocks of the split table (its stride is nblk + 1)
 };
 
 // --- wave sort: <= 64*E terms, one wave, registers ---------------------------
@@ -470,156 +471,20 @@ __device__ __forceinline__ V pick(V b, int) { return b; }
 template <typename V, int N>
 __device__ __forceinline__ V pick(const V (&b)[N], int u) { return b[u]; }
 
-// Visits the terms of one window of a dense column: rows [rlo, rhi) of C,
-// inside row blocks [b0, b1) of the split table (full: the whole column).
-// For every entry q of B(:,j), a long column of A~ (more than kShortLen
-// entries) is cut to its part in the window's blocks by the split table
-// (no cut when full); a short one is taken whole.  Every term whose row lies
-// in [rlo, rhi) gets ap(row, a_ik, b_kj), each exactly once: the blocks
-// cover the window's rows, and rows outside it (the rest of a short column,
-// the part of a block outside a window that splits it) are skipped.
-// Segments of at most kShortLen terms form one flat list over the group;
-// longer ones are walked by whole waves in pieces of U*64 claimed from a
-// per-entry counter, with row ids and values loaded together.
-template <int G, typename V, int U, int CH, typename AP>
-__device__ __forceinline__ void for_each_window_term(
-    int64_t q0, int64_t q1, bool full, int b0, int b1, int nblk, int32_t rlo, int32_t rhi,
-    TermRange tr, const int32_t *__restrict__ Browidx, const int32_t *__restrict__ split,
-    const V *__restrict__ Bvals, const int32_t *__restrict__ At_rowidx,
-    const V *__restrict__ At_vals, TermStage<CH, V> *st, int gt, AP &&ap) {
-    static_assert(G > kWave && CH <= G && G <= kMaxGroupWaves * kWave, "group and chunk sizes");
-    const int team = gt / kWave, tl = lane_id();
-    auto inside = [&](int32_t r) { return r >= rlo && r < rhi; };
-    // applies the U terms of one lane of a piece at offset `off` of an entry
-    // of `elen` terms: ap gets the whole batch, so it can issue its LDS reads
-    // for all of them before it waits
-    auto ap_batch = [&](int off, int elen, const int32_t (&r)[U], const V (&av)[U], V b) {
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) ok[u] = off + u * kWave + tl < elen && inside(r[u]);
-        ap(r, av, b, ok);
-    };
-    for (int64_t qb = q0; qb < q1; qb += CH) {
-        if (gt == 0) {
-            st->nlong = 0;
-            st->qnext = 0;
-        }
-        group_sync<G>();
-        const int64_t q = qb + gt;
-        long long start = 0;
-        int len = 0;
-        V bv = V(0);
-        if (gt < CH && q < q1) {
-            len = tr.len[q];
-            if (len > 0) {
-                start = tr.start[q];
-                bv = Bvals[q];
-                if (!full && len > kShortLen) {
-                    const int32_t *sp = split + (int64_t)Browidx[q] * (nblk + 1);
-                    const int lo = b0 > 0 ? sp[b0] : 0;
-                    const int hi = b1 < nblk ? sp[b1] : len;
-                    start += lo;
-                    len = hi - lo;
-                }
-            }
-        }
-        if (len > kShortLen) {
-            const int slot = atomicAdd(&st->nlong, 1);
-            st->lstart[slot] = start;
-            st->lend[slot] = start + len;
-            st->lbv[slot] = bv;
-            st->lnext[slot] = 0;
-        }
-        int tot;
-        const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0), st->tmp, &tot);
-        const int ns = tot >> 16, nt = tot & 0xFFFF;
-        if (len > 0 && len <= kShortLen) {
-            const int slot = CH - ns + (sp >> 16);
-            st->lstart[slot] = start;
-            st->lbv[slot] = bv;
-            st->lnext[slot] = sp & 0xFFFF;
-        }
-        group_sync<G>();
-        const int nl = st->nlong;
-        constexpr int SU = short_unroll<G>();
-        for (int t0 = 0; t0 < nt; t0 += SU * G) {
-            int32_t r[SU];
-            V av[SU], b[SU];
-            // threads past the list's end load its last term again (in
-            // bounds, no divergent branch) and do not apply it
-#pragma unroll
-            for (int u = 0; u < SU; ++u) {
-                const int t = min(t0 + u * G + gt, nt - 1);
-                const int sl = short_slot<CH, V>(st, ns, t);
-                const long long pos = st->lstart[sl] + (t - st->lnext[sl]);
-                r[u] = At_rowidx[pos];
-                av[u] = At_vals[pos];
-                b[u] = st->lbv[sl];
-            }
-            bool ok[SU];
-#pragma unroll
-            for (int u = 0; u < SU; ++u) ok[u] = t0 + u * G + gt < nt && inside(r[u]);
-            ap(r, av, b, ok);
-        }
-        constexpr int PS = U * kWave;
-        // a piece's row ids and values, loaded without branches (lanes past
-        // the entry's end load its last term again and do not apply it)
-        auto load = [&](long long s0, int elen, int off, int32_t (&r)[U], V (&av)[U]) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const long long at = s0 + min(off + u * kWave + tl, elen - 1);
-                r[u] = At_rowidx[at];
-                av[u] = At_vals[at];
-            }
-        };
-        // the next piece is claimed and its loads are in flight while the
-        // current one is applied
-        auto walk = [&](int e) {
-            const long long s0 = st->lstart[e];
-            const int elen = (int)(st->lend[e] - s0);
-            const V b = st->lbv[e];
-            int off = claim_piece<CH, V>(st, e, PS);
-            if (off >= elen) return;
-            int32_t r[U];
-            V av[U];
-            load(s0, elen, off, r, av);
-            while (true) {
-                const int nxt = claim_piece<CH, V>(st, e, PS);
-                int32_t r2[U];
-                V av2[U];
-                load(s0, elen, min(nxt, elen - 1), r2, av2);
-                ap_batch(off, elen, r, av, b);
-                if (nxt >= elen) break;
-                off = nxt;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    r[u] = r2[u];
-                    av[u] = av2[u];
-                }
-            }
-        };
-        for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
-        auto lim = [&](int e) { return (int)(st->lend[e] - st->lstart[e]); };
-        for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
-             e = entry_with_work(st->lnext, nl, team, lim))
-            walk(e);
-        group_sync<G>();
-    }
-}
-
-// Writes the set rows of bitmap words [wb, we) whose ranks lie in
-// [r0, r0 + cnt) to out[0, cnt): every lane takes one word and stages its
+// Writes the set rows (row0 + bit index) of bitmap words [wb, we) whose
+// ranks lie in [r0, r0 + cnt) to out[0, cnt): every lane takes one word and stages its
 // rows at their ranks in LDS (stage, cnt ints), then the group copies them
 // out coalesced.  All G threads call; ends with a group barrier.
 template <int G>
 __device__ __forceinline__ void window_rows_out(const uint32_t *bits, const uint16_t *wpre,
                                                 const int *sbase, int wb, int we, int r0, int cnt,
-                                                int32_t *stage, int32_t *__restrict__ out) {
+                                                int32_t row0, int32_t *stage,
+                                                int32_t *__restrict__ out) {
     for (int w = wb + (int)threadIdx.x; w < we; w += G) {
         uint32_t b = bits[w];
         int rk = word_rank(wpre, sbase, w) - r0;
         while (b) {
-            if (rk >= 0 && rk < cnt) stage[swz(rk)] = (w << 5) + __ffs(b) - 1;
+            if (rk >= 0 && rk < cnt) stage[swz(rk)] = row0 + (w << 5) + __ffs(b) - 1;
             ++rk;
             b &= b - 1;
         }
@@ -638,117 +503,149 @@ __device__ __forceinline__ void window_rows_out(const uint32_t *bits, const uint
 // outside.  One wave lays out the windows from the ranks at the block
 // borders; per window the group writes the window's row ids, accumulates
 // its values by rank in LDS and writes them.
+//
+// A column of more than kMaxDenseRows rows (m above 2^18) is done in bands
+// of kMaxDenseRows rows, one after another: each band builds its own bitmap
+// from exactly its products (its blocks of the split table) and its ranks
+// follow those of the bands before it.
 template <int G, typename V>
 __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
                                                  uint16_t *wpre, Acc *vals, int VC,
                                                  NumDenseStatic<G, V> &S) {
     constexpr int CH = kDenseChunk < G ? kDenseChunk : G;
-    const int gt = threadIdx.x;
-    const int nw = (int)((a.m + 31) >> 5);
-    const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
-    const int slot = a.dense_bits ? a.col_slot[j] : -1;  // a kept bitmap, if this run kept them
-    if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
-        const uint32_t *src = a.dense_bits + (size_t)slot * nw;
-        copy_words<G>(bits, src, nw);
-        __syncthreads();
-    } else {
-        zero_words<G>(bits, nw);
-        __syncthreads();
-        for_each_term<G, V, kDenseUnroll, CH>(
-            q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
-            [&](int64_t p) { return a.At_rowidx[p]; },
-            [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
-    }
-    const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, nullptr, 0);
-    const int64_t o = a.Ccolptr[j];
     constexpr int kBlockWords = (int)(kSplitRows >> 5);
-    const int nblk = (nw + kBlockWords - 1) / kBlockWords;  // at most 32 (m <= 2^18)
+    constexpr int kBandBlocks = (int)(kMaxDenseRows >> kSplitShift);
+    const int gt = threadIdx.x;
+    const bool banded = a.m > kMaxDenseRows;
+    const int64_t q0 = a.Bcolptr[j], q1 = a.Bcolptr[j + 1];
+    // a kept bitmap, if this run kept them (never for banded columns)
+    const int slot = a.dense_bits && !banded ? a.col_slot[j] : -1;
     const int lane = lane_id();
     int32_t *stage = reinterpret_cast<int32_t *>(vals);
-    for (int w0r = 0; w0r < total;) {
-        if (gt < kWave) {
-            // lane b holds the rank at the start of block b (b == nblk: total)
-            const int rb = lane < nblk ? word_rank(wpre, S.sbase, lane * kBlockWords)
-                                       : (lane == nblk ? total : 0x7fffffff);
-            int n = 0;
-            int r0 = w0r;
-            while (r0 < total && n < kWinBatch) {
-                // the last block starting at or before rank r0, then the
-                // last block border at most VC ranks further
-                const uint64_t m0 = __ballot(lane < nblk && rb <= r0);
-                const int b0 = 63 - __clzll((long long)m0);
-                const uint64_t m1 = __ballot(lane > b0 && lane <= nblk && rb - r0 <= VC);
-                int b1, r1;
-                if (m1) {
-                    b1 = 63 - __clzll((long long)m1);
-                    r1 = __shfl(rb, b1);
-                } else {  // block b0 alone holds more than VC rows of C
-                    b1 = b0 + 1;
-                    r1 = r0 + VC;
-                }
-                if (lane == 0) {
-                    int *wd = S.win[n];
-                    wd[0] = b0;
-                    wd[1] = b1;
-                    wd[2] = r0;
-                    wd[3] = r1;
-                    // rows of the window: block borders when the ranks sit on
-                    // them, else the rows holding ranks r0 and r1
-                    const int rb0 = word_rank(wpre, S.sbase, b0 * kBlockWords);
-                    const int rb1 = b1 < nblk ? word_rank(wpre, S.sbase, b1 * kBlockWords) : total;
-                    wd[4] = r0 == rb0 ? (b0 << kSplitShift)
-                                      : row_of_rank(bits, wpre, S.sbase, nw, r0);
-                    wd[5] = r1 == rb1 ? (int)min<int64_t>((int64_t)b1 << kSplitShift, a.m)
-                                      : row_of_rank(bits, wpre, S.sbase, nw, r1);
-                }
-                ++n;
-                r0 = r1;
-            }
-            if (lane == 0) S.nwin = n;
-        }
-        __syncthreads();
-        const int nwin = S.nwin;
-        for (int wi = 0; wi < nwin; ++wi) {
-            const int wb0 = S.win[wi][0], wb1 = S.win[wi][1];
-            const int r0 = S.win[wi][2], r1 = S.win[wi][3];
-            const int32_t rlo = S.win[wi][4], rhi = S.win[wi][5];
-            const int cnt = r1 - r0;
-            if (slot < 0)  // kept columns have their rows written by k_dense_rows
-                window_rows_out<G>(bits, wpre, S.sbase, wb0 * kBlockWords,
-                                   min(nw, wb1 * kBlockWords), r0, cnt, stage, a.Crow + o + r0);
-            for (int i = gt; i < cnt; i += G) vals[swz64(i)] = Acc(0);
+    int64_t o = a.Ccolptr[j];  // output position of the band's first rank
+    for (int32_t R0 = 0; R0 < a.m; R0 += (int32_t)kMaxDenseRows) {
+        const int32_t R1 = (int32_t)min<int64_t>(a.m, (int64_t)R0 + kMaxDenseRows);
+        const int nw = (R1 - R0 + 31) >> 5;
+        const int sb0 = R0 >> kSplitShift;  // the band's first block
+        if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
+            const uint32_t *src = a.dense_bits + (size_t)slot * nw;
+            copy_words<G>(bits, src, nw);
             __syncthreads();
-            const bool full = r0 == 0 && r1 == total;
-            // per batch: every rank lookup's LDS reads first, then the adds
-            auto add = [&](const auto &r, const auto &av, const auto &bv, const auto &ok) {
+        } else if (!banded) {
+            zero_words<G>(bits, nw);
+            __syncthreads();
+            for_each_term<G, V, kDenseUnroll, CH>(
+                q0, q1, a.tr, (const V *)nullptr, &S.st, gt,
+                [&](int64_t p) { return a.At_rowidx[p]; },
+                [&](int32_t r, V) { atomicOr(&bits[r >> 5], 1u << (r & 31)); });
+        } else {  // the band's products only
+            zero_words<G>(bits, nw);
+            __syncthreads();
+            auto mark = [&](const auto &r, const auto &, const auto &, const auto &ok) {
                 constexpr int N = (int)(sizeof(ok) / sizeof(ok[0]));
-                constexpr int H = N < 4 ? N : 4;  // lookups in flight per step
 #pragma unroll
-                for (int h = 0; h < N; h += H) {
-                    uint32_t wb[H];
-                    int wr[H];
-#pragma unroll
-                    for (int u = 0; u < H; ++u) {
-                        const int w = (ok[h + u] ? r[h + u] : rlo) >> 5;
-                        wb[u] = bits[w];
-                        wr[u] = word_rank(wpre, S.sbase, w);
+                for (int u = 0; u < N; ++u)
+                    if (ok[u]) atomicOr(&bits[(r[u] - R0) >> 5], 1u << (r[u] & 31));
+            };
+            for_each_window_term<G, V, kDenseUnroll, CH, decltype(mark) &, false>(
+                q0, q1, false, sb0, min(a.nblk, sb0 + kBandBlocks), a.nblk, R0, R1, a.tr,
+                a.Browidx, a.split, (const V *)nullptr, a.At_rowidx, (const V *)nullptr, &S.st,
+                gt, mark);
+            __syncthreads();
+        }
+        const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, nullptr, 0);
+        const int nblk = (nw + kBlockWords - 1) / kBlockWords;  // blocks of the band (<= 32)
+        for (int w0r = 0; w0r < total;) {
+            if (gt < kWave) {
+                // lane b holds the rank at the start of block b (b == nblk: total)
+                const int rb = lane < nblk ? word_rank(wpre, S.sbase, lane * kBlockWords)
+                                           : (lane == nblk ? total : 0x7fffffff);
+                int n = 0;
+                int r0 = w0r;
+                while (r0 < total && n < kWinBatch) {
+                    // the last block starting at or before rank r0, then the
+                    // last block border at most VC ranks further
+                    const uint64_t m0 = __ballot(lane < nblk && rb <= r0);
+                    const int b0 = 63 - __clzll((long long)m0);
+                    const uint64_t m1 = __ballot(lane > b0 && lane <= nblk && rb - r0 <= VC);
+                    int b1, r1;
+                    if (m1) {
+                        b1 = 63 - __clzll((long long)m1);
+                        r1 = __shfl(rb, b1);
+                    } else {  // block b0 alone holds more than VC rows of C
+                        b1 = b0 + 1;
+                        r1 = r0 + VC;
                     }
+                    if (lane == 0) {
+                        int *wd = S.win[n];
+                        wd[0] = b0;
+                        wd[1] = b1;
+                        wd[2] = r0;
+                        wd[3] = r1;
+                        // rows of the window: block borders when the ranks
+                        // sit on them, else the rows holding ranks r0 and r1
+                        const int rb0 = word_rank(wpre, S.sbase, b0 * kBlockWords);
+                        const int rb1 =
+                            b1 < nblk ? word_rank(wpre, S.sbase, b1 * kBlockWords) : total;
+                        wd[4] = R0 + (r0 == rb0 ? (b0 << kSplitShift)
+                                                : row_of_rank(bits, wpre, S.sbase, nw, r0));
+                        wd[5] = r1 == rb1
+                                    ? (int)min<int64_t>((int64_t)R0 + ((int64_t)b1 << kSplitShift), R1)
+                                    : R0 + row_of_rank(bits, wpre, S.sbase, nw, r1);
+                    }
+                    ++n;
+                    r0 = r1;
+                }
+                if (lane == 0) S.nwin = n;
+            }
+            __syncthreads();
+            const int nwin = S.nwin;
+            for (int wi = 0; wi < nwin; ++wi) {
+                const int wb0 = S.win[wi][0], wb1 = S.win[wi][1];
+                const int r0 = S.win[wi][2], r1 = S.win[wi][3];
+                const int32_t rlo = S.win[wi][4], rhi = S.win[wi][5];
+                const int cnt = r1 - r0;
+                if (slot < 0)  // kept columns have their rows written by k_dense_rows
+                    window_rows_out<G>(bits, wpre, S.sbase, wb0 * kBlockWords,
+                                       min(nw, wb1 * kBlockWords), r0, cnt, R0, stage,
+                                       a.Crow + o + r0);
+                for (int i = gt; i < cnt; i += G) vals[swz64(i)] = Acc(0);
+                __syncthreads();
+                const bool full = !banded && r0 == 0 && r1 == total;
+                // per batch: every rank lookup's LDS reads first, then the adds
+                auto add = [&](const auto &r, const auto &av, const auto &bv, const auto &ok) {
+                    constexpr int N = (int)(sizeof(ok) / sizeof(ok[0]));
+                    constexpr int H = N < 4 ? N : 4;  // lookups in flight per step
 #pragma unroll
-                    for (int u = 0; u < H; ++u) {
-                        if (ok[h + u]) {
-                            const int rk = wr[u] + __popc(wb[u] & ((1u << (r[h + u] & 31)) - 1u));
-                            lds_atomic_add(&vals[swz64(rk - r0)], prod(av[h + u], pick(bv, h + u)));
+                    for (int h = 0; h < N; h += H) {
+                        uint32_t wb[H];
+                        int wr[H];
+#pragma unroll
+                        for (int u = 0; u < H; ++u) {
+                            const int w = ((ok[h + u] ? r[h + u] : rlo) - R0) >> 5;
+                            wb[u] = bits[w];
+                            wr[u] = word_rank(wpre, S.sbase, w);
+                        }
+#pragma unroll
+                        for (int u = 0; u < H; ++u) {
+                            if (ok[h + u]) {
+                                const int rk =
+                                    wr[u] + __popc(wb[u] & ((1u << (r[h + u] & 31)) - 1u));
+                                lds_atomic_add(&vals[swz64(rk - r0)],
+                                               prod(av[h + u], pick(bv, h + u)));
+                            }
                         }
                     }
-                }
-            };
-            for_each_window_term<G, V, kDenseUnroll, CH>(
-                q0, q1, full, wb0, wb1, nblk, rlo, rhi, a.tr, a.Browidx, a.split, a.Bvals,
-                a.At_rowidx, a.At_vals, &S.st, gt, add);
-            for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = (V)vals[swz64(i)];
-            __syncthreads();
-            w0r = r1;
+                };
+                for_each_window_term<G, V, kDenseUnroll, CH>(
+                    q0, q1, full, sb0 + wb0, sb0 + wb1, a.nblk, rlo, rhi, a.tr, a.Browidx,
+                    a.split, a.Bvals, a.At_rowidx, a.At_vals, &S.st, gt, add);
+                for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = (V)vals[swz64(i)];
+                __syncthreads();
+                w0r = r1;
+            }
         }
+        o += total;
     }
 }
 

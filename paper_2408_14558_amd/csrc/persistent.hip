@@ -263,7 +263,7 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
         P.a = NumArgs<V>{p.m,        p.Bcolptr,    p.term_range(), Bv,        p.At_rowidx,
                          (const V *)p.At_vals,     p.C_colptr,     io[t].C_rowidx,
                          (V *)io[t].C_vals,        p.flop,         p.Browidx, p.split,
-                         p.col_slot, p.dense_bits, p.tiny_perm};
+                         p.col_slot, p.dense_bits, p.tiny_perm, p.nblk};
         for (int b = 0; b < kNumBins; ++b) P.list[b] = p.num_list + (int64_t)b * p.n;
         P.packed = p.m < kPackedRowLimit;
         P.dep_A = io[t].dep_A;

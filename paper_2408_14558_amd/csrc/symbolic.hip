@@ -504,32 +504,74 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
     TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
     uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot,
+    const int32_t *__restrict__ Browidx, const int32_t *__restrict__ split, int32_t nblk,
     DevCounters *__restrict__ ctr) {
     extern __shared__ __align__(16) uint32_t s_bits[];
     __shared__ SymDenseLds L;
     __shared__ int s_item;
     unsigned int *queue = ctr->sym_dense_queue;
-    const int nw = (int)((m + 31) >> 5);
     const int gt = threadIdx.x;
-    for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item)) {
-        const int32_t j = list[w];
-        zero_words<kDenseThreads>(s_bits, nw);
-        __syncthreads();
-        // short entries stay with their thread: a flat walk would give a wave
-        // consecutive rows of one column of A~, whose bits share words
-        for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
-            Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
-            [&](int64_t p) { return At_rowidx[p]; },
-            [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
-        int c = 0;
-        for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
-        int total;
-        (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
-        if (gt == 0) Ccount[j] = total;
-        if (keep_bits) {  // the numeric phase reuses this bitmap
-            uint32_t *dst = keep_bits + (size_t)w * nw;
-            copy_words<kDenseThreads>(dst, s_bits, nw);
-            if (gt == 0) col_slot[j] = w;
+    if (m <= kMaxDenseRows) {
+        const int nw = (int)((m + 31) >> 5);
+        for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item)) {
+            const int32_t j = list[w];
+            zero_words<kDenseThreads>(s_bits, nw);
+            __syncthreads();
+            // short entries stay with their thread: a flat walk would give a
+            // wave consecutive rows of one column of A~, whose bits share words
+            for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
+                Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
+                [&](int64_t p) { return At_rowidx[p]; },
+                [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
+            int c = 0;
+            for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
+            int total;
+            (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
+            if (gt == 0) Ccount[j] = total;
+            if (keep_bits) {  // the numeric phase reuses this bitmap
+                uint32_t *dst = keep_bits + (size_t)w * nw;
+                copy_words<kDenseThreads>(dst, s_bits, nw);
+                if (gt == 0) col_slot[j] = w;
+            }
+        }
+    } else {
+        // m above 2^18: bands of kMaxDenseRows rows, each counted from
+        // exactly its products (its blocks of the split table); no bitmap
+        // is kept
+        constexpr int kBandBlocks = (int)(kMaxDenseRows >> kSplitShift);
+        for (int w = queue_take(queue, &s_item); w < count; w = queue_take(queue, &s_item)) {
+            const int32_t j = list[w];
+            int64_t count_j = 0;
+            for (int64_t R0 = 0; R0 < m; R0 += kMaxDenseRows) {
+                const int64_t R1 = min(m, R0 + kMaxDenseRows);
+                const int nw = (int)((R1 - R0 + 31) >> 5);
+                const int sb0 = (int)(R0 >> kSplitShift);
+                zero_words<kDenseThreads>(s_bits, nw);
+                __syncthreads();
+                auto mark = [&](const auto &r, const auto &, const auto &, const auto &ok) {
+                    constexpr int N = (int)(sizeof(ok) / sizeof(ok[0]));
+#pragma unroll
+                    for (int u = 0; u < N; ++u)
+                        if (ok[u])
+                            atomicOr(&s_bits[(r[u] - (int32_t)R0) >> 5], 1u << (r[u] & 31));
+                };
+                for_each_window_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads,
+                                     decltype(mark) &, false>(
+                    Bcolptr[j], Bcolptr[j + 1], false, sb0, min(nblk, sb0 + kBandBlocks), nblk,
+                    (int32_t)R0, (int32_t)R1, tr, Browidx, split, (const float *)nullptr,
+                    At_rowidx, (const float *)nullptr, &L.st, gt, mark);
+                __syncthreads();
+                int c = 0;
+                for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
+                int total;
+                (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
+                count_j += total;
+                __syncthreads();  // the bitmap is cleared for the next band
+            }
+            if (gt == 0) {
+                Ccount[j] = count_j;
+                if (col_slot) col_slot[j] = -1;
+            }
         }
     }
     queue_leave(queue);
@@ -714,8 +756,9 @@ __global__ void k_symbolic_reset(DevCounters *__restrict__ ctr, uint64_t *__rest
 
 // Split table: for every column c of A that is long in A~ (more than
 // kShortLen entries), split[c * (nblk + 1) + b] = the number of its entries
-// with row below b * kSplitRows, b = 0 .. nblk.  One wave per column; lane b
-// finds border b by a binary search over the column's ascending rows.
+// with row below b * kSplitRows, b = 0 .. nblk.  One wave per column; its
+// lanes take the borders in turn, each by a binary search over the column's
+// ascending rows.
 __global__ __launch_bounds__(256) void k_split_table(int64_t k, int32_t nblk,
                                                      const int64_t *__restrict__ col_start,
                                                      const int32_t *__restrict__ col_len,
@@ -844,16 +887,18 @@ int launch_symbolic_bins(Plan &p, bool tiny_launched) {
     if ((rc = sym_hash_launch<kSymTable[2], 256>(p, kBinH2))) return rc;
     if ((rc = sym_hash_launch<kSymTable[3], 512>(p, kBinH3))) return rc;
     if (p.sym_count[kBinDense] > 0) {
-        if (p.m > kMaxDenseRows)
-            return fail(SPGEMM_EUNSUPPORTED,
-                        "columns with more flops than the largest hash bin need m <= 262144");
-        const size_t lds = (size_t)((p.m + 31) / 32) * 4;
+        // taller columns are counted in bands of kMaxDenseRows rows, which
+        // reach A~ through the split table
+        if (p.m > kMaxDenseRows && (rc = ensure_split_table(p, p.sym_count[kBinDense])))
+            return rc;
+        const size_t lds = (size_t)((std::min<int64_t>(p.m, kMaxDenseRows) + 31) / 32) * 4;
         const unsigned grid = resident_groups((const void *)k_sym_dense, kDenseThreads, lds,
                                               p.device, p.sym_count[kBinDense]);
         hipLaunchKernelGGL(k_sym_dense, dim3(grid), dim3(kDenseThreads), lds, p.stream,
                            p.sym_list + (int64_t)kBinDense * p.n, p.sym_count[kBinDense], p.m,
-                           p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr, p.dense_bits,
-                           p.col_slot, p.ctr);
+                           p.Bcolptr, p.term_range(), p.At_rowidx, p.C_colptr,
+                           p.m <= kMaxDenseRows ? p.dense_bits : nullptr, p.col_slot, p.Browidx,
+                           p.split, p.nblk, p.ctr);
         SPG_LAUNCHED("k_sym_dense (" + std::to_string(grid) + " workgroups)");
     }
     return SPGEMM_OK;

@@ -366,4 +366,142 @@ __device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
 }
 
 
+// Visits the terms of one window of a dense column: rows [rlo, rhi) of C,
+// inside row blocks [b0, b1) of the split table (full: the whole column).
+// For every entry q of B(:,j), a long column of A~ (more than kShortLen
+// entries) is cut to its part in the window's blocks by the split table
+// (no cut when full); a short one is taken whole.  Every term whose row lies
+// in [rlo, rhi) gets ap(row, a_ik, b_kj), each exactly once: the blocks
+// cover the window's rows, and rows outside it (the rest of a short column,
+// the part of a block outside a window that splits it) are skipped.
+// Segments of at most kShortLen terms form one flat list over the group;
+// longer ones are walked by whole waves in pieces of U*64 claimed from a
+// per-entry counter, with row ids and values loaded together.
+// kVals = false: row ids only (values read as 0, Bvals and At_vals unused).
+template <int G, typename V, int U, int CH, typename AP, bool kVals = true>
+__device__ __forceinline__ void for_each_window_term(
+    int64_t q0, int64_t q1, bool full, int b0, int b1, int nblk, int32_t rlo, int32_t rhi,
+    TermRange tr, const int32_t *__restrict__ Browidx, const int32_t *__restrict__ split,
+    const V *__restrict__ Bvals, const int32_t *__restrict__ At_rowidx,
+    const V *__restrict__ At_vals, TermStage<CH, V> *st, int gt, AP &&ap) {
+    static_assert(G > kWave && CH <= G && G <= kMaxGroupWaves * kWave, "group and chunk sizes");
+    const int team = gt / kWave, tl = lane_id();
+    auto inside = [&](int32_t r) { return r >= rlo && r < rhi; };
+    // applies the U terms of one lane of a piece at offset `off` of an entry
+    // of `elen` terms: ap gets the whole batch, so it can issue its LDS reads
+    // for all of them before it waits
+    auto ap_batch = [&](int off, int elen, const int32_t (&r)[U], const V (&av)[U], V b) {
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ok[u] = off + u * kWave + tl < elen && inside(r[u]);
+        ap(r, av, b, ok);
+    };
+    for (int64_t qb = q0; qb < q1; qb += CH) {
+        if (gt == 0) {
+            st->nlong = 0;
+            st->qnext = 0;
+        }
+        group_sync<G>();
+        const int64_t q = qb + gt;
+        long long start = 0;
+        int len = 0;
+        V bv = V(0);
+        if (gt < CH && q < q1) {
+            len = tr.len[q];
+            if (len > 0) {
+                start = tr.start[q];
+                if (kVals) bv = Bvals[q];
+                if (!full && len > kShortLen) {
+                    const int32_t *sp = split + (int64_t)Browidx[q] * (nblk + 1);
+                    const int lo = b0 > 0 ? sp[b0] : 0;
+                    const int hi = b1 < nblk ? sp[b1] : len;
+                    start += lo;
+                    len = hi - lo;
+                }
+            }
+        }
+        if (len > kShortLen) {
+            const int slot = atomicAdd(&st->nlong, 1);
+            st->lstart[slot] = start;
+            st->lend[slot] = start + len;
+            st->lbv[slot] = bv;
+            st->lnext[slot] = 0;
+        }
+        int tot;
+        const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0), st->tmp, &tot);
+        const int ns = tot >> 16, nt = tot & 0xFFFF;
+        if (len > 0 && len <= kShortLen) {
+            const int slot = CH - ns + (sp >> 16);
+            st->lstart[slot] = start;
+            st->lbv[slot] = bv;
+            st->lnext[slot] = sp & 0xFFFF;
+        }
+        group_sync<G>();
+        const int nl = st->nlong;
+        constexpr int SU = short_unroll<G>();
+        for (int t0 = 0; t0 < nt; t0 += SU * G) {
+            int32_t r[SU];
+            V av[SU], b[SU];
+            // threads past the list's end load its last term again (in
+            // bounds, no divergent branch) and do not apply it
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int t = min(t0 + u * G + gt, nt - 1);
+                const int sl = short_slot<CH, V>(st, ns, t);
+                const long long pos = st->lstart[sl] + (t - st->lnext[sl]);
+                r[u] = At_rowidx[pos];
+                av[u] = kVals ? At_vals[pos] : V(0);
+                b[u] = st->lbv[sl];
+            }
+            bool ok[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) ok[u] = t0 + u * G + gt < nt && inside(r[u]);
+            ap(r, av, b, ok);
+        }
+        constexpr int PS = U * kWave;
+        // a piece's row ids and values, loaded without branches (lanes past
+        // the entry's end load its last term again and do not apply it)
+        auto load = [&](long long s0, int elen, int off, int32_t (&r)[U], V (&av)[U]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long at = s0 + min(off + u * kWave + tl, elen - 1);
+                r[u] = At_rowidx[at];
+                av[u] = kVals ? At_vals[at] : V(0);
+            }
+        };
+        // the next piece is claimed and its loads are in flight while the
+        // current one is applied
+        auto walk = [&](int e) {
+            const long long s0 = st->lstart[e];
+            const int elen = (int)(st->lend[e] - s0);
+            const V b = st->lbv[e];
+            int off = claim_piece<CH, V>(st, e, PS);
+            if (off >= elen) return;
+            int32_t r[U];
+            V av[U];
+            load(s0, elen, off, r, av);
+            while (true) {
+                const int nxt = claim_piece<CH, V>(st, e, PS);
+                int32_t r2[U];
+                V av2[U];
+                load(s0, elen, min(nxt, elen - 1), r2, av2);
+                ap_batch(off, elen, r, av, b);
+                if (nxt >= elen) break;
+                off = nxt;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    r[u] = r2[u];
+                    av[u] = av2[u];
+                }
+            }
+        };
+        for (int e = claim_entry<CH, V>(st); e < nl; e = claim_entry<CH, V>(st)) walk(e);
+        auto lim = [&](int e) { return (int)(st->lend[e] - st->lstart[e]); };
+        for (int e = entry_with_work(st->lnext, nl, team, lim); e >= 0;
+             e = entry_with_work(st->lnext, nl, team, lim))
+            walk(e);
+        group_sync<G>();
+    }
+}
+
 }  // namespace spg
