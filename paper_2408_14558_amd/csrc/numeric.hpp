@@ -417,7 +417,7 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
 // --- dense: bitmap of all m rows + rank windows -----------------------------
 // Loads in flight per lane on the long A~ columns of dense output columns.
 #ifndef SPG_DENSE_UNROLL
-#define SPG_DENSE_UNROLL 8
+#define SPG_DENSE_UNROLL 4
 #endif
 constexpr int kDenseUnroll = SPG_DENSE_UNROLL;
 // Entries of B(:,j) staged at once by the dense kernel (its 1024 threads all

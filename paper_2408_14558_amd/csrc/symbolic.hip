@@ -494,7 +494,11 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
 }
 
 // --- dense bin: bitmap of all m rows in LDS ---------------------------------
-constexpr int kSymDenseUnroll = 8;  // row loads in flight per lane on long A~ columns
+// Row loads in flight per lane on long A~ columns.
+#ifndef SPG_SYM_DENSE_UNROLL
+#define SPG_SYM_DENSE_UNROLL 8
+#endif
+constexpr int kSymDenseUnroll = SPG_SYM_DENSE_UNROLL;
 struct SymDenseLds {
     TermStage<kDenseThreads, float> st;
     int red[kDenseThreads / kWave + 2];
