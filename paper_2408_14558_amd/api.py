@@ -22,8 +22,13 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(stream=None):
     if stream is None:
+        if _raw_stream is not None:  # the current stream's handle without a Stream object
+            return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
 
@@ -215,7 +220,7 @@ class Plan:
                                (vals, "C_vals", self.torch_dtype, self.nnzC)):
             if t is None:
                 continue
-            if t.device != torch.device(self.device) or t.dtype != dt or not t.is_contiguous():
+            if t.device != self.device or t.dtype != dt or not t.is_contiguous():
                 raise ValueError(f"{what} must be a contiguous {dt} tensor on {self.device}")
             if t.numel() < n:
                 raise ValueError(f"{what} holds {t.numel()} elements, needs {n}")

@@ -737,10 +737,9 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
         hout->sym_count[tid] = ctr->sym_count[tid].v;
     }
     __syncthreads();
-    if (tid == 0) {
-        __threadfence_system();
-        __hip_atomic_store(hready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    // wave 0 wrote every host-side field: thread 0's system-scope release
+    // store orders them before the flag
+    if (tid == 0) __hip_atomic_store(hready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Clears what one symbolic phase accumulates (the colptr scan's ticket and
