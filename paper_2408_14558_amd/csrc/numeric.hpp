@@ -523,6 +523,11 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
     const int lane = lane_id();
     int32_t *stage = reinterpret_cast<int32_t *>(vals);
     int64_t o = a.Ccolptr[j];  // output position of the band's first rank
+    // a column of at most CH entries keeps them in registers over all its
+    // windows (loaded here, in flight with the bitmap's loads)
+    const bool cached = q1 - q0 <= CH;
+    EntryRegs<V> er;
+    if (cached) er = load_entry<CH, V>(q0, q1, a.tr, a.Browidx, a.Bvals, gt);
     for (int32_t R0 = 0; R0 < a.m; R0 += (int32_t)kMaxDenseRows) {
         const int32_t R1 = (int32_t)min<int64_t>(a.m, (int64_t)R0 + kMaxDenseRows);
         const int nw = (R1 - R0 + 31) >> 5;
@@ -639,7 +644,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
                 };
                 for_each_window_term<G, V, kDenseUnroll, CH>(
                     q0, q1, full, sb0 + wb0, sb0 + wb1, a.nblk, rlo, rhi, a.tr, a.Browidx,
-                    a.split, a.Bvals, a.At_rowidx, a.At_vals, &S.st, gt, add);
+                    a.split, a.Bvals, a.At_rowidx, a.At_vals, &S.st, gt, add, cached, er);
                 for (int i = gt; i < cnt; i += G) a.Cval[o + r0 + i] = (V)vals[swz64(i)];
                 __syncthreads();
                 w0r = r1;

@@ -378,12 +378,43 @@ __device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
 // longer ones are walked by whole waves in pieces of U*64 claimed from a
 // per-entry counter, with row ids and values loaded together.
 // kVals = false: row ids only (values read as 0, Bvals and At_vals unused).
+// What one thread of the group holds of its entry of B(:,j) across the
+// windows of a column: the entry's whole A~ column (start, length), b_kj and
+// the row id that indexes the split table.  A column with at most CH entries
+// is staged once per column instead of once per window.
+template <typename V>
+struct EntryRegs {
+    long long start = 0;
+    int len = 0;
+    int brow = 0;
+    V bv = V(0);
+};
+
+// Loads thread gt's entry (q0 + gt) of a column of at most CH entries.
+template <int CH, typename V, bool kVals = true>
+__device__ __forceinline__ EntryRegs<V> load_entry(int64_t q0, int64_t q1, TermRange tr,
+                                                   const int32_t *__restrict__ Browidx,
+                                                   const V *__restrict__ Bvals, int gt) {
+    EntryRegs<V> e;
+    const int64_t q = q0 + gt;
+    if (gt < CH && q < q1) {
+        e.len = tr.len[q];
+        e.start = tr.start[q];
+        e.brow = Browidx[q];
+        if (kVals) e.bv = Bvals[q];
+    }
+    return e;
+}
+
+// cached: the column has at most CH entries and every thread passes its
+// entry in `er` (load_entry); otherwise the entries are loaded per chunk.
 template <int G, typename V, int U, int CH, typename AP, bool kVals = true>
 __device__ __forceinline__ void for_each_window_term(
     int64_t q0, int64_t q1, bool full, int b0, int b1, int nblk, int32_t rlo, int32_t rhi,
     TermRange tr, const int32_t *__restrict__ Browidx, const int32_t *__restrict__ split,
     const V *__restrict__ Bvals, const int32_t *__restrict__ At_rowidx,
-    const V *__restrict__ At_vals, TermStage<CH, V> *st, int gt, AP &&ap) {
+    const V *__restrict__ At_vals, TermStage<CH, V> *st, int gt, AP &&ap, bool cached = false,
+    const EntryRegs<V> &er = EntryRegs<V>()) {
     static_assert(G > kWave && CH <= G && G <= kMaxGroupWaves * kWave, "group and chunk sizes");
     const int team = gt / kWave, tl = lane_id();
     auto inside = [&](int32_t r) { return r >= rlo && r < rhi; };
@@ -407,12 +438,13 @@ __device__ __forceinline__ void for_each_window_term(
         int len = 0;
         V bv = V(0);
         if (gt < CH && q < q1) {
-            len = tr.len[q];
+            len = cached ? er.len : tr.len[q];
             if (len > 0) {
-                start = tr.start[q];
-                if (kVals) bv = Bvals[q];
+                start = cached ? er.start : tr.start[q];
+                if (kVals) bv = cached ? er.bv : Bvals[q];
                 if (!full && len > kShortLen) {
-                    const int32_t *sp = split + (int64_t)Browidx[q] * (nblk + 1);
+                    const int32_t *sp =
+                        split + (int64_t)(cached ? er.brow : Browidx[q]) * (nblk + 1);
                     const int lo = b0 > 0 ? sp[b0] : 0;
                     const int hi = b1 < nblk ? sp[b1] : len;
                     start += lo;
