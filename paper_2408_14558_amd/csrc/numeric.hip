@@ -68,18 +68,50 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
 // column's bitmap 64 words at a time (a word per lane, kRowAhead rounds of
 // loads in flight), places each round's set rows by a wave scan of the bit
 // counts in its own LDS stage and writes them out coalesced, the running
-// count giving the next round's first position.  Columns whose values went
-// to a hash bin are skipped.
+// count giving the next round's first position.  The stage holds kRowStage
+// rows (a round of 64 words with more set bits is placed in two halves of
+// 32 words), so eight waves fit per SIMD.  Columns whose values went to a
+// hash bin are skipped.
 constexpr int kRowThreads = 256;
 constexpr int kRowWaves = kRowThreads / kWave;
 constexpr int kRowAhead = 4;
+constexpr int kRowStage = 32 * 32;  // the set bits of 32 words
 __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
     int count, const int32_t *__restrict__ list, const int32_t *__restrict__ num_bin, int nw,
     const uint32_t *__restrict__ bits, const int64_t *__restrict__ Ccolptr,
     int32_t *__restrict__ Crow) {
-    __shared__ int32_t stage[kRowWaves][kWave * 32];
+    __shared__ int32_t stage[kRowWaves][kRowStage];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     int32_t *my = stage[wv];
+    // places the set rows of `word` (word index wi, lanes' words in order)
+    // at base and returns their number (wave-uniform)
+    auto place = [&](uint32_t word, int wi, long long base) {
+        const int pc = __popc(word);
+        const int incl = wave_incl_scan(pc);
+        const int n = __shfl(incl, kWave - 1);
+        int rk = incl - pc;
+        while (word) {
+            my[swz(rk++)] = (wi << 5) + __ffs(word) - 1;
+            word &= word - 1;
+        }
+        wave_sync();
+        // four LDS reads in flight before their stores
+        for (int i0 = 0; i0 < n; i0 += 4 * kWave) {
+            int32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kWave + lane;
+                v[u] = my[swz(min(i, n - 1))];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kWave + lane;
+                if (i < n) Crow[base + i] = v[u];
+            }
+        }
+        wave_sync();
+        return n;
+    };
     for (int w = blockIdx.x * kRowWaves + wv; w < count; w += gridDim.x * kRowWaves) {
         const int32_t j = list[w];
         if (num_bin[j] < kBinDense) continue;  // the same for the whole wave
@@ -100,32 +132,14 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
 #pragma unroll
             for (int d = 0; d < kRowAhead; ++d) {
                 const int wi = s0 + d * kWave + lane;
-                uint32_t word = wi < nw ? cur[d] : 0u;
-                const int pc = __popc(word);
-                const int incl = wave_incl_scan(pc);
-                const int n = __shfl(incl, kWave - 1);
-                int rk = incl - pc;
-                while (word) {
-                    my[swz(rk++)] = (wi << 5) + __ffs(word) - 1;
-                    word &= word - 1;
+                const uint32_t word = wi < nw ? cur[d] : 0u;
+                const int total = __shfl(wave_incl_scan(__popc(word)), kWave - 1);
+                if (total <= kRowStage) {
+                    base += place(word, wi, base);
+                } else {  // each half's 32 words hold at most kRowStage bits
+                    base += place(lane < 32 ? word : 0u, wi, base);
+                    base += place(lane < 32 ? 0u : word, wi, base);
                 }
-                wave_sync();
-                // four LDS reads in flight before their stores
-                for (int i0 = 0; i0 < n; i0 += 4 * kWave) {
-                    int32_t v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int i = i0 + u * kWave + lane;
-                        v[u] = my[swz(min(i, n - 1))];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int i = i0 + u * kWave + lane;
-                        if (i < n) Crow[base + i] = v[u];
-                    }
-                }
-                wave_sync();
-                base += n;
             }
 #pragma unroll
             for (int d = 0; d < kRowAhead; ++d) cur[d] = nxt[d];
