@@ -25,6 +25,18 @@ def _ptr(t: Optional[torch.Tensor]):
 _raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
 
 
+def _check_tensor(t, what, dtype, n, exact=False, device=None):
+    """O(1) checks before a tensor's address goes to the library: on a GPU
+    (the given device, if any), contiguous, of the dtype, and holding n
+    elements (at least n unless exact)."""
+    if not t.is_cuda or (device is not None and t.device != device):
+        raise ValueError(f"{what} must be a tensor on the GPU{'' if device is None else f' {device}'}")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor")
+    if (t.numel() != n) if exact else (t.numel() < n):
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {n}")
+
+
 def _stream(stream=None):
     if stream is None:
         if _raw_stream is not None:  # the current stream's handle without a Stream object
@@ -65,6 +77,15 @@ class DeviceCsc:
         kept = self.__dict__.get("_c_struct")
         if kept is not None and kept[0] == key:
             return kept[1]
+        # the library reads these arrays through raw device pointers
+        _check_tensor(self.colptr, "colptr", torch.int64, self.ncols + 1, exact=True)
+        _check_tensor(self.rowidx, "rowidx", torch.int32, nnz, exact=True,
+                      device=self.colptr.device)
+        if self.vals is not None:
+            if self.vals.dtype not in (torch.float32, torch.float64):
+                raise ValueError("vals must be float32 or float64")
+            _check_tensor(self.vals, "vals", self.vals.dtype, nnz, exact=True,
+                          device=self.colptr.device)
         s = _lib.Csc(self.nrows, self.ncols, nnz, key[3], key[4] if nnz else None,
                      key[5] if nnz else None)
         self.__dict__["_c_struct"] = (key, s)
@@ -282,7 +303,15 @@ class SpGEMM(torch.autograd.Function):
         return dA, dB, None
 
 
-def _io_table(io):
+def _io_table(io, plans):
+    if len(io) != len(plans):
+        raise ValueError("one io entry per plan")
+    for p, d in zip(plans, io):
+        nc = p.nnzC or 0  # a plan without symbolic() is refused by the library (ESTATE)
+        for key, dt, n in (("A_vals", p.torch_dtype, p.A.nnz), ("B_vals", p.torch_dtype, p.Bi.nnz),
+                           ("C_rowidx", torch.int32, nc), ("C_vals", p.torch_dtype, nc)):
+            if d.get(key) is not None:
+                _check_tensor(d[key], key, dt, n, device=p.device)
     arr = (_lib.BatchIO * len(io))()
     for t, d in enumerate(io):
         arr[t].A_vals = _ptr(d.get("A_vals"))
@@ -303,7 +332,7 @@ def batched(plans, io, mode: int = 0, stream=None):
     lib = _lib.load()
     plans = list(plans)
     handles = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
-    check(lib.spgemm_batched(len(plans), handles, _io_table(io), mode, _stream(stream)),
+    check(lib.spgemm_batched(len(plans), handles, _io_table(io, plans), mode, _stream(stream)),
           "spgemm_batched")
 
 
@@ -323,7 +352,7 @@ class Batch:
         self.plans = list(plans)
         self.io = [dict(x) for x in io]
         n = len(self.plans)
-        arr = _io_table(self.io)
+        arr = _io_table(self.io, self.plans)
         handles = (ctypes.c_void_p * n)(*[p.handle for p in self.plans])
         h = ctypes.c_void_p()
         tun = ctypes.byref(tuning) if tuning is not None else None

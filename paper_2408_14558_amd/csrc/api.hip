@@ -452,6 +452,10 @@ int ensure_split_table(Plan &p, int64_t dense_columns) {
 int finish_symbolic_counts(Plan &p) {
     if (!p.counts_pending) return SPGEMM_OK;
     SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
+    // the fallback synchronised the stream the scan ran on (spgemm_plan_set_stream
+    // finishes the counts before it switches): the flag must be set by now
+    if (!__atomic_load_n(p.hflags + kFlagColptr, __ATOMIC_ACQUIRE))
+        return fail(SPGEMM_EHIP, "the symbolic scan's counts were not published");
     p.flops = p.hpub->flops;
     for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
     p.counts_pending = false;

@@ -143,27 +143,47 @@ def test_state_and_null_handle_errors(lib):
     assert lib.spgemm_plan_stats(None, None) == _lib.EINVAL
 
 
-def test_c_struct_follows_the_arrays():
-    # the binding keeps a matrix's C struct while its arrays stay the same
-    # and builds a new one when an array, the shape or nnz changes
+def test_c_struct_rejects_arrays_the_library_cannot_read():
+    # the library reads a matrix through raw device pointers: host tensors,
+    # wrong dtypes and wrong lengths are refused before any call
     import torch
     spg = pytest.importorskip("paper_2408_14558_amd")
     M = spg.DeviceCsc(5, 3, torch.tensor([0, 1, 2, 2], dtype=torch.int64),
                       torch.tensor([0, 4], dtype=torch.int32),
                       torch.tensor([1.0, 2.0], dtype=torch.float64))
+    with pytest.raises(ValueError, match="on the GPU"):
+        M.c_struct()
+
+
+@pytest.mark.gpu
+def test_c_struct_follows_the_arrays():
+    # the binding keeps a matrix's C struct while its arrays stay the same
+    # and builds a new one when an array, the shape or nnz changes
+    import torch
+    spg = pytest.importorskip("paper_2408_14558_amd")
+    d = dict(device="cuda")
+    M = spg.DeviceCsc(5, 3, torch.tensor([0, 1, 2, 2], dtype=torch.int64, **d),
+                      torch.tensor([0, 4], dtype=torch.int32, **d),
+                      torch.tensor([1.0, 2.0], dtype=torch.float64, **d))
     s1 = M.c_struct()
     assert M.c_struct() is s1
     assert (s1.nrows, s1.ncols, s1.nnz) == (5, 3, 2)
     assert s1.colptr == M.colptr.data_ptr() and s1.vals == M.vals.data_ptr()
-    M.vals = torch.tensor([3.0, 4.0], dtype=torch.float64)
+    M.vals = torch.tensor([3.0, 4.0], dtype=torch.float64, **d)
     s2 = M.c_struct()
     assert s2 is not s1 and s2.vals == M.vals.data_ptr()
-    M.rowidx = torch.tensor([1], dtype=torch.int32)
-    M.vals = torch.tensor([5.0], dtype=torch.float64)
-    M.colptr = torch.tensor([0, 1, 1, 1], dtype=torch.int64)
+    M.rowidx = torch.tensor([1], dtype=torch.int32, **d)
+    M.vals = torch.tensor([5.0], dtype=torch.float64, **d)
+    M.colptr = torch.tensor([0, 1, 1, 1], dtype=torch.int64, **d)
     s3 = M.c_struct()
     assert s3.nnz == 1 and s3.rowidx == M.rowidx.data_ptr() and s3.colptr == M.colptr.data_ptr()
-    E = spg.DeviceCsc(4, 2, torch.zeros(3, dtype=torch.int64),
-                      torch.zeros(0, dtype=torch.int32), None)
+    E = spg.DeviceCsc(4, 2, torch.zeros(3, dtype=torch.int64, **d),
+                      torch.zeros(0, dtype=torch.int32, **d), None)
     se = E.c_struct()
     assert se.nnz == 0 and not se.rowidx and not se.vals
+    with pytest.raises(ValueError, match="elements"):  # colptr of the wrong length
+        spg.DeviceCsc(4, 3, torch.zeros(3, dtype=torch.int64, **d),
+                      torch.zeros(0, dtype=torch.int32, **d), None).c_struct()
+    with pytest.raises(ValueError, match="int32"):
+        spg.DeviceCsc(4, 2, torch.zeros(3, dtype=torch.int64, **d),
+                      torch.zeros(0, dtype=torch.int64, **d), None).c_struct()
