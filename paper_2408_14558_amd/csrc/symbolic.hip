@@ -26,6 +26,28 @@ __device__ __forceinline__ int num_bin_of(long long f, long long nnz, const Thre
     return kBinDense;
 }
 
+// The calling lane's slot in bin b's workgroup-local list (LDS counters
+// s_cnt; b == kBinEmpty: none, 0).  The lanes of a wave that share a bin
+// take consecutive slots from one LDS atomic: lane by lane, thousands of
+// columns of one bin serialise on its counter (the one-workgroup scan of C2's
+// 4096 tiny columns spent most of its 9 us there).  Every lane of the wave
+// calls.
+__device__ __forceinline__ int wave_bin_slot(int *s_cnt, int b) {
+    int pos = 0;
+#pragma unroll
+    for (int x = kBinEmpty + 1; x < kNumBins; ++x) {
+        const uint64_t m = __ballot(b == x);
+        if (m) {  // wave-uniform
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int base = 0;
+            if (lane_id() == leader) base = atomicAdd(&s_cnt[x], __popcll(m));
+            base = __shfl(base, leader);
+            if (b == x) pos = base + __popcll(m & ((1ull << lane_id()) - 1ull));
+        }
+    }
+    return pos;
+}
+
 // Appends the workgroup's columns to the per-bin lists: one global atomic
 // per non-empty bin and workgroup reserves a contiguous range.
 __device__ __forceinline__ void append_to_bins(int nloc, const int *s_bin, const int *s_lpos,
@@ -140,20 +162,20 @@ __device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups, i
         acc = wave_sum<S>(acc);
         if (lc < nloc && sub == 0) s_f[lc] = is_long ? -1 : acc;
         __syncthreads();
+        int b = kBinEmpty;
         if (tid < nloc) {
             const int64_t j = j0 + tid;
             const long long f = s_f[tid];
             a.col_slot[j] = -1;
-            int code = kBinEmpty << 24;
             if (f >= 0) {  // a long column is binned by the chunk that completes it
                 a.flop[j] = f;
-                const int b = sym_bin_of(f, a.th);
+                b = sym_bin_of(f, a.th);
                 a.sym_bin[j] = b;
                 if (f) atomic_add_i64(&s_flops, f);
-                if (b != kBinEmpty) code = (b << 24) | atomicAdd(&s_cnt[b], 1);
             }
-            s_bl[rd * COLS + tid] = code;
         }
+        const int slot = wave_bin_slot(s_cnt, b);
+        if (tid < nloc) s_bl[rd * COLS + tid] = b != kBinEmpty ? (b << 24) | slot : kBinEmpty << 24;
     }
     __syncthreads();
     if (tid == 0 && s_flops) atomic_add_i64(&a.ctr->flops.v, s_flops);
@@ -615,16 +637,18 @@ __global__ __launch_bounds__(kScanThreads) void k_colptr_scan(
     for (int i = 0; i < kScanItems; ++i) {
         const int lc = tid * kScanItems + i;
         cnt[i] = 0;
+        int b = kBinEmpty;
         if (lc < nloc) {
             const int64_t j = j0 + lc;
             cnt[i] = fl[i] == 0 ? 0 : cc[i];  // empty columns have no count
-            int b = num_bin_of(fl[i], cnt[i], th);
+            b = num_bin_of(fl[i], cnt[i], th);
             if (b == kBinDense && th.dense_first_flop > 0 && fl[i] >= th.dense_first_flop)
                 b = kBinDenseFirst;
             num_bin[j] = b;
             s_bin[lc] = b;
-            s_lpos[lc] = (b != kBinEmpty) ? atomicAdd(&s_cnt[b], 1) : 0;
         }
+        const int slot = wave_bin_slot(s_cnt, b);
+        if (lc < nloc) s_lpos[lc] = slot;
         sum += cnt[i];
     }
     long long total;
@@ -692,7 +716,6 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
             const int64_t j = j0 + (int64_t)tid * kSmallScanItems + i;
             cnt[i] = 0;
             bin[i] = kBinEmpty;
-            lpos[i] = 0;
             if (j < n) {
                 const long long f = fl[i];
                 cnt[i] = f == 0 ? 0 : cc[i];  // empty columns have no count
@@ -701,8 +724,8 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
                     b = kBinDenseFirst;
                 num_bin[j] = b;
                 bin[i] = b;
-                if (b != kBinEmpty) lpos[i] = atomicAdd(&s_cnt[b], 1);
             }
+            lpos[i] = wave_bin_slot(s_cnt, bin[i]);
             sum += cnt[i];
         }
         long long total;
