@@ -113,9 +113,15 @@ __global__ __launch_bounds__(kScanThreads) void k_rank_groups(
             gid[c] = -1;
         }
     }
-    int hsum = wave_sum(hcnt);
-    if (lane_id() == 0 && hsum) atomic_add_i64(&ctr->h_count, (long long)hsum);
+    // one atomic per tile and counter: thousands of workgroups' atomics on
+    // one address queue behind each other
+    const int hsum = wave_sum(hcnt);
+    if (lane_id() == 0) s_tmp[tid / kWave] = hsum;
+    __syncthreads();
     if (tid == 0) {
+        int h = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) h += s_tmp[w];
+        if (h) atomic_add_i64(&ctr->h_count, (long long)h);
         atomic_add_i64(&ctr->nzc, (long long)total);
         if (d.last) {
             const long long nzc_part = s_prefix + total;
@@ -205,8 +211,15 @@ __global__ __launch_bounds__(kScanThreads) void k_select(
             col_len[c] = 0;
         }
     }
-    int msum = wave_sum(mcnt);
-    if (lane_id() == 0 && msum) atomic_add_i64(&ctr->M, (long long)msum);
+    // one atomic per tile (see k_rank_groups)
+    const int msum = wave_sum(mcnt);
+    if (lane_id() == 0) s_tmp[tid / kWave] = msum;
+    __syncthreads();
+    if (tid == 0) {
+        int msum_tile = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) msum_tile += s_tmp[w];
+        if (msum_tile) atomic_add_i64(&ctr->M, (long long)msum_tile);
+    }
     if (t == ntiles - 1 && tid == 0) {
         const long long kt = s_pc + totc;
         const long long nt = s_pn + totn;

@@ -163,6 +163,7 @@ __device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups, i
         if (lc < nloc && sub == 0) s_f[lc] = is_long ? -1 : acc;
         __syncthreads();
         int b = kBinEmpty;
+        long long fsum = 0;
         if (tid < nloc) {
             const int64_t j = j0 + tid;
             const long long f = s_f[tid];
@@ -171,9 +172,12 @@ __device__ __forceinline__ void flop_column_tile(int64_t blk, int64_t ngroups, i
                 a.flop[j] = f;
                 b = sym_bin_of(f, a.th);
                 a.sym_bin[j] = b;
-                if (f) atomic_add_i64(&s_flops, f);
+                fsum = f;
             }
         }
+        // one LDS atomic per wave for the flops total (not one per column)
+        fsum = wave_sum(fsum);
+        if (lane_id() == 0 && fsum) atomic_add_i64(&s_flops, fsum);
         const int slot = wave_bin_slot(s_cnt, b);
         if (tid < nloc) s_bl[rd * COLS + tid] = b != kBinEmpty ? (b << 24) | slot : kBinEmpty << 24;
     }
