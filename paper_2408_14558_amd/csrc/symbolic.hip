@@ -552,7 +552,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
             for_each_term<kDenseThreads, float, kSymDenseUnroll, kDenseThreads, false>(
                 Bcolptr[j], Bcolptr[j + 1], tr, nullptr, &L.st, gt,
                 [&](int64_t p) { return At_rowidx[p]; },
-                [&](int32_t r, float) { atomicOr(&s_bits[r >> 5], 1u << (r & 31)); });
+                [&](int32_t r, float) {
+                    // a row most products reach is set once, not once per
+                    // product (an LDS read costs less than an atomic that
+                    // collides with the wave's other lanes)
+                    const uint32_t bit = 1u << (r & 31);
+                    if (!(s_bits[r >> 5] & bit)) atomicOr(&s_bits[r >> 5], bit);
+                });
             int c = 0;
             for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
             int total;
