@@ -303,7 +303,8 @@ typedef struct spgemm_batch_s *spgemm_batch_t;
 
 /*
  * spgemm_batched - the numeric phase of `count` planned products of one
- * dtype, as one launch DAG on `stream`:
+ * dtype, as one launch DAG on `stream` (or one persistent launch, see
+ * below):
  *   count    number of products (>= 1).
  *   plans    HOST array of `count` distinct plans that have all finished
  *            spgemm_symbolic.
@@ -319,9 +320,11 @@ typedef struct spgemm_batch_s *spgemm_batch_t;
  *   stream   hipStream_t (NULL = null stream); side streams fork from it and
  *            join back, so every product has finished when `stream` reaches
  *            the end of the call.
- * The library keeps one batch per distinct (plans, io) table (built with the
- * default tuning on first use, so that call synchronises the plans'
- * streams once) until one of its plans is destroyed.  Runs of one table
+ * The library keeps one batch per distinct (plans, io) table (built on first
+ * use with the batch fields of plans[0]'s tuning: batch_streams, and
+ * batch_persistent = 1 for one persistent launch per run; that call
+ * synchronises the plans' streams once) until one of its plans is
+ * destroyed.  Runs of one table
  * must not overlap (they share the plans' A~ and scratch); work on the
  * plans' own streams is not ordered with the batch.  Errors: EINVAL (bad
  * table or mode, repeated plan), ESTATE (no symbolic, replay without

@@ -296,7 +296,15 @@ int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch
         if (!b) {
             if (mode == 2)
                 return fail(SPGEMM_ESTATE, "replay needs a capture (mode 1) of the same table first");
-            if (int rc = spgemm_batch_create(count, plans, io, nullptr, &b)) return rc;
+            // the batch fields (side streams, persistent launch) come from
+            // the first plan's tuning, which the autotuner fills
+            spgemm_tuning tun;
+            spgemm_default_tuning(&tun);
+            if (plans[0]) {
+                tun.batch_streams = plans[0]->tun.batch_streams;
+                tun.batch_persistent = plans[0]->tun.batch_persistent;
+            }
+            if (int rc = spgemm_batch_create(count, plans, io, &tun, &b)) return rc;
             g_cache.push_back(CachedBatch{std::vector<spgemm_plan_t>(plans, plans + count),
                                           std::vector<spgemm_batch_io>(io, io + count), b});
         }

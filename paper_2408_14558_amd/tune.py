@@ -32,6 +32,10 @@ SEARCH_SPACE: Dict[str, Tuple[int, ...]] = {
     "hash_max_nnz": (512, 1024, 2048),
     "hash_max_flop": (1024, 2048, 4096),
     "medium_kernel": (1, 2),
+    # the dense kernel's value window (0: as many slots as the LDS holds)
+    # and the product count from which dense columns are handed out first
+    "dense_window": (0, 8192, 4096),
+    "dense_first_flop": (1 << 18, 1 << 16, 1 << 20, 0),
 }
 
 CACHE_VERSION = 1
@@ -155,12 +159,26 @@ def tune(A: DeviceCsc, Bi: DeviceCsc, offsets=None, block_size: int = 256, reps:
 
 
 def tune_batch(plans: Sequence[Plan], io: Sequence[dict],
-               streams: Iterable[int] = (1, 2, 4, 8), reps: int = 10) -> Tuple[int, dict]:
-    """Side-stream count with the fastest graph replay of a batch."""
+               streams: Iterable[int] = (1, 2, 4, 8), persistent: bool = True,
+               reps: int = 10) -> Tuple[dict, dict]:
+    """The batched form with the fastest graph replay of a batch: the stream
+    DAG on each side-stream count, and (when the products allow it) one
+    persistent launch.  Returns (the batch fields of spgemm_tuning, report);
+    spgemm_batched takes them from the first plan's tuning."""
     s = torch.cuda.Stream()
+    cands = [({"batch_streams": ns, "batch_persistent": 0}, f"streams={ns}") for ns in streams]
+    if persistent:
+        cands.append(({"batch_streams": 0, "batch_persistent": 1}, "persistent"))
     times = {}
-    for ns in streams:
-        b = Batch(plans, io, make_tuning(batch_streams=ns))
+    best = None
+    for fields, name in cands:
+        try:
+            b = Batch(plans, io, make_tuning(**fields))
+        except _lib.SpgemmError as e:
+            if e.code != _lib.EUNSUPPORTED:
+                raise
+            times[name] = None  # this form does not take these products
+            continue
         try:
             b.run(1, stream=s)
             s.synchronize()
@@ -171,8 +189,10 @@ def tune_batch(plans: Sequence[Plan], io: Sequence[dict],
                 b.run(2, stream=s)
             e1.record(s)
             s.synchronize()
-            times[ns] = e0.elapsed_time(e1) / reps
+            b.check()
+            times[name] = e0.elapsed_time(e1) / reps
         finally:
             b.close()
-    best = min(times, key=times.get)
-    return best, {"ms": times}
+        if best is None or times[name] < times[best[1]]:
+            best = (fields, name)
+    return dict(best[0]), {"ms": times, "best": best[1]}

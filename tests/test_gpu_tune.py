@@ -42,6 +42,23 @@ def test_tune_batch_picks_a_stream_count():
         io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
     torch.cuda.synchronize()
     best, rep = spg.tune.tune_batch(plans, io, streams=(1, 4), reps=2)
-    assert best in (1, 4) and set(rep["ms"]) == {1, 4}
+    assert set(rep["ms"]) == {"streams=1", "streams=4", "persistent"}
+    assert rep["best"] in rep["ms"] and rep["ms"][rep["best"]] == min(
+        t for t in rep["ms"].values() if t is not None)
+    assert set(best) == {"batch_streams", "batch_persistent"}
+    # spgemm_batched takes the batch fields from the first plan's tuning
+    t = spg.tuning(**best)
+    p0 = spg.Plan(plans[0].A, plans[0].Bi, None, 64, tuning=t)
+    C0 = p0.run()
+    tab = [{"C_rowidx": C0.rowidx, "C_vals": C0.vals}] + io[1:]
+    before = [d["C_vals"].clone() for d in tab]
+    for d in tab:
+        d["C_vals"].zero_()
+    spg.batched([p0] + plans[1:], tab, 0)
+    torch.cuda.synchronize()
+    for d, v in zip(tab, before):  # same products (LDS sums may round differently)
+        tol = 1e-12 * max(float(v.abs().max()), 1.0) if v.numel() else 0.0
+        assert torch.allclose(d["C_vals"], v, rtol=1e-12, atol=tol)
+    p0.close()
     for p in plans:
         p.close()

@@ -38,7 +38,7 @@ def test_cache_round_trip(tmp_path):
 
 def test_coordinate_search_finds_the_separable_minimum():
     target = {"tiny_max_flop": 128, "hash_max_nnz": 1024, "hash_max_flop": 2048,
-              "medium_kernel": 2}
+              "medium_kernel": 2, "dense_window": 4096, "dense_first_flop": 1 << 18}
     calls = []
 
     def cost(f):
@@ -46,7 +46,7 @@ def test_coordinate_search_finds_the_separable_minimum():
         return sum((f[k] != v) * (i + 1) for i, (k, v) in enumerate(target.items()))
 
     start = {"tiny_max_flop": 256, "hash_max_nnz": 2048, "hash_max_flop": 4096,
-             "medium_kernel": 1}
+             "medium_kernel": 1, "dense_window": 0, "dense_first_flop": 1 << 18}
     best, t, log = tune.coordinate_search(cost, start)
     assert best == target and t == 0
     assert len(log) == len(calls)
