@@ -245,8 +245,11 @@ int spgemm_symbolic_noalloc(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC
  * spgemm_numeric - values of C_i = A * B_i.
  *
  *   A_vals    dtype[nnz(A)] new values of A on the planned pattern, or NULL
- *             to use the values gathered by spgemm_plan.  Non-NULL values are
- *             gathered into A~ first (values half of Alg. 1's fetch).
+ *             to use the values A~ holds (gathered by spgemm_plan, or by the
+ *             last call that gathered new ones).  Non-NULL values are
+ *             gathered into A~ first (values half of Alg. 1's fetch) - except
+ *             when A~ holds every entry of A (every nonzero column chosen),
+ *             where they are read in place and A~ keeps its values.
  *   Bi_vals   dtype[nnz(B_i)] or NULL for the values given to spgemm_plan.
  *   C_rowidx  int32[nnzC], caller-allocated; receives ascending row ids.
  *   C_vals    dtype[nnzC], caller-allocated.

@@ -449,6 +449,17 @@ int ensure_split_table(Plan &p, int64_t dense_columns) {
     return SPGEMM_OK;
 }
 
+int take_new_a_values(Plan &p, const void *A_vals, const void **At_vals) {
+    *At_vals = nullptr;
+    if (!A_vals) return SPGEMM_OK;
+    // every nonzero column chosen: A~'s entries are A's, in A's order
+    if (p.nnzAt_pub == p.nnzA) {
+        *At_vals = A_vals;
+        return SPGEMM_OK;
+    }
+    return launch_gather_values(p, A_vals);
+}
+
 int finish_symbolic_counts(Plan &p) {
     if (!p.counts_pending) return SPGEMM_OK;
     SPG_HIP(wait_flag(p, kFlagColptr, [&] { return hipStreamSynchronize(p.stream); }));
@@ -458,6 +469,7 @@ int finish_symbolic_counts(Plan &p) {
         return fail(SPGEMM_EHIP, "the symbolic scan's counts were not published");
     p.flops = p.hpub->flops;
     for (int b = 0; b < kNumBins; ++b) p.num_count[b] = p.hpub->num_count[b];
+    p.nnzAt_pub = p.hpub->nnz_At;
     p.counts_pending = false;
     return SPGEMM_OK;
 }
@@ -895,6 +907,7 @@ static int symbolic_impl(spgemm_plan_t plan, int64_t *C_colptr, int64_t *nnzC, b
             return early ? hipStreamSynchronize(p.stream) : hipEventSynchronize(p.counts_ready);
         }));
         for (int b = 0; b < kNumBins; ++b) p.sym_count[b] = p.hpub->sym_count[b];
+        p.nnzAt_pub = p.hpub->nnz_At;
     } else if ((rc = launch_symbolic_reset(p))) {
         return rc;
     }
@@ -976,9 +989,10 @@ int spgemm_numeric(spgemm_plan_t plan, const void *A_vals, const void *Bi_vals,
     if (p.nnzC > 0 && !Bv) return fail(SPGEMM_EINVAL, "no values for B_i");
     if (!A_vals && !p.Avals && p.nnzC > 0) return fail(SPGEMM_EINVAL, "no values for A");
     int rc;
-    if (A_vals && (rc = launch_gather_values(p, A_vals))) return rc;
+    const void *Atv = nullptr;
+    if ((rc = take_new_a_values(p, A_vals, &Atv))) return rc;
     if ((rc = ensure_split_table(p))) return rc;
-    return launch_numeric_bins(p, Bv, C_rowidx, C_vals);
+    return launch_numeric_bins(p, Bv, C_rowidx, C_vals, Atv);
 }
 
 int spgemm_backward(spgemm_plan_t plan, const int64_t *C_colptr, const int32_t *C_rowidx,

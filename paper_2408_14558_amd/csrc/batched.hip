@@ -46,7 +46,7 @@ struct spgemm_batch_s {
 // Kernels product t enqueues per run (for spgemm_batch_info).
 static int64_t product_launches(const Plan &p, const spgemm_batch_io &io) {
     int64_t n = 0;
-    if (io.A_vals && p.k > 0 && p.nnzA > 0) ++n;
+    if (io.A_vals && p.k > 0 && p.nnzA > 0 && p.nnzAt_pub != p.nnzA) ++n;  // a value gather
     if (p.n == 0 || p.nnzC == 0) return n;
     for (int bin = kBinTiny; bin < kBinDense; ++bin) n += p.num_count[bin] > 0;
     n += p.num_count[kBinDense] + p.num_count[kBinDenseFirst] > 0;  // one launch serves both
@@ -60,9 +60,10 @@ static int run_product(spgemm_batch_s &b, int t, hipStream_t s) {
     const spgemm_batch_io &io = b.io[t];
     const hipStream_t keep = p.stream;
     p.stream = s;
-    int rc = SPGEMM_OK;
-    if (io.A_vals) rc = launch_gather_values(p, io.A_vals);
-    if (!rc) rc = launch_numeric_bins(p, io.B_vals ? io.B_vals : p.Bvals, io.C_rowidx, io.C_vals);
+    const void *Atv = nullptr;
+    int rc = take_new_a_values(p, io.A_vals, &Atv);
+    if (!rc)
+        rc = launch_numeric_bins(p, io.B_vals ? io.B_vals : p.Bvals, io.C_rowidx, io.C_vals, Atv);
     p.stream = keep;
     return rc;
 }

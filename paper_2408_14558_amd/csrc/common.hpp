@@ -228,6 +228,8 @@ __device__ __forceinline__ void publish_counters(const DevCounters *ctr, Publish
     else if (t < 2 + 2 * kNumBins)
         out->num_count[t - 2 - kNumBins] = __hip_atomic_load(
             &ctr->num_count[t - 2 - kNumBins].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (t == 2 + 2 * kNumBins)
+        out->nnz_At = __hip_atomic_load(&ctr->nnz_At, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // wave 0 wrote every field: thread 0's system-scope release store
     // orders them before the flag

@@ -106,6 +106,7 @@ struct PublishedCounts {
     long long nnzC;
     int sym_count[kNumBins];
     int num_count[kNumBins];
+    long long nnz_At;  // entries of A~ (the plan's selection, final before the flops pass)
 };
 
 enum Ticket {
@@ -153,6 +154,7 @@ struct Plan {
     Thresholds th{};
 
     int64_t m = 0, k = 0, n = 0, nnzA = 0, nnzB = 0;
+    int64_t nnzAt_pub = -1;  // nnz(A~) as the device published it (-1: not yet read)
     const int64_t *Acolptr = nullptr;
     const int32_t *Arowidx = nullptr;
     const void *Avals = nullptr;
@@ -312,7 +314,13 @@ int ensure_split_table(Plan &p, int64_t dense_columns = -1);
 // SPGEMM_ESTATE when the plan's kept symbolic data sat in the no-allocation
 // scratch array and a later call has taken the array over.
 int check_kept(const Plan &p);
-int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals);
+// At_vals: A~'s values for this call (NULL: the plan's A~).
+int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals,
+                        const void *At_vals = nullptr);
+// New values of A for one numeric call: when A~ holds every entry of A (in
+// A's order), they are A~'s values as they are and nothing is gathered
+// (returns them); otherwise they are gathered into A~ (returns NULL).
+int take_new_a_values(Plan &p, const void *A_vals, const void **At_vals);
 int launch_backward(Plan &p, const int64_t *Ccolptr, const int32_t *Crow, const void *Avals,
                     const void *Bvals, const void *dC, void *dA, void *dB);
 // The single-launch form of a batch (persistent.hip): its work items,

@@ -208,8 +208,8 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
 }
 
 template <typename V>
-static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
-    NumArgs<V> a{p.m,         p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, (const V *)p.At_vals,
+static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval, const V *Atv) {
+    NumArgs<V> a{p.m,         p.Bcolptr, p.term_range(), Bvals,  p.At_rowidx, Atv,
                  p.C_colptr,  Crow,      Cval,           p.flop, p.Browidx,   p.split,
                  p.col_slot,  p.dense_bits, p.tiny_perm, p.nblk};
     const int64_t n = p.n;
@@ -259,11 +259,15 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval) {
     return SPGEMM_OK;
 }
 
-int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals) {
+int launch_numeric_bins(Plan &p, const void *Bvals, int32_t *Crow, void *Cvals,
+                        const void *At_vals) {
     if (p.n == 0 || p.nnzC == 0) return SPGEMM_OK;
+    const void *Atv = At_vals ? At_vals : p.At_vals;
     if (p.dtype == SPGEMM_F64)
-        return numeric_bins_t<double>(p, (const double *)Bvals, Crow, (double *)Cvals);
-    return numeric_bins_t<float>(p, (const float *)Bvals, Crow, (float *)Cvals);
+        return numeric_bins_t<double>(p, (const double *)Bvals, Crow, (double *)Cvals,
+                                      (const double *)Atv);
+    return numeric_bins_t<float>(p, (const float *)Bvals, Crow, (float *)Cvals,
+                                 (const float *)Atv);
 }
 
 }  // namespace spg

@@ -4,7 +4,8 @@
 // items that the workgroups of a single kernel take in turn.
 //
 // Work items, in dependency order (products by depth; at each depth first
-// every product's value gather, then its numeric columns):
+// every product's value gather, then its numeric columns; a product whose A~
+// holds all of A reads its new A values in place and has no gather):
 //   gather  tiles of 64 columns of A whose new values go into A~ (the
 //           values half of Alg. 1's fetch, for a product whose A is another
 //           product's C);
@@ -16,8 +17,9 @@
 // An atomic ticket hands the items out in that order.  An item waits only
 // for items with lower tickets (its own product's gathers before its
 // numeric columns; the whole numeric phase of the product whose C it
-// reads), and each of those is held by a workgroup that is already running
-// and itself waits only on lower tickets, so the launch always drains.
+// reads, or its A values when they are read in place), and each of those is
+// held by a workgroup that is already running and itself waits only on
+// lower tickets, so the launch always drains.
 //
 // Completion is published per item, the way the chained scans of this
 // library publish their tile states: a workgroup that finishes an item makes
@@ -149,6 +151,10 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(const PItem *__r
                 waited = true;
                 ok = wait_items(flags, P.gather_first, P.n_gather, ctr + kPError, wait_ticks,
                                 &s_stop);
+            } else if (P.dep_A >= 0) {  // A's new values read in place: they are dep_A's C
+                waited = true;
+                ok = wait_items(flags, prods[P.dep_A].numeric_first, prods[P.dep_A].n_numeric,
+                                ctr + kPError, wait_ticks, &s_stop);
             }
             if (ok && P.dep_B >= 0) {
                 waited = true;
@@ -260,8 +266,11 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
         PProd<V> &P = prods[t];
         std::memset(&P, 0, sizeof(P));
         const V *Bv = (const V *)(io[t].B_vals ? io[t].B_vals : p.Bvals);
+        // new A values read in place when A~ holds all of A (nothing to gather)
+        const bool in_place = io[t].A_vals && p.nnzAt_pub == p.nnzA;
+        const V *Atv = (const V *)(in_place ? io[t].A_vals : p.At_vals);
         P.a = NumArgs<V>{p.m,        p.Bcolptr,    p.term_range(), Bv,        p.At_rowidx,
-                         (const V *)p.At_vals,     p.C_colptr,     io[t].C_rowidx,
+                         Atv,                      p.C_colptr,     io[t].C_rowidx,
                          (V *)io[t].C_vals,        p.flop,         p.Browidx, p.split,
                          p.col_slot, p.dense_bits, p.tiny_perm, p.nblk};
         for (int b = 0; b < kNumBins; ++b) P.list[b] = p.num_list + (int64_t)b * p.n;
@@ -280,7 +289,7 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
     for (const std::vector<int> &lvl : levels) {
         for (int t : lvl) {  // value gathers of this depth
             Plan &p = *plans[t];
-            if (!io[t].A_vals || p.k == 0 || p.nnzA == 0) continue;
+            if (!io[t].A_vals || p.k == 0 || p.nnzA == 0 || p.nnzAt_pub == p.nnzA) continue;
             const int64_t tiles = (p.k + kGatherCols - 1) / kGatherCols;
             const int64_t per = item_size(tiles, 1, target);
             prods[t].gather_first = (int32_t)items.size();

@@ -763,6 +763,7 @@ __global__ __launch_bounds__(kSmallScanThreads) void k_colptr_scan_small(
         ctr->nnzC = carry;
         hout->flops = ctr->flops.v;
         hout->nnzC = carry;
+        hout->nnz_At = ctr->nnz_At;
     }
     if (tid < kNumBins) {
         ctr->num_count[tid].v = s_base[tid];

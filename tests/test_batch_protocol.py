@@ -114,11 +114,13 @@ class Memory:
 
 
 def make_dag(rng, nprod):
+    """Products with their dependencies; `in_place` products read their A
+    values where they lie (A~ holds all of A) and so have no gathers."""
     prods = []
     for t in range(nprod):
         dep_a = rng.randrange(-1, t) if t else -1
         dep_b = rng.randrange(-1, t) if t else -1
-        prods.append({"dep_A": dep_a, "dep_B": dep_b})
+        prods.append({"dep_A": dep_a, "dep_B": dep_b, "in_place": rng.random() < 0.4})
     return prods
 
 
@@ -150,6 +152,9 @@ def items_of(prods, width, tile):
         lvl = [t for t in range(len(prods)) if depth[t] == d]
         for kind in ("gather", "numeric"):
             for t in lvl:
+                if kind == "gather" and prods[t].get("in_place"):
+                    span[t][kind] = (len(items), 0)
+                    continue
                 span[t][kind] = (len(items), len(range(0, width, tile)))
                 for f in range(0, width, tile):
                     items.append((kind, t, f))
@@ -199,7 +204,10 @@ def run_launch(mem, prods, width, tile, inputs, n_wg, xcds, rng, release=True, a
                 if p["dep_A"] >= 0:
                     need.append((p["dep_A"], "numeric"))
             else:
-                need.append((t, "gather"))
+                if not p.get("in_place"):
+                    need.append((t, "gather"))
+                elif p["dep_A"] >= 0:  # A values read in place: dep_A's C
+                    need.append((p["dep_A"], "numeric"))
                 if p["dep_B"] >= 0:
                     need.append((p["dep_B"], "numeric"))
             ok = True
@@ -225,7 +233,11 @@ def run_launch(mem, prods, width, tile, inputs, n_wg, xcds, rng, release=True, a
                 for j in range(f, min(width, f + tile)):
                     s = 0
                     for i in range(width):
-                        a = mem.load(x, ("At", t, i))
+                        if p.get("in_place"):
+                            asrc = ("C", p["dep_A"], i) if p["dep_A"] >= 0 else ("A", t, i)
+                        else:
+                            asrc = ("At", t, i)
+                        a = mem.load(x, asrc)
                         b = ("C", p["dep_B"], (i + j) % width) if p["dep_B"] >= 0 \
                             else ("B", t, (i + j) % width)
                         s += a * mem.load(x, b)
