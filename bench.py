@@ -228,6 +228,7 @@ def bench_batched(spg, reps=20):
     b.run(1, stream=s)
     graph_ms = _time_on(s, lambda: b.run(2, stream=s), reps)
     b_amg = spg.Batch(plans[:8], io[:8])
+    eager_amg_ms = _time_on(s, lambda: b_amg.run(0, stream=s), reps)
     b_amg.run(1, stream=s)
     graph_amg_ms = _time_on(s, lambda: b_amg.run(2, stream=s), reps)
     b.check()
@@ -259,8 +260,10 @@ def bench_batched(spg, reps=20):
         "speedup_vs_plain": round(plain_ms / graph_ms, 3),
         "graph_GFLOPs": round(2 * flops / (graph_ms * 1e-3) / 1e9, 2),
         "amg_only": {"products": 8, "flops": int(amg_flops), "plain_ms": round(plain_amg_ms, 4),
+                     "dag_eager_ms": round(eager_amg_ms, 4),
                      "graph_replay_ms": round(graph_amg_ms, 4),
                      "speedup_vs_plain": round(plain_amg_ms / graph_amg_ms, 3),
+                     "eager_speedup_vs_plain": round(plain_amg_ms / eager_amg_ms, 3),
                      "persistent_ms": round(p_amg_ms, 4),
                      "persistent_graph_replay_ms": round(p_amg_graph_ms, 4),
                      "persistent_speedup_vs_plain": round(plain_amg_ms / p_amg_ms, 3)},
