@@ -424,3 +424,26 @@ def test_plans_reuse_pooled_workspace():
     for _ in range(5):
         C = spg.spgemm(Ad, Ad, None, 64)
         assert np.array_equal(C.rowidx.cpu().numpy(), ref.rowidx)
+
+
+def test_set_stream_between_symbolic_and_numeric():
+    """spgemm_plan_set_stream right after a symbolic phase whose counts are
+    still in flight (one-workgroup scan, n <= 8192): the counts are read
+    before the switch and the new stream's work is ordered after the old
+    stream's, so numeric on the new stream gives the oracle's product."""
+    A = synth.erdos_renyi(4096, 4096, 12, seed=61)
+    B = synth.erdos_renyi(4096, 2000, 9, seed=62)
+    ref = oracle.spgemm(A, B)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    Ad, Bd = _dev(A, torch.float64), _dev(B, torch.float64)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with spg.Plan(Ad, Bd, None, 64, stream=s1) as p:
+            colptr = p.symbolic()
+            p.set_stream(s2)
+            with torch.cuda.stream(s2):
+                rows, vals = p.numeric()
+            s2.synchronize()
+            assert np.array_equal(colptr.cpu().numpy(), ref.colptr)
+            assert np.array_equal(rows.cpu().numpy(), ref.rowidx)
+            assert_values(vals.cpu().numpy(), ref.vals, ref.absvals, True)
