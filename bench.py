@@ -688,6 +688,12 @@ def main():
                            for k in ph},
             "GFLOPs_symbolic_plus_numeric": round(
                 2 * flops / ((ph["symbolic"] + ph["numeric"]) * 1e-3) / 1e9, 2),
+            # upper reference: every product's row id (symbolic) or row id and
+            # value (numeric) read once, as a Gustavson walk streams them
+            "gustavson_stream_bytes": {"symbolic": 4 * flops, "numeric": (4 + vsize) * flops},
+            "gustavson_stream_GBs": {
+                "symbolic": round(4 * flops / (ph["symbolic"] * 1e-3) / 1e9, 2),
+                "numeric": round((4 + vsize) * flops / (loop_ms * 1e-3) / 1e9, 2)},
         },
         "sizes": {"flops": flops, "nnz_C": st["nnz_C"], "nnz_At": st["nnz_At"], "kt": st["kt"],
                   "M": st["M"], "K": st["K"], "cv_memA": round(st["cv_memA"], 4),
