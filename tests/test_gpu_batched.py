@@ -295,3 +295,46 @@ def test_persistent_batch_matches_plain(workload):
         check()
     finally:
         b.close()
+
+
+def test_persistent_batch_fp32_with_a_dependency():
+    """The persistent launch in FP32: ER products (tiny and hash columns) and
+    one product whose B is another product's C (read inside the launch),
+    against the oracle on FP32-rounded inputs (normwise)."""
+    pairs = synth.er_batch(3, seed=12)
+    plans, io, refs = [], [], []
+    for A, B in pairs:
+        p = spg.Plan(spg.DeviceCsc.from_host(A, dtype=torch.float32),
+                     spg.DeviceCsc.from_host(B, dtype=torch.float32), None, 64)
+        C = p.run()
+        plans.append(p)
+        io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+        refs.append(oracle.spgemm(synth.as_fp32(A), synth.as_fp32(B)))
+    # A1 * C_0 with a sparse A1: its B values are product 0's C
+    C0 = refs[0]
+    C0f = synth.CSC(C0.nrows, C0.ncols, C0.colptr, C0.rowidx,
+                    np.asarray(C0.vals, dtype=np.float32).astype(np.float64))
+    A1 = synth.erdos_renyi(C0.nrows, C0.nrows, 2, seed=13)
+    Cd0 = spg.DeviceCsc(C0.nrows, C0.ncols, torch.as_tensor(C0.colptr).cuda(),
+                        torch.as_tensor(C0.rowidx).cuda(),
+                        torch.as_tensor(np.asarray(C0f.vals, dtype=np.float32)).cuda())
+    p3 = spg.Plan(spg.DeviceCsc.from_host(A1, dtype=torch.float32), Cd0, None, 64)
+    C3 = p3.run()
+    plans.append(p3)
+    io.append({"B_vals": io[0]["C_vals"], "C_rowidx": C3.rowidx, "C_vals": C3.vals, "dep_B": 0})
+    refs.append(oracle.spgemm(synth.as_fp32(A1), C0f))
+    assert all(_no_dense(p) for p in plans)
+    b = spg.Batch(plans, io, spg.tuning(batch_persistent=1))
+    try:
+        for rep in range(2):
+            for d in io:
+                d["C_vals"].fill_(-3.0)
+            b.run(0)
+            b.check()
+            for d, ref in zip(io, refs):
+                assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
+                assert_values(d["C_vals"].cpu().numpy(), ref.vals, ref.absvals, False)
+    finally:
+        b.close()
+        for p in plans:
+            p.close()
