@@ -338,6 +338,57 @@ __device__ __forceinline__ int bitmap_ranks(const uint32_t *bits, uint16_t *wpre
     return total;
 }
 
+// A kept bitmap copied from device memory into LDS with the word ranks of
+// bitmap_ranks (superblock bases included) computed on the way: each wave
+// takes the same range of words as there and holds them in registers, so
+// the bitmap is read once instead of once for the copy and twice for the
+// ranks.  G = 1024 threads and at most 8192 words (one band): at most eight
+// words per lane.  All G threads call; ends with a group barrier.
+template <int G>
+__device__ __forceinline__ int load_bitmap_ranks(const uint32_t *__restrict__ src, uint32_t *bits,
+                                                 uint16_t *wpre, int *sbase, int nw, int *red) {
+    constexpr int NW = G / kWave;
+    constexpr int kRegs = 8;
+    static_assert(NW * kWave * kRegs >= (int)(kMaxDenseRows >> 5), "eight words per lane");
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    int per = kWave;
+    while (per * NW < nw) per <<= 1;
+    const int wb = min(nw, wv * per), we = min(nw, wb + per);
+    uint32_t wr[kRegs];
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) {
+        const int w = wb + i * kWave + lane;
+        wr[i] = w < we ? src[w] : 0u;
+    }
+    int mine = 0;
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) {
+        const int w = wb + i * kWave + lane;
+        if (w < we) bits[w] = wr[i];
+        mine += __popc(wr[i]);
+    }
+    const int wave_total = wave_sum(mine);
+    int total;
+    const int pre = group_excl_scan<G>(lane == 0 ? wave_total : 0, red, &total);
+    const int off = __shfl(pre, 0);
+    if (lane == 0 && wb < we && (wb & ((1 << kSuperShift) - 1)) == 0)
+        sbase[wb >> kSuperShift] = off;
+    __syncthreads();
+    const int sb = wb < we ? sbase[wb >> kSuperShift] : 0;
+    int run = off;
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) {
+        if (wb + i * kWave >= we) break;  // the same for the whole wave
+        const int w = wb + i * kWave + lane;
+        const int c = __popc(wr[i]);
+        const int incl = wave_incl_scan(c);
+        if (w < we) wpre[w] = (uint16_t)(run + incl - c - sb);
+        run += __shfl(incl, kWave - 1);
+    }
+    __syncthreads();
+    return total;
+}
+
 __device__ __forceinline__ int word_rank(const uint16_t *wpre, const int *sbase, int w) {
     return (sbase ? sbase[w >> kSuperShift] : 0) + wpre[w];
 }
@@ -532,10 +583,10 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
         const int32_t R1 = (int32_t)min<int64_t>(a.m, (int64_t)R0 + kMaxDenseRows);
         const int nw = (R1 - R0 + 31) >> 5;
         const int sb0 = R0 >> kSplitShift;  // the band's first block
+        int total = -1;  // set with the ranks when a kept bitmap is loaded
         if (slot >= 0) {  // the symbolic phase kept this column's row bitmap
-            const uint32_t *src = a.dense_bits + (size_t)slot * nw;
-            copy_words<G>(bits, src, nw);
-            __syncthreads();
+            total = load_bitmap_ranks<G>(a.dense_bits + (size_t)slot * nw, bits, wpre, S.sbase,
+                                         nw, S.red);
         } else if (!banded) {
             zero_words<G>(bits, nw);
             __syncthreads();
@@ -558,7 +609,7 @@ __device__ __forceinline__ void num_dense_column(const NumArgs<V> &a, int32_t j,
                 gt, mark);
             __syncthreads();
         }
-        const int total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, nullptr, 0);
+        if (total < 0) total = bitmap_ranks<G>(bits, wpre, S.sbase, nw, S.red, nullptr, 0);
         const int nblk = (nw + kBlockWords - 1) / kBlockWords;  // blocks of the band (<= 32)
         for (int w0r = 0; w0r < total;) {
             if (gt < kWave) {

@@ -559,15 +559,20 @@ __global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
                     const uint32_t bit = 1u << (r & 31);
                     if (!(s_bits[r >> 5] & bit)) atomicOr(&s_bits[r >> 5], bit);
                 });
+            // the count, and the copy of the bitmap the numeric phase reuses,
+            // from one read of each word
+            uint32_t *dst = keep_bits ? keep_bits + (size_t)w * nw : nullptr;
             int c = 0;
-            for (int i = gt; i < nw; i += kDenseThreads) c += __popc(s_bits[i]);
+            for (int i = gt; i < nw; i += kDenseThreads) {
+                const uint32_t b = s_bits[i];
+                c += __popc(b);
+                if (dst) dst[i] = b;
+            }
             int total;
             (void)group_excl_scan<kDenseThreads>(c, L.red, &total);
-            if (gt == 0) Ccount[j] = total;
-            if (keep_bits) {  // the numeric phase reuses this bitmap
-                uint32_t *dst = keep_bits + (size_t)w * nw;
-                copy_words<kDenseThreads>(dst, s_bits, nw);
-                if (gt == 0) col_slot[j] = w;
+            if (gt == 0) {
+                Ccount[j] = total;
+                if (dst) col_slot[j] = w;
             }
         }
     } else {
