@@ -84,24 +84,23 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
     const int wv = threadIdx.x / kWave, lane = lane_id();
     int32_t *my = stage[wv];
     // places the set rows of `word` (word index wi, lanes' words in order)
-    // at base and returns their number (wave-uniform)
-    auto place = [&](uint32_t word, int wi, long long base) {
-        const int pc = __popc(word);
-        const int incl = wave_incl_scan(pc);
-        const int n = __shfl(incl, kWave - 1);
-        int rk = incl - pc;
+    // at base; incl is the wave's inclusive scan of the words' bit counts and
+    // n its total (wave-uniform)
+    auto place = [&](uint32_t word, int wi, long long base, int incl, int n) {
+        int rk = incl - __popc(word);
         while (word) {
             my[swz(rk++)] = (wi << 5) + __ffs(word) - 1;
             word &= word - 1;
         }
         wave_sync();
-        // four LDS reads in flight before their stores
+        // up to four LDS reads in flight before their stores (only the
+        // reads some lane needs)
         for (int i0 = 0; i0 < n; i0 += 4 * kWave) {
-            int32_t v[4];
+            int32_t v[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * kWave + lane;
-                v[u] = my[swz(min(i, n - 1))];
+                if (i0 + u * kWave < n) v[u] = my[swz(min(i, n - 1))];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -110,7 +109,6 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
             }
         }
         wave_sync();
-        return n;
     };
     for (int w = blockIdx.x * kRowWaves + wv; w < count; w += gridDim.x * kRowWaves) {
         const int32_t j = list[w];
@@ -133,12 +131,21 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
             for (int d = 0; d < kRowAhead; ++d) {
                 const int wi = s0 + d * kWave + lane;
                 const uint32_t word = wi < nw ? cur[d] : 0u;
-                const int total = __shfl(wave_incl_scan(__popc(word)), kWave - 1);
+                const int incl = wave_incl_scan(__popc(word));
+                const int total = __shfl(incl, kWave - 1);
                 if (total <= kRowStage) {
-                    base += place(word, wi, base);
+                    place(word, wi, base, incl, total);
+                    base += total;
                 } else {  // each half's 32 words hold at most kRowStage bits
-                    base += place(lane < 32 ? word : 0u, wi, base);
-                    base += place(lane < 32 ? 0u : word, wi, base);
+                    const uint32_t lo = lane < 32 ? word : 0u, hi = lane < 32 ? 0u : word;
+                    const int il = wave_incl_scan(__popc(lo));
+                    const int nl = __shfl(il, kWave - 1);
+                    place(lo, wi, base, il, nl);
+                    base += nl;
+                    const int ih = wave_incl_scan(__popc(hi));
+                    const int nh = __shfl(ih, kWave - 1);
+                    place(hi, wi, base, ih, nh);
+                    base += nh;
                 }
             }
 #pragma unroll
