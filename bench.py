@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import subprocess
 import sys
@@ -189,8 +190,10 @@ def bench_batched(spg, reps=20):
     3D 7-point Laplacian on 64^3 (2x2x2 aggregation, 4 levels, A_c =
     P^T (A P), chained) plus 64 independent ER products (seed 4).  Plain =
     every product's spgemm_numeric in order on one stream; batched = one
-    replay of the captured DAG.  Both gather new A values where the chain
-    needs them and write the same outputs."""
+    replay of the captured DAG (the products of a depth with tiny and hash
+    columns only sharing one launch per bin; `separate_graph_replay_ms`:
+    every product launching its own kernels).  All gather new A values where
+    the chain needs them and write the same outputs."""
     import torch
     import synth
     A0 = spg.DeviceCsc.from_host(synth.laplacian3d(64))
@@ -227,6 +230,11 @@ def bench_batched(spg, reps=20):
     eager_ms = _time_on(s, lambda: b.run(0, stream=s), reps)
     b.run(1, stream=s)
     graph_ms = _time_on(s, lambda: b.run(2, stream=s), reps)
+    sep = spg.Batch(plans, io, spg.tuning(batch_form=2))
+    sep.run(1, stream=s)
+    sep_graph_ms = _time_on(s, lambda: sep.run(2, stream=s), reps)
+    sep.check()
+    sep.close()
     b_amg = spg.Batch(plans[:8], io[:8])
     eager_amg_ms = _time_on(s, lambda: b_amg.run(0, stream=s), reps)
     b_amg.run(1, stream=s)
@@ -235,7 +243,7 @@ def bench_batched(spg, reps=20):
     streams, launches = b.info()
     # the persistent form (one launch per run) on the AMG chain, and on every
     # product without dense columns against the stream DAG of the same table
-    persistent_tun = spg.tuning(batch_persistent=1)
+    persistent_tun = spg.tuning(batch_form=1)
     p_amg = spg.Batch(plans[:8], io[:8], persistent_tun)
     p_amg_ms = _time_on(s, lambda: p_amg.run(0, stream=s), reps)
     p_amg.run(1, stream=s)
@@ -251,6 +259,32 @@ def bench_batched(spg, reps=20):
     d_all.run(1, stream=s)
     d_all_graph_ms = _time_on(s, lambda: d_all.run(2, stream=s), reps)
     d_all.check()
+    # many small independent products: one launch per bin and kernel for all
+    # of them (the default form) against a launch per product and bin
+    rng = np.random.default_rng(6)
+    small_plans, small_io = [], []
+    for t in range(1024):
+        n_t = int(round(math.exp(rng.uniform(math.log(100), math.log(1000)))))
+        d_t = int(round(math.exp(rng.uniform(math.log(2), math.log(8)))))
+        sd = int(rng.integers(0, 2 ** 31 - 1))
+        p = spg.Plan(spg.DeviceCsc.from_host(synth.erdos_renyi(n_t, n_t, d_t, sd)),
+                     spg.DeviceCsc.from_host(synth.erdos_renyi(n_t, n_t, d_t, sd + 1)), None, 64)
+        C = p.run()
+        p.set_stream(s)
+        small_plans.append(p)
+        small_io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+    torch.cuda.synchronize()
+    small_flops = sum(p.stats()["flops"] for p in small_plans)
+    small = {}
+    for form, key in ((0, "grouped"), (2, "separate")):
+        bs = spg.Batch(small_plans, small_io, spg.tuning(batch_form=form))
+        bs.run(1, stream=s)
+        small[key + "_graph_replay_ms"] = round(_time_on(s, lambda: bs.run(2, stream=s), reps), 4)
+        small[key + "_launches"] = bs.info()[1]
+        bs.check()
+        bs.close()
+    for p in small_plans:
+        p.close()
     out = {
         "workload": "amg7pt64_4levels_plus_64er_f64",
         "products": len(plans), "launches": launches, "side_streams": streams,
@@ -258,6 +292,7 @@ def bench_batched(spg, reps=20):
         "plain_ms": round(plain_ms, 4), "dag_eager_ms": round(eager_ms, 4),
         "graph_replay_ms": round(graph_ms, 4),
         "speedup_vs_plain": round(plain_ms / graph_ms, 3),
+        "separate_graph_replay_ms": round(sep_graph_ms, 4),
         "graph_GFLOPs": round(2 * flops / (graph_ms * 1e-3) / 1e9, 2),
         "amg_only": {"products": 8, "flops": int(amg_flops), "plain_ms": round(plain_amg_ms, 4),
                      "dag_eager_ms": round(eager_amg_ms, 4),
@@ -267,6 +302,10 @@ def bench_batched(spg, reps=20):
                      "persistent_ms": round(p_amg_ms, 4),
                      "persistent_graph_replay_ms": round(p_amg_graph_ms, 4),
                      "persistent_speedup_vs_plain": round(plain_amg_ms / p_amg_ms, 3)},
+        "small_products": {"workload": "1024 ER products, n 100-1000, 2-8 per column (seed 6)",
+                           "flops": int(small_flops), **small,
+                           "grouped_speedup": round(small["separate_graph_replay_ms"] /
+                                                    small["grouped_graph_replay_ms"], 3)},
         "no_dense_table": {"products": len(keep), "persistent_ms": round(p_all_ms, 4),
                            "dag_graph_replay_ms": round(d_all_graph_ms, 4)},
     }

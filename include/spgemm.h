@@ -80,10 +80,15 @@ typedef struct {
                                    sort, 2 = LDS bitmap and rank */
     int32_t batch_streams;      /* batched: side streams independent products spread over
                                    (0 = 4, at most 8) */
-    int32_t batch_persistent;   /* batched: 0 = the stream DAG of per-bin kernels; 1 = one
-                                   persistent launch per run (products with tiny and hash
-                                   columns only: SPGEMM_EUNSUPPORTED when a product has
-                                   dense columns or tiny_max_flop > 256) */
+    int32_t batch_form;         /* batched: 0 = the stream DAG, where at each dependency
+                                   depth the products of at most 4096 columns without dense
+                                   columns share one launch per numeric bin and kernel (the
+                                   others, and value gathers, run their own kernels on side
+                                   streams); 1 = one persistent launch per run (products
+                                   with tiny and hash columns only: SPGEMM_EUNSUPPORTED when
+                                   a product has dense columns or tiny_max_flop > 256); 2 =
+                                   the stream DAG with every product launching its own
+                                   kernels */
     int32_t dense_first_flop;   /* dense output columns with at least this many products are
                                    handed out first (numeric bin 7), so the longest ones do
                                    not finish last; 0 = no such bin */
@@ -324,8 +329,8 @@ typedef struct spgemm_batch_s *spgemm_batch_t;
  *            join back, so every product has finished when `stream` reaches
  *            the end of the call.
  * The library keeps one batch per distinct (plans, io) table (built on first
- * use with the batch fields of plans[0]'s tuning: batch_streams, and
- * batch_persistent = 1 for one persistent launch per run; that call
+ * use with the batch fields of plans[0]'s tuning: batch_streams and
+ * batch_form (1: one persistent launch per run); that call
  * synchronises the plans' streams once) until one of its plans is
  * destroyed.  Runs of one table
  * must not overlap (they share the plans' A~ and scratch); work on the
@@ -342,7 +347,7 @@ int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch
  * table exactly as spgemm_batched does and synchronises the plans' streams
  * once; spgemm_batch_run takes spgemm_batched's mode and stream; the io
  * table is copied and the plans and buffers must outlive the batch.
- * With tuning.batch_persistent = 1 one run is ONE persistent launch: its
+ * With tuning.batch_form = 1 one run is ONE persistent launch: its
  * workgroups take the products' work items (value-gather tiles of A~,
  * numeric column groups) by an atomic ticket in dependency order and wait,
  * bounded in time, for the completion flags of the items they read; the
@@ -350,7 +355,7 @@ int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch
  * launch puts back to 0, so runs and graph replays of one batch must not
  * overlap.  spgemm_batch_check then also reports (SPGEMM_EHIP) a run whose
  * dependency wait ran out of time (its outputs are not valid).
- * Errors of create: EINVAL, ESTATE, EUNSUPPORTED (batch_persistent = 1 and a
+ * Errors of create: EINVAL, ESTATE, EUNSUPPORTED (batch_form = 1 and a
  * product with dense columns or tiny_max_flop > 256), EHIP.
  */
 int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_batch_io *io,

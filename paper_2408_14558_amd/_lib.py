@@ -43,7 +43,7 @@ class Tuning(ctypes.Structure):
                 ("hash_max_nnz", ctypes.c_int32), ("dense_window", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("own_partition", ctypes.c_int32),
                 ("own_partition_whole", ctypes.c_int32), ("medium_kernel", ctypes.c_int32),
-                ("batch_streams", ctypes.c_int32), ("batch_persistent", ctypes.c_int32),
+                ("batch_streams", ctypes.c_int32), ("batch_form", ctypes.c_int32),
                 ("dense_first_flop", ctypes.c_int32),
                 ("reserved", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64)]

@@ -504,7 +504,7 @@ int spgemm_default_tuning(spgemm_tuning *t) {
     t->dense_window = 0;
     t->medium_kernel = 0;
     t->batch_streams = 0;
-    t->batch_persistent = 0;
+    t->batch_form = 0;
     t->dense_first_flop = 1 << 18;
     t->reserved = 0;
     t->validate = 0;

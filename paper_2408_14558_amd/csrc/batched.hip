@@ -2,22 +2,25 @@
 // sizes, optionally chained like the two products of every AMG Galerkin
 // level) issued as one dependency DAG of the per-bin kernels, optionally
 // captured once into a hipGraph and replayed; or, with
-// tuning.batch_persistent = 1, as one persistent launch (persistent.hip).
+// tuning.batch_form = 1, as one persistent launch (persistent.hip).
 //
 // Products are ordered by dependency depth (a product's depth is one more
 // than the deepest product it reads).  Products of one depth are
-// independent, so they are spread round-robin over side streams forked from
-// the caller's stream and joined back before the next depth starts: small
-// products of one level overlap on the device, and a level never starts
-// before the products it reads have finished.  Each product runs exactly
-// the kernels its plain spgemm_numeric call would run (value gather of A~
+// independent.  With batch_form = 0, the depth's products without dense
+// columns (at least two of them) share one launch per numeric bin and
+// kernel (grouped.hip), after their value gathers; the depth's other
+// products are spread round-robin over side streams forked from the
+// caller's stream and joined back before the next depth starts, each running
+// exactly the kernels of its plain spgemm_numeric call (value gather of A~
 // when new A values are given, then one launch per non-empty numeric bin).
+// batch_form = 2 runs every product that way.  A depth never starts before
+// the products it reads have finished.
 #include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
 
-#include "internal.hpp"
+#include "grouped.hpp"
 
 using namespace spg;
 
@@ -37,16 +40,21 @@ struct spgemm_batch_s {
     std::vector<hipStream_t> side;         // default priority, non-blocking
     std::vector<hipEvent_t> fork, join;    // one fork event, one join event per side stream
     int64_t launches = 0;                  // kernels one run enqueues
+    std::vector<GroupedDepth> groups;      // per depth: its grouped products (np = 0: none)
     bool persistent = false;               // one persistent launch per run
     PersistentBatch pb;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
+// Whether product t gathers new A values into A~ before its numeric phase.
+static bool gathers_values(const Plan &p, const spgemm_batch_io &io) {
+    return io.A_vals && p.k > 0 && p.nnzA > 0 && p.nnzAt_pub != p.nnzA;
+}
+
 // Kernels product t enqueues per run (for spgemm_batch_info).
 static int64_t product_launches(const Plan &p, const spgemm_batch_io &io) {
-    int64_t n = 0;
-    if (io.A_vals && p.k > 0 && p.nnzA > 0 && p.nnzAt_pub != p.nnzA) ++n;  // a value gather
+    int64_t n = gathers_values(p, io) ? 1 : 0;
     if (p.n == 0 || p.nnzC == 0) return n;
     for (int bin = kBinTiny; bin < kBinDense; ++bin) n += p.num_count[bin] > 0;
     n += p.num_count[kBinDense] + p.num_count[kBinDenseFirst] > 0;  // one launch serves both
@@ -68,20 +76,51 @@ static int run_product(spgemm_batch_s &b, int t, hipStream_t s) {
     return rc;
 }
 
+// Enqueues the value gathers of a depth's grouped products on s.
+static int grouped_gathers(spgemm_batch_s &b, const GroupedDepth &g, hipStream_t s) {
+    for (int t : g.members) {
+        Plan &p = *b.plans[t];
+        if (!gathers_values(p, b.io[t])) continue;
+        const hipStream_t keep = p.stream;
+        p.stream = s;
+        const int rc = launch_gather_values(p, b.io[t].A_vals);
+        p.stream = keep;
+        if (rc) return rc;
+    }
+    return SPGEMM_OK;
+}
+
 // Enqueues the whole DAG on s (eagerly, or into a capture that s is in).
+// At a depth, the grouped products' value gathers go first on s; then the
+// other products and the grouped launches share s and the side streams.
 static int enqueue_dag(spgemm_batch_s &b, hipStream_t s) {
     if (b.persistent) return persistent_launch(b.pb, s);
-    for (const std::vector<int> &lvl : b.levels) {
-        const int width = std::min<int>((int)b.side.size(), (int)lvl.size());
-        if (width <= 1) {
-            for (int t : lvl)
+    for (size_t d = 0; d < b.levels.size(); ++d) {
+        const std::vector<int> &lvl = b.levels[d];
+        const GroupedDepth &g = b.groups[d];
+        std::vector<int> rest;  // products that run their own kernels
+        for (int t : lvl)
+            if (std::find(g.members.begin(), g.members.end(), t) == g.members.end())
+                rest.push_back(t);
+        if (int rc = grouped_gathers(b, g, s)) return rc;
+        const size_t jobs = rest.size() + g.launches.size();
+        const int width = std::min<int>((int)b.side.size(), (int)jobs - 1);
+        if (width <= 0) {
+            if (int rc = grouped_launch(g, {s})) return rc;
+            for (int t : rest)
                 if (int rc = run_product(b, t, s)) return rc;
             continue;
         }
         SPG_HIP(hipEventRecord(b.fork[0], s));
         for (int i = 0; i < width; ++i) SPG_HIP(hipStreamWaitEvent(b.side[i], b.fork[0], 0));
-        for (size_t u = 0; u < lvl.size(); ++u)
-            if (int rc = run_product(b, lvl[u], b.side[u % width])) return rc;
+        // s and the side streams in turn: the grouped launches first, then
+        // the other products
+        std::vector<hipStream_t> all(1, s);
+        all.insert(all.end(), b.side.begin(), b.side.begin() + width);
+        if (int rc = grouped_launch(g, all)) return rc;
+        for (size_t u = 0; u < rest.size(); ++u)
+            if (int rc = run_product(b, rest[u], all[(g.launches.size() + u) % all.size()]))
+                return rc;
         for (int i = 0; i < width; ++i) {
             SPG_HIP(hipEventRecord(b.join[i], b.side[i]));
             SPG_HIP(hipStreamWaitEvent(s, b.join[i], 0));
@@ -96,6 +135,7 @@ static void release(spgemm_batch_s *b) {
     for (hipEvent_t e : b->fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
     for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    for (GroupedDepth &g : b->groups) grouped_free(g);
     persistent_free(b->pb);
     delete b;
 }
@@ -151,8 +191,8 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
     spgemm_tuning tun;
     spgemm_default_tuning(&tun);
     if (tuning) tun = *tuning;
-    if (tun.batch_persistent != 0 && tun.batch_persistent != 1)
-        return fail(SPGEMM_EINVAL, "batch_persistent must be 0 or 1");
+    if (tun.batch_form < 0 || tun.batch_form > 2)
+        return fail(SPGEMM_EINVAL, "batch_form must be 0, 1 or 2");
     if (tun.batch_streams < 0 || tun.batch_streams > kMaxBatchStreams)
         return fail(SPGEMM_EINVAL, "batch_streams must be in 0..8");
     const spgemm_dtype dt = plans[0] ? plans[0]->dtype : SPGEMM_F64;
@@ -196,7 +236,7 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         b->launches += product_launches(*plans[t], io[t]);
     }
     hipError_t e = hipGetDevice(&b->device);
-    if (e == hipSuccess && tun.batch_persistent) {
+    if (e == hipSuccess && tun.batch_form == 1) {
         std::vector<Plan *> pv(plans, plans + count);
         std::vector<spgemm_batch_io> iov(io, io + count);
         // the products' symbolic phases (bin lists, counts) ran on the plans' streams
@@ -212,10 +252,36 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
             return SPGEMM_OK;
         }
     }
+    // grouped launches: at each depth, the products without dense columns,
+    // when there are at least two
+    b->groups.resize(b->levels.size());
+    if (e == hipSuccess && tun.batch_form == 0) {
+        std::vector<Plan *> pv(plans, plans + count);
+        std::vector<spgemm_batch_io> iov(io, io + count);
+        for (size_t d = 0; d < b->levels.size(); ++d) {
+            std::vector<int> members;
+            for (int t : b->levels[d]) {
+                const Plan &p = *plans[t];
+                if (p.n > 0 && p.nnzC > 0 && groupable(p)) members.push_back(t);
+            }
+            if (members.size() < 2) continue;
+            if (int rc = grouped_build(pv, iov, members, b->groups[d])) {
+                release(b);
+                return rc;
+            }
+            for (int t : members) b->launches -= product_launches(*plans[t], io[t]);
+            for (int t : members) b->launches += gathers_values(*plans[t], io[t]) ? 1 : 0;
+            b->launches += (int64_t)b->groups[d].launches.size();
+        }
+    }
+    // side streams: one fewer than the most jobs of a depth (products that
+    // run their own kernels, and grouped launches), s taking one of them
     size_t widest = 0;
-    for (const auto &l : b->levels) widest = std::max(widest, l.size());
+    for (size_t d = 0; d < b->levels.size(); ++d)
+        widest = std::max(widest, b->levels[d].size() - b->groups[d].members.size() +
+                                      b->groups[d].launches.size());
     const int nside = (int)std::min<size_t>(
-        widest > 1 ? widest : 0, tun.batch_streams ? tun.batch_streams : kDefaultBatchStreams);
+        widest > 1 ? widest - 1 : 0, tun.batch_streams ? tun.batch_streams : kDefaultBatchStreams);
     for (int i = 0; i < nside && e == hipSuccess; ++i) {
         hipStream_t st = nullptr;
         hipEvent_t ev = nullptr;
@@ -303,7 +369,7 @@ int spgemm_batched(int32_t count, const spgemm_plan_t *plans, const spgemm_batch
             spgemm_default_tuning(&tun);
             if (plans[0]) {
                 tun.batch_streams = plans[0]->tun.batch_streams;
-                tun.batch_persistent = plans[0]->tun.batch_persistent;
+                tun.batch_form = plans[0]->tun.batch_form;
             }
             if (int rc = spgemm_batch_create(count, plans, io, &tun, &b)) return rc;
             g_cache.push_back(CachedBatch{std::vector<spgemm_plan_t>(plans, plans + count),

@@ -167,14 +167,6 @@ __global__ __launch_bounds__(G) void k_num_bitmap(const int32_t *__restrict__ li
     num_bitmap_column<G, V>(a, list[blockIdx.x], bits, wpre, vals, vcap, S);
 }
 
-// Bitmap instead of hash for a medium bin when the bitmap is not much
-// larger than the bin's table and fits next to the values.
-static bool use_bitmap(int64_t m, int table, size_t vsize, size_t *lds) {
-    const size_t nw = (size_t)((m + 31) / 32);
-    *lds = ((nw * 6 + 15) & ~(size_t)15) + (size_t)(table / 2) * vsize;
-    return nw <= (size_t)8 * table && *lds <= 96 * 1024;
-}
-
 // Dynamic LDS of the dense kernel and the number of values one rank window
 // holds: whatever the device's per-workgroup LDS leaves after the bitmap,
 // the word ranks and the kernel's static part.
@@ -196,9 +188,7 @@ static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     const int cnt = p.num_count[bin];
     if (cnt <= 0) return SPGEMM_OK;
     size_t lds;
-    const bool fits = use_bitmap(p.m, T, sizeof(Acc), &lds);
-    const int mk = p.tun.medium_kernel;
-    if ((mk == 0 && fits) || (mk == 2 && lds <= 96 * 1024)) {
+    if (medium_uses_bitmap(p.m, T, p.tun.medium_kernel, sizeof(Acc), &lds)) {
         constexpr int GB = T <= 512 ? 128 : 256;
         hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(cnt), dim3(GB), lds, p.stream,
                            p.num_list + (int64_t)bin * p.n, cnt, a, T / 2);

@@ -434,6 +434,20 @@ struct NumBitmapStatic {
     int red[G / kWave + 2];
 };
 
+// Which kernel takes a medium bin of table size `table`: the LDS bitmap over
+// all m rows (true) instead of the LDS hash, when the bitmap is not much
+// larger than the table and fits next to the values (medium_kernel 0), or
+// whenever it fits in 96 KB (medium_kernel 2; 1: always the hash).  *lds:
+// the bitmap kernel's dynamic LDS bytes.
+inline bool medium_uses_bitmap(int64_t m, int table, int medium_kernel, size_t vsize,
+                               size_t *lds) {
+    const size_t nw = (size_t)((m + 31) / 32);
+    *lds = ((nw * 6 + 15) & ~(size_t)15) + (size_t)(table / 2) * vsize;
+    const bool small = *lds <= 96 * 1024;
+    return (medium_kernel == 0 && small && nw <= (size_t)8 * table) ||
+           (medium_kernel == 2 && small);
+}
+
 template <int G, typename V>
 __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j, uint32_t *bits,
                                                   uint16_t *wpre, Acc *vals, int vcap,

@@ -162,13 +162,15 @@ def tune_batch(plans: Sequence[Plan], io: Sequence[dict],
                streams: Iterable[int] = (1, 2, 4, 8), persistent: bool = True,
                reps: int = 10) -> Tuple[dict, dict]:
     """The batched form with the fastest graph replay of a batch: the stream
-    DAG on each side-stream count, and (when the products allow it) one
+    DAG with grouped launches, and with every product launched on its own,
+    on each side-stream count, and (when the products allow it) one
     persistent launch.  Returns (the batch fields of spgemm_tuning, report);
     spgemm_batched takes them from the first plan's tuning."""
     s = torch.cuda.Stream()
-    cands = [({"batch_streams": ns, "batch_persistent": 0}, f"streams={ns}") for ns in streams]
+    cands = [({"batch_streams": ns, "batch_form": f}, f"{'grouped' if f == 0 else 'separate'},"
+              f" streams={ns}") for f in (0, 2) for ns in streams]
     if persistent:
-        cands.append(({"batch_streams": 0, "batch_persistent": 1}, "persistent"))
+        cands.append(({"batch_streams": 0, "batch_form": 1}, "persistent"))
     times = {}
     best = None
     for fields, name in cands:

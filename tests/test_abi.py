@@ -46,7 +46,7 @@ def test_default_tuning_and_version(lib):
     t = _lib.Tuning()
     assert lib.spgemm_default_tuning(ctypes.byref(t)) == 0
     assert t.tiny_max_flop == 256 and t.hash_max_flop == 4096 and t.hash_max_nnz == 2048
-    assert t.batch_streams == 0 and t.batch_persistent == 0 and t.reserved == 0
+    assert t.batch_streams == 0 and t.batch_form == 0 and t.reserved == 0
     assert ctypes.sizeof(_lib.Tuning) == 56
     assert lib.spgemm_default_tuning(None) == _lib.EINVAL
     assert b"gfx950" in lib.spgemm_version()

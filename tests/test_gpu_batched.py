@@ -1,8 +1,11 @@
 """GPU tests of the batched form: the numeric phase of many planned products
 (the 64^3 AMG Galerkin hierarchy, four levels, chained; plus 64 independent
-ER products of uneven sizes) as one dependency DAG over side streams,
-directly and as a captured hipGraph replayed several times; and the same
-table as one persistent launch (tuning.batch_persistent = 1)."""
+ER products of uneven sizes) as one dependency DAG, with the products of a
+depth that have tiny and hash columns only sharing one launch per bin
+(tuning.batch_form = 0) or every product launching its own kernels on side
+streams (batch_form = 2), directly and as a captured hipGraph replayed
+several times; and the same table as one persistent launch
+(batch_form = 1)."""
 
 import numpy as np
 import pytest
@@ -73,7 +76,14 @@ def test_batched_direct_launch(workload):
     b = spg.Batch(plans, io)
     streams, launches = b.info()
     print("batch side streams", streams, "launches", launches, flush=True)
-    assert streams == 4 and launches >= len(plans)
+    # at depth 0 the ER products of at most 4096 columns share one launch
+    # per non-empty bin and kernel; the larger ones and the chain run their
+    # own kernels
+    sep = spg.Batch(plans, io, spg.tuning(batch_form=2))
+    streams2, launches2 = sep.info()
+    sep.close()
+    assert streams == 4 and launches < launches2
+    assert streams2 == 4 and launches2 >= len(plans)
     for C in outs:
         C.vals.fill_(-7.0)
         C.rowidx.fill_(-1)
@@ -111,7 +121,8 @@ def test_batched_graph_replays(workload):
 
 def test_batched_stream_counts_give_the_same_results(workload):
     A0, plans, io, outs, er = workload
-    for tun in (spg.tuning(batch_streams=1), spg.tuning(batch_streams=8)):
+    for tun in (spg.tuning(batch_streams=1), spg.tuning(batch_streams=8),
+                spg.tuning(batch_form=2), spg.tuning(batch_form=2, batch_streams=1)):
         b = spg.Batch(plans, io, tun)
         for C in outs:
             C.vals.fill_(3.0)
@@ -136,7 +147,7 @@ def test_batched_errors(workload):
         spg.Batch(plans[:2], io[:2], spg.tuning(batch_streams=9))
     assert e.value.code == -1
     with pytest.raises(spg.SpgemmError) as e:
-        spg.Batch(plans[:2], io[:2], spg.tuning(batch_persistent=2))
+        spg.Batch(plans[:2], io[:2], spg.tuning(batch_form=3))
     assert e.value.code == -1
     b = spg.Batch(plans[:2], io[:2])
     lib = spg.load()
@@ -174,7 +185,7 @@ def test_graph_replays_of_dense_queue_kernels():
         p.set_stream(s)
     # the persistent form takes tiny and hash columns only
     with pytest.raises(spg.SpgemmError) as e:
-        spg.Batch(plans, io, spg.tuning(batch_persistent=1))
+        spg.Batch(plans, io, spg.tuning(batch_form=1))
     assert e.value.code == -4
     b = spg.Batch(plans, io)
     try:
@@ -189,6 +200,119 @@ def test_graph_replays_of_dense_queue_kernels():
                 assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
                 assert_values(d["C_vals"].cpu().numpy(), ref.vals, ref.absvals, True)
         b.check()
+    finally:
+        b.close()
+        for p in plans:
+            p.close()
+
+
+def _device(M, dt):
+    return spg.DeviceCsc(M.nrows, M.ncols, torch.as_tensor(M.colptr).cuda(),
+                         torch.as_tensor(M.rowidx).cuda(),
+                         torch.as_tensor(np.asarray(M.vals)).to(dt).cuda())
+
+
+def test_grouped_depths_with_dense_products_and_dependencies():
+    """Depth 0 holds five small ER products without dense columns (one
+    grouped launch per bin and kernel) beside two R-MAT squares whose columns
+    are all dense (their own kernels on side streams); depth 1 holds two grouped
+    products that read depth-0 outputs: A1 * C_0 (B values are product 0's C,
+    read in place) and C_1 * S (A values are product 1's C, gathered into
+    A~ first, since S needs few of C_1's columns).  Unit values make every
+    result an integer, so the batch is compared exactly with the oracle,
+    directly, captured and replayed, in FP64 and FP32."""
+    tun_dense = spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0, dense_window=64)
+    for dt in (torch.float64, torch.float32):
+        # five products small enough to be grouped (at most 4096 columns),
+        # from tiny to medium columns (d = 32: about 1000 products a column)
+        host = []
+        for t, (n, d) in enumerate(((500, 4), (1200, 8), (2500, 12), (3000, 20), (4000, 32))):
+            host.append((synth.unit_values(synth.erdos_renyi(n, n, d, seed=50 + t)),
+                         synth.unit_values(synth.erdos_renyi(n, n, d, seed=60 + t)), None))
+        for sd in (41, 42):
+            M = synth.unit_values(synth.rmat(10, 16, 0.57, 0.19, 0.19, 0.05, seed=sd))
+            host.append((M, M, tun_dense))
+        plans, io, refs = [], [], []
+        for A, B, tun in host:
+            p = spg.Plan(_device(A, dt), _device(B, dt), None, 64, tuning=tun)
+            C = p.run()
+            plans.append(p)
+            io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+            refs.append(oracle.spgemm(A, B))
+        C0, C1 = refs[0], refs[1]
+        A1 = synth.unit_values(synth.erdos_renyi(C0.nrows, C0.nrows, 2, seed=43))
+        p = spg.Plan(_device(A1, dt), _device(C0, dt), None, 64)
+        C = p.run()
+        plans.append(p)
+        io.append({"B_vals": io[0]["C_vals"], "C_rowidx": C.rowidx, "C_vals": C.vals,
+                   "dep_B": 0})
+        refs.append(oracle.spgemm(A1, C0))
+        S = synth.unit_values(synth.erdos_renyi(C1.ncols, 4, 1, seed=44))
+        p = spg.Plan(_device(C1, dt), _device(S, dt), None, 64)
+        C = p.run()
+        assert p.stats()["nnz_At"] < C1.colptr[-1]  # part of C_1: a value gather
+        plans.append(p)
+        io.append({"A_vals": io[1]["C_vals"], "C_rowidx": C.rowidx, "C_vals": C.vals,
+                   "dep_A": 1})
+        refs.append(oracle.spgemm(C1, S))
+        dense = [not _no_dense(q) for q in plans]
+        assert dense == [False] * 5 + [True, True] + [False, False]
+        s = torch.cuda.Stream()
+        b = spg.Batch(plans, io)
+        try:
+            streams, launches = b.info()
+            assert streams >= 2  # the dense products beside depth 0's grouped launches
+            sep = spg.Batch(plans, io, spg.tuning(batch_form=2))
+            assert launches < sep.info()[1]
+            sep.close()
+            for mode in (0, 1, 2, 2):
+                with torch.cuda.stream(s):
+                    for d in io:
+                        d["C_vals"].fill_(-3.0)
+                        d["C_rowidx"].fill_(-1)
+                    b.run(mode, stream=s)
+                s.synchronize()
+                b.check()
+                for d, ref in zip(io, refs):
+                    assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
+                    assert np.array_equal(d["C_vals"].cpu().double().numpy(), ref.vals)
+        finally:
+            b.close()
+            for q in plans:
+                q.close()
+
+
+def test_grouped_many_small_products():
+    """Two hundred independent small ER products (100-800 columns, 2-8 per
+    column): the default form puts all of them in one launch per bin and
+    kernel; direct run, capture and replays against the oracle."""
+    rng = np.random.default_rng(7)
+    plans, io, refs = [], [], []
+    for t in range(200):
+        n = int(rng.integers(100, 801))
+        d = int(rng.integers(2, 9))
+        A = synth.erdos_renyi(n, n, d, seed=1000 + 2 * t)
+        B = synth.erdos_renyi(n, n, d, seed=1001 + 2 * t)
+        p = spg.Plan(spg.DeviceCsc.from_host(A), spg.DeviceCsc.from_host(B), None, 64)
+        C = p.run()
+        plans.append(p)
+        io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+        refs.append(oracle.spgemm(A, B))
+    s = torch.cuda.Stream()
+    b = spg.Batch(plans, io)
+    try:
+        streams, launches = b.info()
+        assert launches <= 5  # tiny, and one per medium bin present
+        for mode in (0, 1, 2, 2):
+            with torch.cuda.stream(s):
+                for d in io:
+                    d["C_vals"].fill_(-3.0)
+                b.run(mode, stream=s)
+            s.synchronize()
+            b.check()
+            for d, ref in zip(io, refs):
+                assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
+                assert_values(d["C_vals"].cpu().numpy(), ref.vals, ref.absvals, True)
     finally:
         b.close()
         for p in plans:
@@ -243,7 +367,7 @@ def _no_dense(p):
 
 
 def test_persistent_batch_matches_plain(workload):
-    """tuning.batch_persistent = 1: the AMG chain and the ER products without
+    """tuning.batch_form = 1: the AMG chain and the ER products without
     dense columns as ONE persistent launch (items by ticket in dependency
     order, per-item completion flags, bounded waits).  Direct runs, a
     capture and replays with new fine-level values give the plain results,
@@ -253,7 +377,7 @@ def test_persistent_batch_matches_plain(workload):
     assert keep[:8] == list(range(8))
     print("persistent batch of", len(keep), "products", flush=True)
     b = spg.Batch([plans[t] for t in keep], [io[t] for t in keep],
-                  spg.tuning(batch_persistent=1))
+                  spg.tuning(batch_form=1))
     streams, launches = b.info()
     assert streams == 0 and launches == 1
 
@@ -324,7 +448,7 @@ def test_persistent_batch_fp32_with_a_dependency():
     io.append({"B_vals": io[0]["C_vals"], "C_rowidx": C3.rowidx, "C_vals": C3.vals, "dep_B": 0})
     refs.append(oracle.spgemm(synth.as_fp32(A1), C0f))
     assert all(_no_dense(p) for p in plans)
-    b = spg.Batch(plans, io, spg.tuning(batch_persistent=1))
+    b = spg.Batch(plans, io, spg.tuning(batch_form=1))
     try:
         for rep in range(2):
             for d in io:

@@ -42,10 +42,11 @@ def test_tune_batch_picks_a_stream_count():
         io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
     torch.cuda.synchronize()
     best, rep = spg.tune.tune_batch(plans, io, streams=(1, 4), reps=2)
-    assert set(rep["ms"]) == {"streams=1", "streams=4", "persistent"}
+    assert set(rep["ms"]) == {"grouped, streams=1", "grouped, streams=4",
+                              "separate, streams=1", "separate, streams=4", "persistent"}
     assert rep["best"] in rep["ms"] and rep["ms"][rep["best"]] == min(
         t for t in rep["ms"].values() if t is not None)
-    assert set(best) == {"batch_streams", "batch_persistent"}
+    assert set(best) == {"batch_streams", "batch_form"}
     # spgemm_batched takes the batch fields from the first plan's tuning
     t = spg.tuning(**best)
     p0 = spg.Plan(plans[0].A, plans[0].Bi, None, 64, tuning=t)
