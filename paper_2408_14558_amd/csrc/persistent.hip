@@ -171,16 +171,21 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(const PItem *__r
                 gather_tile<V, false>(g, P.Acolptr, nullptr, P.Avals, P.map, P.At_colptr, P.k,
                                       nullptr, P.At_vals, L.g);
         } else if (it.kind == kPTiny) {
+            // the product's arguments copied once per item, so the column
+            // routines keep them in scalar registers instead of reading them
+            // from the table at every use
+            const NumArgs<V> a = P.a;
             const int wv = tid / kWave;
             for (int c = it.first + wv; c < end; c += kPThreads / kWave) {
                 const int32_t j = P.list[kBinTiny][c];
                 if (P.packed)
-                    num_wave_dispatch<V, 4, true>(P.a, j, L.tiny.rows[wv], L.tiny.vals[wv]);
+                    num_wave_dispatch<V, 4, true>(a, j, L.tiny.rows[wv], L.tiny.vals[wv]);
                 else
-                    num_wave_dispatch<V, 4, false>(P.a, j, L.tiny.rows[wv], L.tiny.vals[wv]);
+                    num_wave_dispatch<V, 4, false>(a, j, L.tiny.rows[wv], L.tiny.vals[wv]);
                 wave_sync();  // the wave's LDS rows are reused by its next column
             }
         } else {
+            const NumArgs<V> a = P.a;  // copied once per item (see above)
             // num_hash_column ends with a barrier of its group, so a group's
             // next column may reuse its table
             const int h = it.kind - kPHash0;
@@ -188,17 +193,17 @@ __global__ __launch_bounds__(kPThreads) void k_batch_persistent(const PItem *__r
             if (h == 0) {
                 const int grp = tid / 32;
                 for (int c = it.first + grp; c < end; c += kPThreads / 32)
-                    num_hash_column<kNumTable[0], 32, V>(P.a, list[c], L.h0[grp], tid % 32);
+                    num_hash_column<kNumTable[0], 32, V>(a, list[c], L.h0[grp], tid % 32);
             } else if (h == 1) {
                 const int grp = tid / kWave;
                 for (int c = it.first + grp; c < end; c += kPThreads / kWave)
-                    num_hash_column<kNumTable[1], 64, V>(P.a, list[c], L.h1[grp], tid % kWave);
+                    num_hash_column<kNumTable[1], 64, V>(a, list[c], L.h1[grp], tid % kWave);
             } else if (h == 2) {
                 for (int c = it.first; c < end; ++c)
-                    num_hash_column<kNumTable[2], kPThreads, V>(P.a, list[c], L.h2, tid);
+                    num_hash_column<kNumTable[2], kPThreads, V>(a, list[c], L.h2, tid);
             } else {
                 for (int c = it.first; c < end; ++c)
-                    num_hash_column<kNumTable[3], kPThreads, V>(P.a, list[c], L.h3, tid);
+                    num_hash_column<kNumTable[3], kPThreads, V>(a, list[c], L.h3, tid);
             }
         }
         // publish, where another item reads this one's output: every wave's
