@@ -364,8 +364,11 @@ __device__ __forceinline__ void flop_long_chunk(int64_t c, const FlopArgs &a) {
 // workgroups publishes the counters (else the early tiny symbolic launch
 // does).
 static_assert(kFlopThreads == kGatherThreads, "all tiles use the whole workgroup");
+// Compiled for eight waves per SIMD (eight workgroups per CU, as many as
+// their LDS allows), which caps the registers at 64 per lane.
+constexpr int kFlopWaves = 8;
 template <int S, typename V>
-__global__ __launch_bounds__(kFlopThreads) void k_flop_bin_gather(
+__global__ __launch_bounds__(kFlopThreads, kFlopWaves) void k_flop_bin_gather(
     FlopArgs a, int64_t ncols_tiles, int rounds, int64_t nchunks,
     PublishedCounts *__restrict__ hout,
     unsigned int *__restrict__ hready, int64_t k, const int64_t *__restrict__ Acolptr,
@@ -525,12 +528,17 @@ __global__ __launch_bounds__(G < 256 ? 256 : G) void k_sym_hash(
 #define SPG_SYM_DENSE_UNROLL 8
 #endif
 constexpr int kSymDenseUnroll = SPG_SYM_DENSE_UNROLL;
+// Waves per SIMD the kernel is compiled for: eight, i.e. two workgroups of
+// 1024 threads per CU (their LDS fits twice), which caps the registers at
+// 64 per lane; the walk is bound by the latency of its row-id loads, so
+// twice the resident waves hide more of it.
+constexpr int kSymDenseWaves = 8;
 struct SymDenseLds {
     TermStage<kDenseThreads, float> st;
     int red[kDenseThreads / kWave + 2];
 };
 
-__global__ __launch_bounds__(kDenseThreads) void k_sym_dense(
+__global__ __launch_bounds__(kDenseThreads, kSymDenseWaves) void k_sym_dense(
     const int32_t *__restrict__ list, int count, int64_t m, const int64_t *__restrict__ Bcolptr,
     TermRange tr, const int32_t *__restrict__ At_rowidx, int64_t *__restrict__ Ccount,
     uint32_t *__restrict__ keep_bits, int32_t *__restrict__ col_slot,
