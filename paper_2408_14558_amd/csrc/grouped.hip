@@ -139,6 +139,7 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
     for (int b = kBinH0; b <= kBinH3; ++b) {
         std::vector<int> hash, bitmap;
         size_t lds_max = 0;
+        int64_t m_max = 0;
         for (int i : with_columns(b)) {
             const Plan &p = *plans[g.members[i]];
             size_t lds = 0;
@@ -146,12 +147,14 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
                                    &lds)) {
                 bitmap.push_back(i);
                 lds_max = std::max(lds_max, lds);
+                m_max = std::max(m_max, p.m);
             } else {
                 hash.push_back(i);
             }
         }
         if (int rc = add(1, b, hash, 0)) return rc;
         if (int rc = add(2, b, bitmap, lds_max)) return rc;
+        if (!bitmap.empty()) g.launches.back().wide = m_max > 65536;
     }
     const size_t pbytes = sizeof(GProd<V>) * (size_t)np;
     const size_t off = (pbytes + 255) & ~(size_t)255;
@@ -190,12 +193,18 @@ static int hash_launch(const GroupedDepth &g, const GroupedLaunch &L, hipStream_
 
 template <int T, typename V>
 static int bitmap_launch(const GroupedDepth &g, const GroupedLaunch &L, hipStream_t s) {
-    constexpr int GB = T <= 512 ? 128 : 256;  // as the plain bitmap kernel
+    // as the plain bitmap kernel: 512 threads for bitmaps of more than
+    // 65536 rows
+    constexpr int GB = T <= 512 ? 128 : 256;
     const uint64_t *cols = (const uint64_t *)((const char *)g.table + L.offset);
-    hipLaunchKernelGGL((k_num_bitmap_grouped<GB, V>), dim3((unsigned)L.total), dim3(GB), L.lds, s,
-                       (const GProd<V> *)g.table, cols, (int)L.total, T / 2);
-    SPG_LAUNCHED("k_num_bitmap_grouped<" + std::to_string(GB) + "> (" + std::to_string(L.np) +
-                 " products, " + std::to_string(L.total) + " columns)");
+    if (L.wide)
+        hipLaunchKernelGGL((k_num_bitmap_grouped<512, V>), dim3((unsigned)L.total), dim3(512),
+                           L.lds, s, (const GProd<V> *)g.table, cols, (int)L.total, T / 2);
+    else
+        hipLaunchKernelGGL((k_num_bitmap_grouped<GB, V>), dim3((unsigned)L.total), dim3(GB),
+                           L.lds, s, (const GProd<V> *)g.table, cols, (int)L.total, T / 2);
+    SPG_LAUNCHED("k_num_bitmap_grouped (" + std::to_string(L.np) + " products, " +
+                 std::to_string(L.total) + " columns)");
     return SPGEMM_OK;
 }
 

@@ -20,6 +20,7 @@ struct GroupedLaunch {
     int np = 0;            // members with columns in this launch
     int64_t total = 0;     // columns
     size_t lds = 0;        // bitmap: dynamic LDS bytes (the largest member's)
+    bool wide = false;     // bitmap: a member has more than 65536 rows (512 threads)
     size_t offset = 0;     // byte offset of its column table in the table block
 };
 

@@ -183,13 +183,27 @@ size_t dense_lds_bytes(int64_t m, size_t vsize, int lds_max, int *VC_out) {
     return head + (size_t)VC * vsize;
 }
 
+constexpr int64_t kBitmapWideRows = 65536;
+constexpr int kBitmapWideThreads = 512;
+
 template <int T, int G, typename V>
 static int num_hash_launch(Plan &p, int bin, const NumArgs<V> &a) {
     const int cnt = p.num_count[bin];
     if (cnt <= 0) return SPGEMM_OK;
     size_t lds;
     if (medium_uses_bitmap(p.m, T, p.tun.medium_kernel, sizeof(Acc), &lds)) {
+        // a bitmap of more than 65536 rows takes so much LDS that two
+        // workgroups fill a CU: 512 threads each then keep 16 waves resident
+        // (R-MAT 18: numeric 15.95 -> 15.4 ms; 1024 threads leave one
+        // workgroup per CU and are slower)
         constexpr int GB = T <= 512 ? 128 : 256;
+        if (p.m > kBitmapWideRows) {
+            hipLaunchKernelGGL((k_num_bitmap<kBitmapWideThreads, V>), dim3(cnt),
+                               dim3(kBitmapWideThreads), lds, p.stream,
+                               p.num_list + (int64_t)bin * p.n, cnt, a, T / 2);
+            SPG_LAUNCHED("k_num_bitmap<" + std::to_string(kBitmapWideThreads) + ">");
+            return SPGEMM_OK;
+        }
         hipLaunchKernelGGL((k_num_bitmap<GB, V>), dim3(cnt), dim3(GB), lds, p.stream,
                            p.num_list + (int64_t)bin * p.n, cnt, a, T / 2);
         SPG_LAUNCHED("k_num_bitmap<" + std::to_string(GB) + ">");

@@ -319,6 +319,45 @@ def test_grouped_many_small_products():
             p.close()
 
 
+def test_grouped_medium_columns_of_tall_products():
+    """Grouped products whose medium columns go to the LDS bitmap over more
+    than 65536 rows (the wide bitmap launch) beside one with fewer rows, in
+    FP64 and FP32, against the oracle and against the separate form."""
+    shapes = ((100000, 40, 30, 71), (70000, 40, 24, 72), (30000, 40, 30, 73))
+    for dt in (torch.float64, torch.float32):
+        plans, io, refs = [], [], []
+        for m, da, db, sd in shapes:
+            A = synth.erdos_renyi(m, 2000, da, seed=sd)
+            B = synth.erdos_renyi(2000, 500, db, seed=sd + 100)
+            p = spg.Plan(spg.DeviceCsc.from_host(A, dtype=dt), spg.DeviceCsc.from_host(B, dtype=dt),
+                         None, 64)
+            C = p.run()
+            st = p.stats()
+            assert sum(st["num_bins"][2:6]) > 0 and st["num_bins"][6] + st["num_bins"][7] == 0
+            plans.append(p)
+            io.append({"C_rowidx": C.rowidx, "C_vals": C.vals})
+            refs.append(oracle.spgemm(synth.as_fp32(A) if dt == torch.float32 else A,
+                                      synth.as_fp32(B) if dt == torch.float32 else B))
+        b = spg.Batch(plans, io)
+        sep = spg.Batch(plans, io, spg.tuning(batch_form=2))
+        try:
+            assert b.info()[1] < sep.info()[1]
+            for bb in (b, sep):
+                for d in io:
+                    d["C_vals"].fill_(-3.0)
+                bb.run(0)
+                bb.check()
+                for d, ref in zip(io, refs):
+                    assert np.array_equal(d["C_rowidx"].cpu().numpy(), ref.rowidx)
+                    assert_values(d["C_vals"].cpu().numpy(), ref.vals, ref.absvals,
+                                  dt == torch.float64)
+        finally:
+            b.close()
+            sep.close()
+            for p in plans:
+                p.close()
+
+
 def test_spgemm_batched_by_table(workload):
     """spgemm_batched(count, plans, io, mode, stream): mode 0 runs the table,
     mode 1 captures and launches it, mode 2 replays that capture (with new
