@@ -236,21 +236,20 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         b->launches += product_launches(*plans[t], io[t]);
     }
     hipError_t e = hipGetDevice(&b->device);
+    // the products' symbolic phases (bin lists, counts) ran on the plans'
+    // streams: finished before any table is built from them
+    for (int t = 0; t < count && e == hipSuccess; ++t) e = hipStreamSynchronize(plans[t]->stream);
     if (e == hipSuccess && tun.batch_form == 1) {
         std::vector<Plan *> pv(plans, plans + count);
         std::vector<spgemm_batch_io> iov(io, io + count);
-        // the products' symbolic phases (bin lists, counts) ran on the plans' streams
-        for (int t = 0; t < count && e == hipSuccess; ++t) e = hipStreamSynchronize(plans[t]->stream);
-        if (e == hipSuccess) {
-            if (int rc = persistent_build(pv, iov, b->levels, b->pb)) {
-                release(b);
-                return rc;
-            }
-            b->persistent = true;
-            b->launches = b->pb.nitems > 0 ? 1 : 0;
-            *out = b;
-            return SPGEMM_OK;
+        if (int rc = persistent_build(pv, iov, b->levels, b->pb)) {
+            release(b);
+            return rc;
         }
+        b->persistent = true;
+        b->launches = b->pb.nitems > 0 ? 1 : 0;
+        *out = b;
+        return SPGEMM_OK;
     }
     // grouped launches: at each depth, the products without dense columns,
     // when there are at least two
@@ -295,8 +294,6 @@ int spgemm_batch_create(int32_t count, const spgemm_plan_t *plans, const spgemm_
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess) b->fork.push_back(ev);
     }
-    // the products' symbolic phases ran on the plans' streams
-    for (int t = 0; t < count && e == hipSuccess; ++t) e = hipStreamSynchronize(plans[t]->stream);
     if (e != hipSuccess) {
         release(b);
         return fail(SPGEMM_EHIP, std::string("batch set-up: ") + hipGetErrorString(e));

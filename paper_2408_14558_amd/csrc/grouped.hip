@@ -106,8 +106,15 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
     // the launches: tiny, then per medium bin the hash and the bitmap kernel
     // (a member's columns of a medium bin go to the kernel its plain phase
     // uses); each launch's column table lists its members' columns in order
+    // every member's numeric bin lists, one copy per member (kNumBins x n)
+    std::vector<std::vector<int32_t>> lists(np);
+    for (int i = 0; i < np; ++i) {
+        const Plan &p = *plans[g.members[i]];
+        lists[i].resize((size_t)kNumBins * (size_t)p.n);
+        SPG_HIP(hipMemcpy(lists[i].data(), p.num_list, sizeof(int32_t) * lists[i].size(),
+                          hipMemcpyDeviceToHost));
+    }
     std::vector<uint64_t> cols;
-    std::vector<int32_t> list;
     auto add = [&](int kind, int bin, const std::vector<int> &who, size_t lds) {
         GroupedLaunch L;
         L.kind = kind;
@@ -118,11 +125,9 @@ static int build_t(const std::vector<Plan *> &plans, const std::vector<spgemm_ba
         for (int i : who) {
             const Plan &p = *plans[g.members[i]];
             const int64_t c = p.num_count[bin];
-            list.resize((size_t)c);
-            SPG_HIP(hipMemcpy(list.data(), p.num_list + (int64_t)bin * p.n,
-                              sizeof(int32_t) * (size_t)c, hipMemcpyDeviceToHost));
+            const int32_t *list = lists[i].data() + (size_t)bin * (size_t)p.n;
             for (int64_t q = 0; q < c; ++q)
-                cols.push_back(((uint64_t)(uint32_t)i << 32) | (uint32_t)list[(size_t)q]);
+                cols.push_back(((uint64_t)(uint32_t)i << 32) | (uint32_t)list[q]);
             L.total += c;
         }
         if (L.total >= INT32_MAX) return fail(SPGEMM_EUNSUPPORTED, "too many grouped columns");
