@@ -166,7 +166,8 @@ constexpr uint64_t kValMask = ~kStMask;
 // A status word carries all a look-back needs (state and value), and no
 // tile reads data another tile wrote besides it: relaxed agent-scope stores
 // and loads suffice (no L2 write-back per publish, no invalidation per poll;
-// a release store here cost C2's two plan scans about 4 us).
+// a release store here cost the two plan scans of an ER 65536 partition
+// (16 per column, 4096 columns) about 4 us).
 __device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

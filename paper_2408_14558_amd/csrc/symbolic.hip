@@ -29,8 +29,9 @@ __device__ __forceinline__ int num_bin_of(long long f, long long nnz, const Thre
 // The calling lane's slot in bin b's workgroup-local list (LDS counters
 // s_cnt; b == kBinEmpty: none, 0).  The lanes of a wave that share a bin
 // take consecutive slots from one LDS atomic: lane by lane, thousands of
-// columns of one bin serialise on its counter (the one-workgroup scan of C2's
-// 4096 tiny columns spent most of its 9 us there).  Every lane of the wave
+// columns of one bin serialise on its counter (the one-workgroup scan of the
+// 4096 tiny columns of one ER 65536 partition (16 per column) spent most of
+// its 9 us there).  Every lane of the wave
 // calls.
 __device__ __forceinline__ int wave_bin_slot(int *s_cnt, int b) {
     int pos = 0;
