@@ -78,8 +78,9 @@ typedef struct {
                                    Alg. 2 to it as to the remote partitions; C_i is the same */
     int32_t medium_kernel;      /* medium numeric bins: 0 = choose by m, 1 = LDS hash and
                                    sort, 2 = LDS bitmap and rank */
-    int32_t batch_streams;      /* batched: side streams independent products spread over
-                                   (0 = 4, at most 8) */
+    int32_t batch_streams;      /* batched: side streams that, with the caller's stream, the
+                                   independent work of one depth (products, grouped
+                                   launches) is spread over (0 = 4, at most 8) */
     int32_t batch_form;         /* batched: 0 = the stream DAG, where at each dependency
                                    depth the products of at most 4096 columns without dense
                                    columns share one launch per numeric bin and kernel (the
