@@ -63,6 +63,92 @@ __global__ __launch_bounds__(kDenseThreads) void k_num_dense(
     queue_leave(queue);
 }
 
+// The order in which k_dense_rows takes the kept bitmaps: by descending
+// number of rows (eight buckets per power of two), so the waves of its
+// grid-stride loop get about equal shares (the columns of a power-law
+// product differ by orders of magnitude, and in list order the large ones
+// cluster).  One workgroup; order[i] is a position in the dense list.  Each
+// wave counts, and later places, its own items (thread t takes positions t,
+// t + 1024, ...) in a histogram of its own, so LDS atomics only meet inside
+// a wave; the positions' columns and row counts are loaded kOrderBatch at a
+// time, so their loads are in flight together.
+constexpr int kOrderBuckets = 256;
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBatch = 8;
+__global__ __launch_bounds__(kOrderThreads) void k_dense_order(int count,
+                                                               const int32_t *__restrict__ list,
+                                                               const int64_t *__restrict__ Ccolptr,
+                                                               int32_t *__restrict__ order) {
+    constexpr int NW = kOrderThreads / kWave;
+    __shared__ int s_h[NW][kOrderBuckets];
+    const int tid = threadIdx.x, wv = tid / kWave;
+    for (int i = tid; i < NW * kOrderBuckets; i += kOrderThreads) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    // buckets of this thread's positions w0 + u * kOrderThreads (-1 past count)
+    auto buckets = [&](int w0, int (&bk)[kOrderBatch]) {
+        int32_t j[kOrderBatch];
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) j[u] = list[min(w0 + u * kOrderThreads, count - 1)];
+        long long a[kOrderBatch], z[kOrderBatch];
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) {
+            a[u] = Ccolptr[j[u]];
+            z[u] = Ccolptr[j[u] + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u) {
+            const long long nz = z[u] - a[u];
+            int b = kOrderBuckets - 1;
+            if (nz > 1) {
+                const int lg = 63 - __clzll((unsigned long long)nz);
+                const int frac = (int)((lg >= 3 ? nz >> (lg - 3) : nz << (3 - lg)) & 7);
+                b = max(0, kOrderBuckets - 1 - (lg * 8 + frac));  // more rows: lower bucket
+            }
+            bk[u] = w0 + u * kOrderThreads < count ? b : -1;
+        }
+    };
+    constexpr int kStep = kOrderBatch * kOrderThreads;
+    for (int w0 = tid; w0 < count; w0 += kStep) {
+        int bk[kOrderBatch];
+        buckets(w0, bk);
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u)
+            if (bk[u] >= 0) atomicAdd(&s_h[wv][bk[u]], 1);
+    }
+    __syncthreads();
+    // bucket-major, wave-minor exclusive scan: thread b < 256 holds bucket b
+    __shared__ int s_tot[kOrderBuckets];
+    if (tid < kOrderBuckets) {
+        int run = 0;
+        for (int v = 0; v < NW; ++v) {
+            const int c = s_h[v][tid];
+            s_h[v][tid] = run;
+            run += c;
+        }
+        s_tot[tid] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            const int c = s_tot[b];
+            s_tot[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    if (tid < kOrderBuckets)
+        for (int v = 0; v < NW; ++v) s_h[v][tid] += s_tot[tid];
+    __syncthreads();
+    for (int w0 = tid; w0 < count; w0 += kStep) {
+        int bk[kOrderBatch];
+        buckets(w0, bk);
+#pragma unroll
+        for (int u = 0; u < kOrderBatch; ++u)
+            if (bk[u] >= 0) order[atomicAdd(&s_h[wv][bk[u]], 1)] = w0 + u * kOrderThreads;
+    }
+}
+
 // Row ids of the dense columns whose row bitmaps the symbolic phase kept,
 // one column per wave with no workgroup barrier: the wave streams the
 // column's bitmap 64 words at a time (a word per lane, kRowAhead rounds of
@@ -77,9 +163,9 @@ constexpr int kRowWaves = kRowThreads / kWave;
 constexpr int kRowAhead = 4;
 constexpr int kRowStage = 32 * 32;  // the set bits of 32 words
 __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
-    int count, const int32_t *__restrict__ list, const int32_t *__restrict__ num_bin, int nw,
-    const uint32_t *__restrict__ bits, const int64_t *__restrict__ Ccolptr,
-    int32_t *__restrict__ Crow) {
+    int count, const int32_t *__restrict__ list, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ num_bin, int nw, const uint32_t *__restrict__ bits,
+    const int64_t *__restrict__ Ccolptr, int32_t *__restrict__ Crow) {
     __shared__ int32_t stage[kRowWaves][kRowStage];
     const int wv = threadIdx.x / kWave, lane = lane_id();
     int32_t *my = stage[wv];
@@ -110,7 +196,8 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
         }
         wave_sync();
     };
-    for (int w = blockIdx.x * kRowWaves + wv; w < count; w += gridDim.x * kRowWaves) {
+    for (int i = blockIdx.x * kRowWaves + wv; i < count; i += gridDim.x * kRowWaves) {
+        const int w = order[i];
         const int32_t j = list[w];
         if (num_bin[j] < kBinDense) continue;  // the same for the whole wave
         long long base = Ccolptr[j];
@@ -253,8 +340,15 @@ static int numeric_bins_t(Plan &p, const V *Bvals, int32_t *Crow, V *Cval, const
                                                 p.device,
                                                 (p.sym_count[kBinDense] + kRowWaves - 1) /
                                                     kRowWaves);
-            hipLaunchKernelGGL(k_dense_rows, dim3(rg), dim3(kRowThreads), 0, p.stream,
+            // the order goes to the symbolic lists' dense-first slice, which
+            // the symbolic phase never fills
+            int32_t *order = p.sym_list + (int64_t)kBinDenseFirst * n;
+            hipLaunchKernelGGL(k_dense_order, dim3(1), dim3(kOrderThreads), 0, p.stream,
                                p.sym_count[kBinDense], p.sym_list + (int64_t)kBinDense * n,
+                               p.C_colptr, order);
+            SPG_LAUNCHED("k_dense_order");
+            hipLaunchKernelGGL(k_dense_rows, dim3(rg), dim3(kRowThreads), 0, p.stream,
+                               p.sym_count[kBinDense], p.sym_list + (int64_t)kBinDense * n, order,
                                p.num_bin, nw, p.dense_bits, p.C_colptr, Crow);
             SPG_LAUNCHED("k_dense_rows");
         }

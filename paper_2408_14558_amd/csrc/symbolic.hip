@@ -853,8 +853,13 @@ int launch_symbolic_reset(Plan &p) {
 template <int S, typename V>
 static int flop_bin_gather_launch(Plan &p) {
     constexpr int COLS = kFlopThreads / S;
-    // about kFlopTiles tiles at most: several rounds per tile beyond that
-    constexpr int64_t kFlopTiles = 512;
+    // about kFlopTiles tiles at most: several rounds per tile beyond that.
+    // Each tile takes its bins' list slots with one counter atomic per bin,
+    // and those atomics on a few addresses queue behind each other: R-MAT 18
+    // (262144 columns) plan + symbolic 3.50 ms at 512 tiles, 3.18 ms at 256,
+    // 3.75 ms at 2048 (1024-column tiles at most; 2048- and 4096-column
+    // tiles were slower again)
+    constexpr int64_t kFlopTiles = 256;
     const int64_t base = (p.n + COLS - 1) / COLS;
     const int64_t want = std::max<int64_t>(1, (base + kFlopTiles - 1) / kFlopTiles);
     const int rounds = (int)std::min<int64_t>(kFlopTileCols / COLS, want);
