@@ -10,8 +10,10 @@ namespace spg {
 
 // Entries of B(:,j) whose column of A~ holds more than kShortLen entries
 // are "long": a team of lanes walks them with consecutive (coalesced)
-// positions.  Shorter ones are walked by the thread that loaded the entry.
-constexpr int kShortLen = 32;
+// positions.  Shorter ones are walked by the thread that loaded the entry,
+// or (groups of more than one wave) as one flat list of terms over the
+// group.  Measured on the R-MAT scale-18 product: 64 beat 16, 32 and 128.
+constexpr int kShortLen = 64;
 
 // Row id above every real row (row ids are below 2^31 - 1).
 constexpr int kNoRow = 0x7fffffff;
@@ -100,10 +102,16 @@ __device__ __forceinline__ int short_slot(const TermStage<CH, V> *st, int ns, in
 template <int G>
 constexpr int short_unroll() { return G >= 512 ? 2 : 4; }
 
-// Scan value of one entry for the flat short list: (1 << 16) | its length
-// (a chunk holds at most 1024 entries of at most kShortLen terms, so the
-// length sum stays below 2^16 and the count below 2^11).
-__device__ __forceinline__ int short_code(int len) { return len > 0 ? ((1 << 16) | len) : 0; }
+// Scan value of one entry for the flat short list: (1 << kShortShift) | its
+// length (a chunk holds at most 1024 entries of at most kShortLen terms, so
+// the length sum stays at or below 2^16, below 2^kShortShift, and the count
+// below 2^11: the packed sum stays below 2^28).
+constexpr int kShortShift = 17;
+constexpr int kShortMask = (1 << kShortShift) - 1;
+static_assert(kMaxGroupWaves * kWave * kShortLen <= kShortMask, "flat short list length");
+__device__ __forceinline__ int short_code(int len) {
+    return len > 0 ? ((1 << kShortShift) | len) : 0;
+}
 
 // A term's row id and a_ik.
 template <typename V>
@@ -161,13 +169,13 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
                 int tot;
                 const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0),
                                                   st->tmp, &tot);
-                ns = tot >> 16;
-                nt = tot & 0xFFFF;
+                ns = tot >> kShortShift;
+                nt = tot & kShortMask;
                 if (len > 0 && len <= kShortLen) {
-                    const int slot = CH - ns + (sp >> 16);
+                    const int slot = CH - ns + (sp >> kShortShift);
                     st->lstart[slot] = start;
                     st->lbv[slot] = bv;
-                    st->lnext[slot] = sp & 0xFFFF;
+                    st->lnext[slot] = sp & kShortMask;
                 }
             } else if (len <= kShortLen) {
                 for (int e = 0; e < len; e += kUnroll) {
@@ -461,12 +469,12 @@ __device__ __forceinline__ void for_each_window_term(
         }
         int tot;
         const int sp = group_excl_scan<G>(short_code(len <= kShortLen ? len : 0), st->tmp, &tot);
-        const int ns = tot >> 16, nt = tot & 0xFFFF;
+        const int ns = tot >> kShortShift, nt = tot & kShortMask;
         if (len > 0 && len <= kShortLen) {
-            const int slot = CH - ns + (sp >> 16);
+            const int slot = CH - ns + (sp >> kShortShift);
             st->lstart[slot] = start;
             st->lbv[slot] = bv;
-            st->lnext[slot] = sp & 0xFFFF;
+            st->lnext[slot] = sp & kShortMask;
         }
         group_sync<G>();
         const int nl = st->nlong;

@@ -237,6 +237,24 @@ def test_dense_windows_on_big_columns():
     assert (nbin == 6).sum() > 0
 
 
+@pytest.mark.parametrize("dense", [False, True])
+def test_flat_short_list_at_its_length_limit(dense):
+    """Every column of A holds exactly 64 entries (the longest a flat short
+    list takes) and B_i columns hold 1024 and more entries: one staged chunk
+    of 1024 entries then lists 65536 terms, the most its packed scan holds.
+    m above 2^18 sends dense columns through the banded symbolic walk."""
+    rng = np.random.default_rng(77)
+    m, k = (1 << 18) + 1000, 3000
+    rows = np.concatenate([rng.choice(m, size=64, replace=False) for _ in range(k)])
+    cols = np.repeat(np.arange(k), 64)
+    A = synth.from_triplets(m, k, rows, cols, rng.uniform(-1.0, 1.0, rows.size))
+    Bi = _with_long_columns(rng, k, 5, 2, {0: 1024, 1: 2048, 3: 1500})
+    tun = spg.tuning(tiny_max_flop=0, hash_max_flop=0, hash_max_nnz=0) if dense else None
+    st, _, nbin = check_local(A, Bi, synth.partition_offsets(k, 1), 64, tun=tun)
+    if dense:
+        assert set(np.unique(nbin)) <= {0, 6, 7}
+
+
 @pytest.mark.parametrize("first", [1, 3000])
 def test_dense_first_bin_and_self_resetting_queues(first):
     """Dense columns with at least dense_first_flop products go to numeric
