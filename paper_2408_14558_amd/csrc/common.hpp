@@ -56,7 +56,9 @@ __device__ __forceinline__ int wave_incl_scan_dpp(int v) {
 // Inclusive scan over the lanes of a wave (width W, power of two <= 64).
 template <int W = kWave, typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-    if constexpr (W == kWave && std::is_same<T, int>::value) return wave_incl_scan_dpp(v);
+    // 32-bit integers take the DPP scan (HIP's __popc returns unsigned int)
+    if constexpr (W == kWave && (std::is_same<T, int>::value || std::is_same<T, unsigned>::value))
+        return (T)wave_incl_scan_dpp((int)v);
     const int l = lane_id() & (W - 1);
 #pragma unroll
     for (int d = 1; d < W; d <<= 1) {
@@ -65,6 +67,9 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     }
     return v;
 }
+
+// Lane 63's value, wave-uniform (a scalar register; no LDS round trip).
+__device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, kWave - 1); }
 
 template <int W = kWave, typename T>
 __device__ __forceinline__ T wave_sum(T v) {

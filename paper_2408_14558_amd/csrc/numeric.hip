@@ -219,18 +219,18 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
                 const int wi = s0 + d * kWave + lane;
                 const uint32_t word = wi < nw ? cur[d] : 0u;
                 const int incl = wave_incl_scan(__popc(word));
-                const int total = __shfl(incl, kWave - 1);
+                const int total = wave_last(incl);
                 if (total <= kRowStage) {
                     place(word, wi, base, incl, total);
                     base += total;
                 } else {  // each half's 32 words hold at most kRowStage bits
                     const uint32_t lo = lane < 32 ? word : 0u, hi = lane < 32 ? 0u : word;
                     const int il = wave_incl_scan(__popc(lo));
-                    const int nl = __shfl(il, kWave - 1);
+                    const int nl = wave_last(il);
                     place(lo, wi, base, il, nl);
                     base += nl;
                     const int ih = wave_incl_scan(__popc(hi));
-                    const int nh = __shfl(ih, kWave - 1);
+                    const int nh = wave_last(ih);
                     place(hi, wi, base, ih, nh);
                     base += nh;
                 }

@@ -150,7 +150,7 @@ __device__ __forceinline__ void num_wave_column(const NumArgs<V> &a, int64_t q0,
         nh += hd[r];
     }
     const int incl = wave_incl_scan(nh);
-    const int total = __shfl(incl, kWave - 1);
+    const int total = wave_last(incl);
     for (int e = lane; e < total; e += kWave) s_vals[e] = Acc(0);
     wave_sync();
     int run = incl - nh - 1;
@@ -332,7 +332,7 @@ __device__ __forceinline__ int bitmap_ranks(const uint32_t *bits, uint16_t *wpre
                 b &= b - 1;
             }
         }
-        run += __shfl(incl, kWave - 1);
+        run += wave_last(incl);
     }
     __syncthreads();
     return total;
@@ -383,7 +383,7 @@ __device__ __forceinline__ int load_bitmap_ranks(const uint32_t *__restrict__ sr
         const int c = __popc(wr[i]);
         const int incl = wave_incl_scan(c);
         if (w < we) wpre[w] = (uint16_t)(run + incl - c - sb);
-        run += __shfl(incl, kWave - 1);
+        run += wave_last(incl);
     }
     __syncthreads();
     return total;

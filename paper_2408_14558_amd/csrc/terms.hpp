@@ -299,7 +299,7 @@ __device__ __forceinline__ void wave_terms(int64_t q0, int64_t q1, TermRange tr,
             if (Bvals) b = Bvals[q];
         }
         const int incl = wave_incl_scan(len);
-        const int S = __shfl(incl, kWave - 1);
+        const int S = wave_last(incl);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int s = r * kWave + lane - base;
