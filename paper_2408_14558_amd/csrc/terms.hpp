@@ -47,12 +47,14 @@ constexpr int next_pow2_const(int x) {
 // have unclaimed pieces, so hub columns of A~ (power-law inputs) are spread
 // over the group instead of holding one wave while the others wait.
 
-// The next long entry to start for the calling wave (wave-uniform).
+// The next long entry to start for the calling wave (wave-uniform; the
+// whole wave calls, so lane 0 is its first active lane and readfirstlane
+// broadcasts the claim without an LDS round trip).
 template <int CH, typename V>
 __device__ __forceinline__ int claim_entry(TermStage<CH, V> *st) {
     int e = 0;
     if (lane_id() == 0) e = atomicAdd(&st->qnext, 1);
-    return __shfl(e, 0);
+    return __builtin_amdgcn_readfirstlane(e);
 }
 
 // The offset (from lstart) of the next unclaimed piece of entry e.
@@ -60,7 +62,7 @@ template <int CH, typename V>
 __device__ __forceinline__ int claim_piece(TermStage<CH, V> *st, int e, int piece) {
     int off = 0;
     if (lane_id() == 0) off = atomicAdd(&st->lnext[e], piece);
-    return __shfl(off, 0);
+    return __builtin_amdgcn_readfirstlane(off);
 }
 
 // A long entry with unclaimed pieces before lim(e), or -1 (one LDS read per
@@ -74,7 +76,9 @@ __device__ __forceinline__ int entry_with_work(const int *lnext, int nl, int fro
         if (e >= nl) e -= nl;  // b + lane < nl and first < nl, so e < 2 nl
         const bool left = b + lane_id() < nl && lnext[e] < lim(e);
         const uint64_t m = __ballot(left);
-        if (m) return __shfl(e, __ffsll((unsigned long long)m) - 1);
+        if (m)
+            return __builtin_amdgcn_readlane(
+                e, __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1));
     }
     return -1;
 }
