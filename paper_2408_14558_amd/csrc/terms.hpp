@@ -506,11 +506,20 @@ __device__ __forceinline__ void for_each_window_term(
         // a piece's row ids and values, loaded without branches (lanes past
         // the entry's end load its last term again and do not apply it)
         auto load = [&](long long s0, int elen, int off, int32_t (&r)[U], V (&av)[U]) {
+            // the entry's first term as a scalar base and 32-bit offsets per
+            // lane: one address operation per load (the walk is bound by
+            // vector instruction issue)
+            const long long sb =
+                (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(s0 >> 32))
+                             << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)s0));
+            const int32_t *rb = At_rowidx + sb;
+            const V *vb = kVals ? At_vals + sb : nullptr;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long long at = s0 + min(off + u * kWave + tl, elen - 1);
-                r[u] = At_rowidx[at];
-                av[u] = kVals ? At_vals[at] : V(0);
+                const uint32_t at = (uint32_t)min(off + u * kWave + tl, elen - 1);
+                r[u] = rb[at];
+                av[u] = kVals ? vb[at] : V(0);
             }
         };
         // the next piece is claimed and its loads are in flight while the
