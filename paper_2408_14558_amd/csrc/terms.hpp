@@ -216,9 +216,14 @@ __device__ __forceinline__ void for_each_term(int64_t q0, int64_t q1, TermRange 
             // last term again and do not apply it), and the next piece's
             // loads in flight while the current piece is applied
             auto load = [&](long long s0, int len, int off, Item (&it)[U]) {
+                // the entry's first position as a scalar and 32-bit lane
+                // offsets: less address arithmetic per load
+                const long long sb = (long long)(
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(s0 >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)s0));
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    it[u] = ld((int64_t)(s0 + min(off + u * kWave + tl, len - 1)));
+                    it[u] = ld((int64_t)(sb + (uint32_t)min(off + u * kWave + tl, len - 1)));
             };
             auto walk = [&](int e) {
                 const long long s0 = st->lstart[e];
