@@ -229,18 +229,23 @@ class Plan:
                 out: Optional[tuple] = None):
         if self.nnzC is None:
             raise RuntimeError("numeric() needs symbolic() first")
+        checks = []
+        if A_vals is not None:
+            checks.append((A_vals, "A_vals", self.torch_dtype, self.A.nnz))
+        if B_vals is not None:
+            checks.append((B_vals, "B_vals", self.torch_dtype, self.Bi.nnz))
         if out is None:
+            # allocated here with the right device, dtype and length: nothing
+            # to check (this runs between nnz(C_i) and the numeric launch, so
+            # its host time is device idle time)
             rows = torch.empty(self.nnzC, dtype=torch.int32, device=self.device)
             vals = torch.empty(self.nnzC, dtype=self.torch_dtype, device=self.device)
         else:
             rows, vals = out
+            checks.append((rows, "C_rowidx", torch.int32, self.nnzC))
+            checks.append((vals, "C_vals", self.torch_dtype, self.nnzC))
         # the library reads and writes these through raw device pointers
-        for t, what, dt, n in ((A_vals, "A_vals", self.torch_dtype, self.A.nnz),
-                               (B_vals, "B_vals", self.torch_dtype, self.Bi.nnz),
-                               (rows, "C_rowidx", torch.int32, self.nnzC),
-                               (vals, "C_vals", self.torch_dtype, self.nnzC)):
-            if t is None:
-                continue
+        for t, what, dt, n in checks:
             if t.device != self.device or t.dtype != dt or not t.is_contiguous():
                 raise ValueError(f"{what} must be a contiguous {dt} tensor on {self.device}")
             if t.numel() < n:
