@@ -68,11 +68,44 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// The value of lane (lane ^ d).  For d = 1 and 2 (quad permutes), d = 4
+// (shifts by 4 inside each row of 16 lanes, one per direction) and d = 8 (a
+// rotation by 8 inside each row) DPP moves, with no LDS round trip; d = 16
+// and 32 take a shuffle.  d must be a constant after unrolling (the DPP
+// control is an immediate); every lane must be active.
+__device__ __forceinline__ int lane_xor_i32(int v, int d) {
+    if (d == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    if (d == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    if (d == 4) {
+        const int up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xf, 0xf, false);  // row_shl:4
+        const int dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+        return (lane_id() & 4) ? dn : up;
+    }
+    if (d == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    return __shfl_xor(v, d);
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_xor(T x, int d) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_xor_i32(__builtin_bit_cast(int, x), d));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = (uint32_t)lane_xor_i32((int)(uint32_t)u, d);
+        const uint32_t hi = (uint32_t)lane_xor_i32((int)(uint32_t)(u >> 32), d);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
 // Lane 63's value, wave-uniform (a scalar register; no LDS round trip).
 __device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, kWave - 1); }
 
 template <int W = kWave, typename T>
 __device__ __forceinline__ T wave_sum(T v) {
+    // 32-bit integers over a whole wave: the DPP scan and lane 63's total
+    if constexpr (W == kWave && (std::is_same<T, int>::value || std::is_same<T, unsigned>::value))
+        return (T)wave_last(wave_incl_scan_dpp((int)v));
 #pragma unroll
     for (int d = W >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, W);
     return v;

@@ -369,9 +369,9 @@ __device__ __forceinline__ void wave_sort(int (&key)[E], V (&val)[E]) {
                 const bool keep_min = lower == up;
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
-                    const int ok = __shfl_xor(key[r], ld);
+                    const int ok = lane_xor(key[r], ld);
                     if constexpr (kVals) {
-                        const V ov = __shfl_xor(val[r], ld);
+                        const V ov = lane_xor(val[r], ld);
                         const bool take = keep_min ? (ok < key[r]) : (ok > key[r]);
                         val[r] = take ? ov : val[r];
                     }
