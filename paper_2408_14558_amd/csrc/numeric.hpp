@@ -480,9 +480,13 @@ __device__ __forceinline__ void num_bitmap_column(const NumArgs<V> &a, int32_t j
 }
 
 // --- dense: bitmap of all m rows + rank windows -----------------------------
-// Loads in flight per lane on the long A~ columns of dense output columns.
+// Loads in flight per lane on the long A~ columns of dense output columns:
+// a wave walks pieces of this many rows of 64 terms.  Measured on the R-MAT
+// scale-18 product: 3 beat 2 and 4 (numeric 13.42 against 13.64 and 13.55
+// ms; window segments of a few hundred terms leave lanes of larger pieces
+// idle, and the walk is bound by vector instruction issue).
 #ifndef SPG_DENSE_UNROLL
-#define SPG_DENSE_UNROLL 4
+#define SPG_DENSE_UNROLL 3
 #endif
 constexpr int kDenseUnroll = SPG_DENSE_UNROLL;
 // Entries of B(:,j) staged at once by the dense kernel (its 1024 threads all
